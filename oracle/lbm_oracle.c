@@ -1,0 +1,480 @@
+/*
+ * Oracle of the non-ideal compressible double-distribution lattice Boltzmann
+ * step (arXiv 2510.14712, Section 3.2 "Lattice Boltzmann realization" and the
+ * flowchart figure at its end).
+ *
+ * TEST INFRASTRUCTURE ONLY: plain scalar FP64, no blocking or fusion beyond
+ * what the paper's equations state.  Only the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library; it shares nothing
+ * with the GPU path.
+ *
+ * Each pass below names the equation it evaluates.  Where the paper is
+ * ambiguous the reading taken is stated next to the code (the list of
+ * readings is kept with the design notes of the repository).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
+ */
+#include "lbm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define LATTICE_SOUND_SPEED_SQ (1.0 / 3.0) /* varsigma^2, eq. (cs) */
+
+/* ---------------------------------------------------------------------- */
+/* Velocity set: c_{i a} in {-1,0,1}, i = (c_x+1) + 3(c_y+1) [+ 9(c_z+1)]  */
+/* (eq. D3Q27c; D2Q9 is the same product restricted to two axes).          */
+/* ---------------------------------------------------------------------- */
+static int num_vel(int D) { return D == 2 ? 9 : 27; }
+
+static void vel(int D, int i, int c[3]) {
+    c[0] = i % 3 - 1;
+    c[1] = (i / 3) % 3 - 1;
+    c[2] = D == 3 ? (i / 9) - 1 : 0;
+}
+
+/* Psi_{i a}(xi, zeta) = 1 - c^2 + [(3c^2 - 2) zeta + c xi] / 2   (eq. phi) */
+static double Psi(int c, double xi, double zeta) {
+    double c2 = (double)(c * c);
+    return 1.0 - c2 + 0.5 * ((3.0 * c2 - 2.0) * zeta + (double)c * xi);
+}
+
+/* ---------------------------------------------------------------------- */
+/* f^eq (eq. LBMeq): rho * prod_a Psi(c_ia; u_a, theta + u_a^2)            */
+/* ---------------------------------------------------------------------- */
+void oracle_feq(int D, double rho, const double *u, double theta, double *feq) {
+    int Q = num_vel(D);
+    for (int i = 0; i < Q; i++) {
+        int c[3];
+        vel(D, i, c);
+        double prod = 1.0;
+        for (int a = 0; a < D; a++) prod *= Psi(c[a], u[a], theta + u[a] * u[a]);
+        feq[i] = rho * prod;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* g^eq (eqs. Egen, Oa, LBMeqG): the product of Psi with xi -> O_a and     */
+/* zeta -> O_a^2 acting on the generating function E = e + |u|^2/2.        */
+/* The operators are applied literally to E held as a polynomial in the    */
+/* velocity components; the result is evaluated at the given velocity.     */
+/* ---------------------------------------------------------------------- */
+#define PD 5 /* per-variable degree bound: E has degree 2, O_a^2 adds 2 */
+typedef struct { double c[PD][PD][PD]; } poly3;
+
+/* out = O_a in = theta * d(in)/du_a + u_a * in */
+static void poly_apply_O(const poly3 *in, poly3 *out, int a, double theta) {
+    memset(out, 0, sizeof(*out));
+    for (int i = 0; i < PD; i++)
+        for (int j = 0; j < PD; j++)
+            for (int k = 0; k < PD; k++) {
+                double v = in->c[i][j][k];
+                if (v == 0.0) continue;
+                int e[3] = {i, j, k};
+                int n = e[a];
+                if (n > 0) { /* derivative term */
+                    int d[3] = {i, j, k};
+                    d[a] = n - 1;
+                    out->c[d[0]][d[1]][d[2]] += theta * (double)n * v;
+                }
+                /* multiplication by u_a; the degree bound is never exceeded
+                 * for at most two applications per axis on E */
+                int m[3] = {i, j, k};
+                m[a] = n + 1;
+                if (m[a] < PD) out->c[m[0]][m[1]][m[2]] += v;
+                else abort();
+            }
+}
+
+static double poly_eval(const poly3 *p, const double *u) {
+    double pw[3][PD];
+    for (int a = 0; a < 3; a++) {
+        pw[a][0] = 1.0;
+        for (int n = 1; n < PD; n++) pw[a][n] = pw[a][n - 1] * u[a];
+    }
+    double s = 0.0;
+    for (int i = 0; i < PD; i++)
+        for (int j = 0; j < PD; j++)
+            for (int k = 0; k < PD; k++)
+                if (p->c[i][j][k] != 0.0) s += p->c[i][j][k] * pw[0][i] * pw[1][j] * pw[2][k];
+    return s;
+}
+
+void oracle_operator_moments(int D, const double *u, double e, double theta, double *M) {
+    double uu[3] = {u[0], u[1], D == 3 ? u[2] : 0.0};
+    poly3 E;
+    memset(&E, 0, sizeof(E));
+    E.c[0][0][0] = e;         /* e(rho, T) */
+    E.c[2][0][0] += 0.5;      /* u_x^2 / 2 */
+    E.c[0][2][0] += 0.5;      /* u_y^2 / 2 */
+    if (D == 3) E.c[0][0][2] += 0.5;
+    int nz = D == 3 ? 3 : 1;
+    poly3 Pz[3], Pyz[3][3], t;
+    Pz[0] = E;
+    if (D == 3) {
+        poly_apply_O(&Pz[0], &Pz[1], 2, theta);
+        poly_apply_O(&Pz[1], &Pz[2], 2, theta);
+    }
+    for (int kz = 0; kz < nz; kz++) {
+        Pyz[0][kz] = Pz[kz];
+        poly_apply_O(&Pyz[0][kz], &Pyz[1][kz], 1, theta);
+        poly_apply_O(&Pyz[1][kz], &Pyz[2][kz], 1, theta);
+        for (int ky = 0; ky < 3; ky++) {
+            poly3 cur = Pyz[ky][kz];
+            for (int kx = 0; kx < 3; kx++) {
+                if (kx > 0) {
+                    poly_apply_O(&cur, &t, 0, theta);
+                    cur = t;
+                }
+                M[kx + 3 * ky + 9 * kz] = poly_eval(&cur, uu);
+            }
+        }
+    }
+}
+
+/* Weight of O^k inside Psi(c; O, O^2): constant term (1 - c^2) for k = 0,
+ * c/2 for k = 1 and (3c^2 - 2)/2 for k = 2 (eq. phi). */
+static double psi_weight(int c, int k) {
+    double c2 = (double)(c * c);
+    if (k == 0) return 1.0 - c2;
+    if (k == 1) return 0.5 * (double)c;
+    return 0.5 * (3.0 * c2 - 2.0);
+}
+
+void oracle_geq(int D, double rho, const double *u, double e, double theta, double *geq) {
+    int Q = num_vel(D);
+    double M[27];
+    oracle_operator_moments(D, u, e, theta, M);
+    int nk = D == 3 ? 27 : 9;
+    for (int i = 0; i < Q; i++) {
+        int c[3];
+        vel(D, i, c);
+        double s = 0.0;
+        for (int kk = 0; kk < nk; kk++) {
+            int k[3] = {kk % 3, (kk / 3) % 3, kk / 9};
+            double w = 1.0;
+            for (int a = 0; a < D; a++) w *= psi_weight(c[a], k[a]);
+            s += w * M[kk];
+        }
+        geq[i] = rho * s;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Grid helpers                                                            */
+/* ---------------------------------------------------------------------- */
+static int check_params(const oracle_params *p) {
+    if (!p) return -1;
+    if (p->D != 2 && p->D != 3) return -1;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return -1;
+    if (p->D == 2 && p->nz != 1) return -1;
+    for (int a = 0; a < 3; a++)
+        if (p->bc[a] != 0 && p->bc[a] != 1) return -1;
+    return 0;
+}
+
+static int coord(int x, int n, int bc) {
+    if (x >= 0 && x < n) return x;
+    if (bc == 0) return ((x % n) + n) % n; /* periodic */
+    return x < 0 ? 0 : n - 1;               /* zero-gradient: clamp */
+}
+
+/* index of the cell at (x, y, z) + (dx, dy, dz) under the boundary rules */
+static long nbr(const oracle_params *p, long idx, int dx, int dy, int dz) {
+    int x = (int)(idx % p->nx);
+    int y = (int)((idx / p->nx) % p->ny);
+    int z = (int)(idx / ((long)p->nx * p->ny));
+    int X = coord(x + dx, p->nx, p->bc[0]);
+    int Y = coord(y + dy, p->ny, p->bc[1]);
+    int Z = coord(z + dz, p->nz, p->bc[2]);
+    return X + (long)p->nx * (Y + (long)p->ny * Z);
+}
+
+static long nbr_axis(const oracle_params *p, long idx, int a, int s) {
+    int d[3] = {0, 0, 0};
+    d[a] = s;
+    return nbr(p, idx, d[0], d[1], d[2]);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Macroscopic fields of a state: flowchart boxes "compute rho and F" and  */
+/* "compute u, E, T, P" (eqs. def_h, FK, def_u, def_E, lbm_temp, Pvdw).    */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    double *rho, *J, *G, *lap, *F, *u, *E, *T, *P, *theta, *e, *h, *cs2, *Lam;
+} work_fields;
+
+static void work_alloc(work_fields *w, long N, int D) {
+    w->rho = calloc(N, sizeof(double));
+    w->J = calloc((size_t)D * N, sizeof(double));
+    w->G = calloc(N, sizeof(double));
+    w->lap = calloc(N, sizeof(double));
+    w->F = calloc((size_t)D * N, sizeof(double));
+    w->u = calloc((size_t)D * N, sizeof(double));
+    w->E = calloc(N, sizeof(double));
+    w->T = calloc(N, sizeof(double));
+    w->P = calloc(N, sizeof(double));
+    w->theta = calloc(N, sizeof(double));
+    w->e = calloc(N, sizeof(double));
+    w->h = calloc(N, sizeof(double));
+    w->cs2 = calloc(N, sizeof(double));
+    w->Lam = calloc((size_t)D * N, sizeof(double));
+}
+
+static void work_free(work_fields *w) {
+    free(w->rho); free(w->J); free(w->G); free(w->lap); free(w->F); free(w->u);
+    free(w->E); free(w->T); free(w->P); free(w->theta); free(w->e); free(w->h);
+    free(w->cs2); free(w->Lam);
+}
+
+static void compute_fields(const oracle_params *p, const double *f, const double *g,
+                           work_fields *w) {
+    const int D = p->D, Q = num_vel(D);
+    const long N = (long)p->nx * p->ny * p->nz;
+
+    /* rho = sum f_i (eq. def_h); sum c_i f_i and sum g_i enter eqs. def_u, def_E */
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < N; x++) {
+        double rho = 0.0, J[3] = {0.0, 0.0, 0.0}, G = 0.0;
+        for (int i = 0; i < Q; i++) {
+            int c[3];
+            vel(D, i, c);
+            rho += f[i * N + x];
+            for (int a = 0; a < D; a++) J[a] += (double)c[a] * f[i * N + x];
+            G += g[i * N + x];
+        }
+        w->rho[x] = rho;
+        for (int a = 0; a < D; a++) w->J[a * N + x] = J[a];
+        w->G[x] = G;
+    }
+
+    /* Laplacian of rho by the central second-order difference per axis */
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < N; x++) {
+        double s = 0.0;
+        for (int a = 0; a < D; a++)
+            s += w->rho[nbr_axis(p, x, a, +1)] + w->rho[nbr_axis(p, x, a, -1)] - 2.0 * w->rho[x];
+        w->lap[x] = s;
+    }
+
+    /* Korteweg force F = kappa rho grad(lap rho)  (eq. FK), central gradient */
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < N; x++) {
+        for (int a = 0; a < D; a++) {
+            double d = 0.5 * (w->lap[nbr_axis(p, x, a, +1)] - w->lap[nbr_axis(p, x, a, -1)]);
+            w->F[a * N + x] = p->kappa * w->rho[x] * d;
+        }
+    }
+
+    /* u, E, T, P and the derived per-cell quantities */
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < N; x++) {
+        double rho = w->rho[x];
+        double u[3] = {0.0, 0.0, 0.0}, uF = 0.0, u2 = 0.0;
+        for (int a = 0; a < D; a++) {
+            u[a] = (w->J[a * N + x] + 0.5 * w->F[a * N + x]) / rho; /* eq. def_u */
+            uF += u[a] * w->F[a * N + x];
+            u2 += u[a] * u[a];
+        }
+        double E = (w->G[x] + 0.5 * uF) / rho;                  /* eq. def_E */
+        double T = (E - 0.5 * u2 + p->a * rho) / p->cv;         /* eq. lbm_temp */
+        double P = rho * p->R * T / (1.0 - p->b * rho) - p->a * rho * rho; /* eq. Pvdw */
+        double theta = P / rho;                                 /* eq. theta */
+        double e = E - 0.5 * u2;                                /* eq. rhoE */
+        double h = e + P / rho;                                 /* eq. enthalpy */
+        double omb = 1.0 - p->b * rho;
+        double cs2 = p->R * T * (1.0 + p->R / p->cv) / (omb * omb) - 2.0 * p->a * rho; /* eq. vdW_speed_of_sound */
+        for (int a = 0; a < D; a++) {
+            w->u[a * N + x] = u[a];
+            /* Lambda_a = rho u_a^3 + 3 rho u_a (theta - varsigma^2) */
+            w->Lam[a * N + x] = rho * u[a] * u[a] * u[a] + 3.0 * rho * u[a] * (theta - LATTICE_SOUND_SPEED_SQ);
+        }
+        w->E[x] = E; w->T[x] = T; w->P[x] = P; w->theta[x] = theta;
+        w->e[x] = e; w->h[x] = h; w->cs2[x] = cs2;
+    }
+}
+
+static void export_fields(const oracle_params *p, const work_fields *w, oracle_fields *out) {
+    if (!out) return;
+    const long N = (long)p->nx * p->ny * p->nz;
+    const int D = p->D;
+#define CP(dst, src, n) if (out->dst) memcpy(out->dst, w->src, (size_t)(n) * sizeof(double))
+    CP(rho, rho, N); CP(u, u, D * N); CP(E, E, N); CP(T, T, N); CP(P, P, N);
+    CP(theta, theta, N); CP(h, h, N); CP(cs2, cs2, N); CP(F, F, D * N);
+    CP(Lambda, Lam, D * N); CP(lap, lap, N);
+#undef CP
+}
+
+/* sgn with sgn(0) = 0 (reading: a zero velocity takes the central average) */
+static double sgn(double v) { return v > 0.0 ? 1.0 : (v < 0.0 ? -1.0 : 0.0); }
+
+/* ---------------------------------------------------------------------- */
+/* Collision (eqs. fLBGK, gLBGK with LBMeq, LBMstar, LBMeqG, LBMgstar)     */
+/* ---------------------------------------------------------------------- */
+static void collide_all(const oracle_params *p, const double *f, const double *g,
+                        const work_fields *w, double *fpost, double *gpost) {
+    const int D = p->D, Q = num_vel(D);
+    const long N = (long)p->nx * p->ny * p->nz;
+
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < N; x++) {
+        double rho = w->rho[x], P = w->P[x], theta = w->theta[x], T = w->T[x];
+        double u[3] = {0, 0, 0}, F[3] = {0, 0, 0};
+        for (int a = 0; a < D; a++) { u[a] = w->u[a * N + x]; F[a] = w->F[a * N + x]; }
+
+        /* central differences: div u, grad h, grad T */
+        double divu = 0.0, gh[3] = {0, 0, 0}, gT[3] = {0, 0, 0}, Phi[3] = {0, 0, 0};
+        for (int a = 0; a < D; a++) {
+            long xp = nbr_axis(p, x, a, +1), xm = nbr_axis(p, x, a, -1);
+            divu += 0.5 * (w->u[a * N + xp] - w->u[a * N + xm]);
+            gh[a] = 0.5 * (w->h[xp] - w->h[xm]);
+            gT[a] = 0.5 * (w->T[xp] - w->T[xm]);
+            /* upwind-biased derivative of Lambda_a by the sign of u_a at x,
+             * then Phi_aa = -(1/rho) d_a Lambda_a (eq. correction) */
+            double s = sgn(u[a]);
+            double dL = 0.5 * (1.0 + s) * (w->Lam[a * N + x] - w->Lam[a * N + xm])
+                      + 0.5 * (1.0 - s) * (w->Lam[a * N + xp] - w->Lam[a * N + x]);
+            Phi[a] = -dL / rho;
+        }
+
+        double tau = p->mu / P;                                         /* tau = mu / P */
+        double beta = 1.0 / (2.0 * tau + 1.0);                         /* eq. beta_main, dt = 1 */
+        double alpha = (double)(D + 2) / (double)D - rho * w->cs2[x] / P - p->eta / p->mu; /* eq. corr_bulk */
+
+        double us[3] = {0, 0, 0}, FF = 0.0;
+        for (int a = 0; a < D; a++) { us[a] = u[a] + F[a] / rho; FF += F[a] * F[a]; } /* eq. sh_vel_1 */
+        double thetas = theta + alpha * theta * divu;                  /* eq. sh_temp_1 */
+        double Ts = T - FF / (2.0 * rho * rho * p->cv);                /* eq. sh_T_1 */
+        double qc[3] = {0, 0, 0};
+        for (int a = 0; a < D; a++) qc[a] = P * (gh[a] - (p->k / p->mu) * gT[a]); /* eq. qc_1 */
+
+        double e_eq = p->cv * T - p->a * rho;   /* caloric vdW EOS e(rho, T) (eq. de_vdW) */
+        double e_st = p->cv * Ts - p->a * rho;  /* e(rho, T*) */
+
+        double feq[27], fst[27], geq[27], gst[27];
+        oracle_feq(D, rho, u, theta, feq);
+        for (int i = 0; i < Q; i++) {           /* eq. LBMstar */
+            int c[3];
+            vel(D, i, c);
+            double prod = 1.0;
+            for (int a = 0; a < D; a++) prod *= Psi(c[a], us[a], thetas + us[a] * us[a] + Phi[a]);
+            fst[i] = rho * prod;
+        }
+        oracle_geq(D, rho, u, e_eq, theta, geq);
+        oracle_geq(D, rho, us, e_st, thetas, gst);
+        for (int i = 0; i < Q; i++) {           /* eq. LBMgstar: + c_i.q^c / 2 on |c_i|^2 = 1 */
+            int c[3];
+            vel(D, i, c);
+            int c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+            if (c2 == 1) {
+                double cq = 0.0;
+                for (int a = 0; a < D; a++) cq += (double)c[a] * qc[a];
+                gst[i] += 0.5 * cq;
+            }
+        }
+        for (int i = 0; i < Q; i++) {
+            double fi = f[i * N + x], gi = g[i * N + x];
+            fpost[i * N + x] = fi + 2.0 * beta * (feq[i] - fi) + (1.0 - beta) * (fst[i] - feq[i]);
+            gpost[i * N + x] = gi + 2.0 * beta * (geq[i] - gi) + (1.0 - beta) * (gst[i] - geq[i]);
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Public entry points                                                     */
+/* ---------------------------------------------------------------------- */
+int oracle_init(const oracle_params *p, const double *rho, const double *u,
+                const double *T, double *f, double *g) {
+    if (check_params(p)) return -1;
+    const int D = p->D, Q = num_vel(D);
+    const long N = (long)p->nx * p->ny * p->nz;
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < N; x++) {
+        double r = rho[x], t = T[x], uu[3] = {0, 0, 0};
+        for (int a = 0; a < D; a++) uu[a] = u[a * N + x];
+        double P = r * p->R * t / (1.0 - p->b * r) - p->a * r * r;
+        double theta = P / r;
+        double e = p->cv * t - p->a * r;
+        double feq[27], geq[27];
+        oracle_feq(D, r, uu, theta, feq);
+        oracle_geq(D, r, uu, e, theta, geq);
+        for (int i = 0; i < Q; i++) { f[i * N + x] = feq[i]; g[i * N + x] = geq[i]; }
+    }
+    return 0;
+}
+
+int oracle_fields_eval(const oracle_params *p, const double *f, const double *g,
+                       oracle_fields *out) {
+    if (check_params(p)) return -1;
+    const long N = (long)p->nx * p->ny * p->nz;
+    work_fields w;
+    work_alloc(&w, N, p->D);
+    compute_fields(p, f, g, &w);
+    export_fields(p, &w, out);
+    work_free(&w);
+    return 0;
+}
+
+int oracle_collide(const oracle_params *p, const double *f, const double *g,
+                   double *fpost, double *gpost, oracle_fields *out) {
+    if (check_params(p)) return -1;
+    const long N = (long)p->nx * p->ny * p->nz;
+    work_fields w;
+    work_alloc(&w, N, p->D);
+    compute_fields(p, f, g, &w);
+    collide_all(p, f, g, &w, fpost, gpost);
+    export_fields(p, &w, out);
+    work_free(&w);
+    return 0;
+}
+
+int oracle_stream(const oracle_params *p, const double *fpost, const double *gpost,
+                  double *f, double *g) {
+    if (check_params(p)) return -1;
+    const int D = p->D, Q = num_vel(D);
+    const long N = (long)p->nx * p->ny * p->nz;
+    /* f_i(x + c_i, t + 1) = f'_i(x, t), written as a pull from x - c_i */
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < N; x++) {
+        for (int i = 0; i < Q; i++) {
+            int c[3];
+            vel(D, i, c);
+            long src = nbr(p, x, -c[0], -c[1], -c[2]);
+            f[i * N + x] = fpost[i * N + src];
+            g[i * N + x] = gpost[i * N + src];
+        }
+    }
+    return 0;
+}
+
+int oracle_run(const oracle_params *p, double *f, double *g, int nsteps) {
+    if (check_params(p) || nsteps < 0) return -1;
+    const int Q = num_vel(p->D);
+    const long N = (long)p->nx * p->ny * p->nz;
+    double *fp = malloc((size_t)Q * N * sizeof(double));
+    double *gp = malloc((size_t)Q * N * sizeof(double));
+    if (!fp || !gp) { free(fp); free(gp); return -2; }
+    work_fields w;
+    work_alloc(&w, N, p->D);
+    for (int s = 0; s < nsteps; s++) {
+        compute_fields(p, f, g, &w);
+        collide_all(p, f, g, &w, fp, gp);
+        oracle_stream(p, fp, gp, f, g);
+    }
+    work_free(&w);
+    free(fp);
+    free(gp);
+    return 0;
+}
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
