@@ -1,0 +1,189 @@
+"""Throughput of the fused stream-collide step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tgv512]
+
+Workload (default): the D3Q27 near-critical Taylor-Green vortex on a 512^3
+periodic lattice (rho_c, 1.1 T_c, Mach 0.5, 1 % seeded density noise), run in
+the two forms the metric compares on the same steps:
+  * plain: FP32 populations, FP32 arithmetic, explicit van der Waals EOS;
+  * surrogate: BF16 deviation storage, FP32 arithmetic, MLP EOS (BF16 MFMA)
+    with residual check and FP64 Newton fallback, FP64 conservation sums.
+`value` is the surrogate form's MLUPS (the full hot path); the plain form's
+figures are reported beside it.  Inputs are synthetic and resident in HBM
+before the timed region; the timed region is K steps bracketed by device
+synchronisation.  One JSON line is printed.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def _p(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload(name, st):
+    from paper_2510_14712_amd import inputs
+    if name in ("tgv512", "tgv256"):
+        c = st["tgv_3d_512" if name == "tgv512" else "tgv_3d_256"]
+        shape = tuple(c["shape"])
+        rho, u, T = inputs.taylor_green(shape, c["seed"], c["rho0"], c["T0"], c["U0"], c["noise"])
+        desc = (f"D3Q27 near-critical Taylor-Green vortex {shape[0]}x{shape[1]}x{shape[2]} periodic, "
+                f"rho_c, 1.1 T_c, Mach 0.5, 1% noise (seed {c['seed']})")
+        return shape, (0, 0, 0), (rho, u, T), (c["rho0"], c["T0"]), desc
+    if name == "drop3d":
+        c = st["shock_drop_3d"]
+        shape = tuple(c["shape"])
+        rho, u, T = inputs.shock_drop(shape, c["centre"], c["radius"], c["width"], c["rho_liquid"],
+                                      c["rho_vapour"], c["T1"], c["x_shock"], c["rho2"], c["T2"], c["u2"])
+        desc = (f"D3Q27 shock-drop {shape[0]}x{shape[1]}x{shape[2]}, sphere R {c['radius']}, Ma 1.47, "
+                f"T = 0.85 T_c")
+        return shape, tuple(c["bc"]), (rho, u, T), (c["rho_vapour"], c["T1"]), desc
+    raise SystemExit(f"unknown workload {name}")
+
+
+def train_surrogate(st, lbm):
+    c = st["shock_drop_3d"]
+    box = [c["mlp_box"]["rho"][0], c["mlp_box"]["rho"][1], c["mlp_box"]["T"][0], c["mlp_box"]["T"][1]]
+    from paper_2510_14712_amd import inputs
+    k = st["constants"]
+    p0 = inputs.mlp_params(c["mlp_seed"]).astype(np.float32)
+    t0 = time.perf_counter()
+    params, norm, loss = lbm.mlp_train(box, c["mlp_samples"], c["mlp_seed"], 40, 8192, 3e-3, p0,
+                                       a=k["a"], b=k["b"], R=k["R"], cv=k["cv"])
+    return params, norm, loss, time.perf_counter() - t0
+
+
+def time_form(lbm, torch, shape, bc, fields, ref, kw, storage, eos, steps, warmup, mlp=None):
+    rho, u, T = fields
+    N = int(np.prod(shape))
+    lat = lbm.Lattice(3, shape, bc=bc, storage=storage, eos=eos, mlp_tol=1e-6, ref_rho=ref[0], ref_T=ref[1], **kw)
+    try:
+        if mlp is not None:
+            lat.mlp_set(mlp[0], mlp[1])
+        lat.init(rho, u, T)
+        lat.step(warmup)
+        lat.synchronize()
+        if eos == "mlp":
+            lat.mlp_stats()  # reset the fallback counters
+        t0 = time.perf_counter()
+        lat.step(steps)
+        lat.synchronize()
+        dt = time.perf_counter() - t0
+        sums = lat.conservation(raise_on_nan=False)
+        fb = lat.mlp_stats() if eos == "mlp" else None
+        kt = lat.step_timed(3)
+        bpc = lat.bytes_per_cell
+    finally:
+        lat.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return dict(seconds=dt, mlups=N * steps / dt / 1e6, ms_per_step=1e3 * dt / steps, bytes_per_cell=bpc,
+                kernel_ms=kt, finite=bool(sums[-1] == 0), fallback_fraction=fb, mass=float(sums[0]))
+
+
+def cpu_baseline(st, seconds_target=15.0):
+    import oracle
+    c = st["tgv_3d_256"]
+    k = st["constants"]
+    shape = (64, 64, 64)
+    from paper_2510_14712_amd import inputs
+    rho, u, T = inputs.taylor_green(shape, c["seed"], c["rho0"], c["T0"], c["U0"], c["noise"])
+    p = oracle.Params(3, shape, a=k["a"], b=k["b"], R=k["R"], cv=k["cv"], mu=k["mu"], eta=k["eta"], k=k["k"],
+                      kappa=k["kappa"])
+    f, g = oracle.init(p, rho, u, T)
+    t0 = time.perf_counter()
+    f, g = oracle.run(p, f, g, 1)
+    one = time.perf_counter() - t0
+    n = max(1, int(seconds_target / max(one, 1e-3)))
+    t0 = time.perf_counter()
+    oracle.run(p, f, g, n)
+    dt = time.perf_counter() - t0
+    return {"value": p.N * n / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle, D3Q27 Taylor-Green 64^3 (same state recipe), {n} steps, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="tgv512")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2510_14712_amd import inputs, lbm
+    lbm.load()
+    torch.cuda.set_device(0)
+    st = inputs.states()
+    k = st["constants"]
+    kw = dict(a=k["a"], b=k["b"], R=k["R"], cv=k["cv"], mu=k["mu"], eta=k["eta"], k=k["k"], kappa=k["kappa"])
+    shape, bc, fields, ref, desc = workload(args.workload, st)
+    N = int(np.prod(shape))
+
+    _p("training the surrogate EOS on the GPU")
+    params, norm, loss, t_train = train_surrogate(st, lbm)
+    _p(f"  loss {loss:.3e} in {t_train:.1f} s")
+    _p(f"plain FP32 form on {shape}")
+    plain = time_form(lbm, torch, shape, bc, fields, ref, kw, "f32", "vdw", args.steps, args.warmup)
+    _p(f"  {plain['mlups']:.0f} MLUPS, kernels {plain['kernel_ms']}")
+    _p("surrogate + BF16 deviation form")
+    surr = time_form(lbm, torch, shape, bc, fields, ref, kw, "bf16", "mlp", args.steps, args.warmup,
+                     mlp=(params, norm))
+    _p(f"  {surr['mlups']:.0f} MLUPS, kernels {surr['kernel_ms']}, fallback {surr['fallback_fraction']}")
+
+    def roof(form):
+        kms = form["kernel_ms"]
+        dom = max(kms, key=kms.get)
+        bytes_launch = form["bytes_per_cell"] * N
+        achieved = bytes_launch / (kms[dom] * 1e-3) / 1e9
+        return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+
+    dom, rl = roof(surr)
+    line = {
+        "metric": "MLUPS & % HBM peak, D3Q27 fused step: plain FP32 vs surrogate-EOS/BF16 form",
+        "value": round(surr["mlups"], 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(surr["ms_per_step"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16-storage/f32", "data": "synthetic",
+        "config": {"workload": desc, "form": "BF16 deviation storage + MLP EOS (BF16 MFMA) + Newton fallback",
+                   "cells": N},
+        "roofline": dict(rl, kernel=dom),
+        "forms": {
+            "plain_fp32": {"mlups": round(plain["mlups"], 1), "ms_per_step": round(plain["ms_per_step"], 4),
+                           "step_hbm_frac": round(plain["bytes_per_cell"] * plain["mlups"] * 1e6 / 1e9
+                                                  / HBM_PEAK_GBS, 4),
+                           "kernel_ms": plain["kernel_ms"], "finite": plain["finite"],
+                           "roofline": roof(plain)[1]},
+            "surrogate_bf16": {"mlups": round(surr["mlups"], 1), "ms_per_step": round(surr["ms_per_step"], 4),
+                               "step_hbm_frac": round(surr["bytes_per_cell"] * surr["mlups"] * 1e6 / 1e9
+                                                      / HBM_PEAK_GBS, 4),
+                               "kernel_ms": surr["kernel_ms"], "finite": surr["finite"],
+                               "fallback_fraction": surr["fallback_fraction"], "mlp_train_s": round(t_train, 2),
+                               "mlp_loss": loss},
+        },
+    }
+    if not args.no_cpu_baseline:
+        _p("CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline(st)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) fused stream-collide step of the
+ * non-ideal compressible double-distribution lattice Boltzmann method of
+ * Hosseini, Feinberg & Karlin (arXiv 2510.14712).
+ *
+ * The calls follow the paper's statement of the problem (Section 3.2 and the
+ * flowchart closing it): initialise {f_i, g_i} = {f_i^eq, g_i^eq} from
+ * (rho, u, T); iterate "moments -> Korteweg force -> u, E, T, P, Phi, q^c ->
+ * attractors -> collide and stream"; read back rho, u, T, P.
+ *
+ * Conventions shared by every entry point
+ *   - Lattice units: dx = dt = 1, lattice speed 1, lattice sound speed^2 = 1/3,
+ *     quasi-equilibrium relaxation time lambda = dt (Section 3.2).
+ *   - D = 2 uses D2Q9, D = 3 uses D3Q27 (eq. D3Q27c).  Velocity index
+ *       i = (c_x + 1) + 3 (c_y + 1) [+ 9 (c_z + 1)],  c_a in {-1, 0, 1}.
+ *   - Cell index idx = x + nx (y + ny z), x fastest; nz = 1 when D = 2.
+ *   - Fields are FP64 structure-of-arrays: scalar[N], vector[a * N + idx],
+ *     populations[i * N + idx], N = nx ny nz.
+ *   - Per axis boundary: LBM_BC_PERIODIC, or LBM_BC_ZEROGRAD (populations
+ *     entering from outside are the boundary cell's own post-collision
+ *     values; finite-difference stencils clamp to the domain).
+ *   - Pointers named dev_* are device pointers on the context's device
+ *     (e.g. torch.cuda tensors' data_ptr()); they are caller-owned and only
+ *     accessed during the call (asynchronously on the context's stream for
+ *     calls documented as asynchronous).  Host pointers are named host_*.
+ *   - Every function returns LBM_OK (0) or a negative status; no exception
+ *     or abort crosses the ABI.  lbm_strerror() names a status.
+ *   - A context is not thread-safe; use one context per stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)     /* invalid argument or parameter combination */
+#define LBM_ENOMEM (-2)     /* device allocation failed */
+#define LBM_EDEVICE (-3)    /* a HIP call or kernel launch failed */
+#define LBM_EUNSTABLE (-4)  /* a cell left the admissible set (theta <= 0,
+                               theta + u_a^2 >= 1, rho <= 0 or b rho >= 1) */
+#define LBM_ENAN (-5)       /* a non-finite value was found */
+#define LBM_ESTATE (-6)     /* call out of order (e.g. step before init) */
+
+/* ---- enumerations ------------------------------------------------------ */
+#define LBM_BC_PERIODIC 0
+#define LBM_BC_ZEROGRAD 1
+
+/* population storage; arithmetic is FP64 for LBM_STORE_F64 and FP32 for the
+ * others.  The two 16-bit forms store f_i - f_i^ref (and g_i - g_i^ref) with
+ * round-to-nearest-even, where the reference is the rest equilibrium at
+ * (ref_rho, ref_T): f^ref = f^eq(ref_rho, 0, theta_ref), g^ref likewise. */
+#define LBM_STORE_F64 0
+#define LBM_STORE_F32 1
+#define LBM_STORE_BF16 2
+#define LBM_STORE_F16 3
+
+/* equation-of-state evaluation inside the step */
+#define LBM_EOS_VDW 0       /* explicit van der Waals caloric inversion, eq. lbm_temp */
+#define LBM_EOS_MLP 1       /* learned surrogate (rho, e) -> (T, P, c_s^2) with a
+                               per-cell residual check and exact Newton fallback */
+
+/* ---- parameters --------------------------------------------------------- */
+typedef struct {
+    int lattice;            /* 2 (D2Q9) or 3 (D3Q27) */
+    int nx, ny, nz;         /* lattice size, nz = 1 for lattice 2 */
+    int bc[3];              /* per-axis LBM_BC_* */
+    double a, b, R, cv;     /* van der Waals constants (eq. Pvdw) and c_v */
+    double mu, eta, k;      /* shear and bulk viscosity, thermal conductivity */
+    double kappa;           /* capillarity coefficient (eq. FK) */
+    int storage;            /* LBM_STORE_* */
+    int eos;                /* LBM_EOS_* */
+    double mlp_tol;         /* surrogate acceptance threshold on
+                               |e(rho, T_hat) - e| / (c_v T_hat) */
+    double ref_rho, ref_T;  /* reference state of the 16-bit storage forms */
+    void *stream;           /* hipStream_t for all asynchronous work; NULL =
+                               the null stream */
+} lbm_params;
+
+typedef struct lbm_ctx lbm_ctx; /* opaque, library-owned */
+
+/* Create a context: validates parameters and allocates the two population
+ * buffers and the per-cell work arrays on the current device.
+ * Errors: LBM_EINVAL (bad sizes, lattice, bc, storage/eos combination,
+ * non-positive cv, mu; nz != 1 for lattice 2), LBM_ENOMEM, LBM_EDEVICE. */
+int lbm_create(const lbm_params *params, lbm_ctx **out);
+
+/* Release every device allocation of the context (NULL is accepted). */
+void lbm_destroy(lbm_ctx *ctx);
+
+/* Initialise f_i = f_i^eq(rho, u, theta), g_i = g_i^eq(rho, u, T, theta) with
+ * theta = P(rho, T)/rho (flowchart "initialise"; eqs. LBMeq, LBMeqG).
+ * dev_rho[N], dev_u[D*N], dev_T[N]: FP64 device arrays.  Asynchronous.
+ * Errors: LBM_EINVAL (NULL pointer), LBM_EDEVICE. */
+int lbm_init(lbm_ctx *ctx, const double *dev_rho, const double *dev_u, const double *dev_T);
+
+/* Advance n >= 0 full steps (collide + stream).  Asynchronous: non-finite
+ * states surface through lbm_conservation().
+ * Errors: LBM_ESTATE (not initialised), LBM_EINVAL (n < 0), LBM_EDEVICE. */
+int lbm_step(lbm_ctx *ctx, int n);
+
+/* Macroscopic fields of the current state with the half-force corrections
+ * (eqs. def_h, def_u, def_E, lbm_temp, Pvdw).  Any pointer may be NULL.
+ * dev_rho[N], dev_u[D*N], dev_T[N], dev_P[N] FP64.  Asynchronous. */
+int lbm_moments(lbm_ctx *ctx, double *dev_rho, double *dev_u, double *dev_T, double *dev_P);
+
+/* Raw populations (decoded to FP64) of the current state, post-streaming at
+ * time t; layout populations[i * N + idx].  Asynchronous. */
+int lbm_get_populations(lbm_ctx *ctx, double *dev_f, double *dev_g);
+
+/* Overwrite the state with the given FP64 populations (rounded to the
+ * storage form).  Asynchronous.  Resume from lbm_get_populations output
+ * reproduces the continuation bitwise for FP64/FP32 storage. */
+int lbm_set_populations(lbm_ctx *ctx, const double *dev_f, const double *dev_g);
+
+/* FP64 global sums of the current state, deterministic order (wavefront
+ * reductions, fixed-order second pass).  host_out receives, in order:
+ *   [0] sum rho, [1..D] sum (sum_i c_i f_i + F/2) = sum rho u,
+ *   [D+1] sum_i g_i summed over cells, [D+2] number of non-finite cells.
+ * Blocking (synchronises the stream).  Returns LBM_ENAN when [D+2] > 0. */
+int lbm_conservation(lbm_ctx *ctx, double *host_out);
+
+/* Block until all work queued on the context's stream has finished. */
+int lbm_synchronize(lbm_ctx *ctx);
+
+/* Timed variant of lbm_step for measurement: runs n steps on the context's
+ * stream with HIP events around every kernel launch and writes the average
+ * duration in milliseconds of each kernel kind of the step to host_ms[k],
+ * k < LBM_NUM_KERNELS (names from lbm_kernel_name).  Blocking.
+ * Errors: as lbm_step; LBM_EINVAL when nslots < LBM_NUM_KERNELS. */
+#define LBM_NUM_KERNELS 4
+int lbm_step_timed(lbm_ctx *ctx, int n, double *host_ms, int nslots);
+const char *lbm_kernel_name(int kernel);
+
+/* Algorithmic HBM bytes moved per cell update by lbm_step (2 Q populations
+ * read + 2 Q written, in the storage width) -- the traffic an ideal fused
+ * kernel needs, used for roofline accounting. */
+double lbm_bytes_per_cell(const lbm_ctx *ctx);
+
+const char *lbm_strerror(int status);
+
+/* Text of the most recent failed HIP call seen by the library on the calling
+ * thread ("" if none): the detail behind LBM_EDEVICE and LBM_ENOMEM. */
+const char *lbm_last_error(void);
+
+/* ---- learned equation-of-state surrogate ------------------------------- */
+/* Network 2 -> 64 -> 64 -> 3 with tanh hidden layers.  Parameter vector
+ * (4547 FP32 values, LBM_MLP_NPARAMS):
+ *   W1[64][2], b1[64], W2[64][64], b2[64], W3[3][64], b3[3]
+ * Normalisation vector (10 FP32 values, LBM_MLP_NNORM):
+ *   lo_rho, hi_rho, lo_e, hi_e, mean_T, std_T, mean_P, std_P, mean_c2, std_c2
+ * Inputs are scaled to [-1, 1]: xhat = 2 (x - lo)/(hi - lo) - 1; outputs are
+ * yhat * std + mean.  The 64x64 layer runs on BF16 MFMA with FP32 accumulate
+ * (LBM_MLP_BF16) or in FP32 on the vector ALU (LBM_MLP_F32). */
+#define LBM_MLP_NPARAMS 4547
+#define LBM_MLP_NNORM 10
+#define LBM_MLP_BF16 0
+#define LBM_MLP_F32 1
+
+/* Train a surrogate on the GPU with the library's own forward, backward and
+ * Adam kernels.  Samples (rho, T) are drawn uniformly from the box
+ * host_box = {rho_lo, rho_hi, T_lo, T_hi} by a counter-based generator
+ * seeded with `seed`; targets (T, P, c_s^2) and inputs (rho, e) come from
+ * the context-free van der Waals closed forms with the constants of params
+ * (eqs. Pvdw, de_vdW, vdW_speed_of_sound).  MSE loss on z-scored outputs,
+ * Adam (beta1 0.9, beta2 0.999, eps 1e-8), learning rate lr with cosine
+ * decay over `epochs` passes of n_samples / batch minibatches.
+ * host_params[4547] (in: initial weights, out: trained), host_norm[10]
+ * (out), host_loss (out, nullable: final epoch's mean loss).  Blocking.
+ * Errors: LBM_EINVAL (n_samples < batch, batch not a multiple of 64). */
+int lbm_mlp_train(const lbm_params *params, const double *host_box, int n_samples,
+                  uint64_t seed, int epochs, int batch, float lr, int precision,
+                  float *host_params, float *host_norm, double *host_loss);
+
+/* Install a trained surrogate in a context created with eos = LBM_EOS_MLP.
+ * host_params[4547], host_norm[10].  Blocking copy to device memory. */
+int lbm_mlp_set(lbm_ctx *ctx, const float *host_params, const float *host_norm);
+
+/* Fraction of cell evaluations since the last call that failed the residual
+ * check and took the Newton fallback (blocking; resets the counters). */
+int lbm_mlp_stats(lbm_ctx *ctx, double *host_fallback_fraction);
+
+/* Stand-alone surrogate forward pass: dev_x[2*B] raw (rho, e) pairs,
+ * dev_y[3*B] de-normalised (T, P, c_s^2); dev_params[4547], dev_norm[10].
+ * B >= 0 any size.  Asynchronous on `stream`. */
+int lbm_mlp_forward(const float *dev_params, const float *dev_norm, const float *dev_x,
+                    float *dev_y, int B, int precision, void *stream);
+
+/* Mean-squared loss and its gradient on a batch: dev_xn[2*B] normalised
+ * inputs, dev_tn[3*B] normalised targets (row-major per sample),
+ * dev_grad[4547] (out), dev_loss[1] (out).  B a positive multiple of 64.
+ * Asynchronous on `stream`. */
+int lbm_mlp_loss_grad(const float *dev_params, const float *dev_xn, const float *dev_tn,
+                      int B, float *dev_grad, float *dev_loss, int precision, void *stream);
+
+/* ---- precision codec ---------------------------------------------------- */
+/* dev_out[n] = 16-bit code of dev_x[n] - dev_ref[n] (FP32 subtraction,
+ * round-to-nearest-even; kind LBM_STORE_BF16 or LBM_STORE_F16); the decode
+ * is dev_ref + code.  Asynchronous on `stream`. */
+int lbm_codec_encode(int kind, const float *dev_x, const float *dev_ref, uint16_t *dev_out,
+                     int64_t n, void *stream);
+int lbm_codec_decode(int kind, const uint16_t *dev_code, const float *dev_ref, float *dev_out,
+                     int64_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

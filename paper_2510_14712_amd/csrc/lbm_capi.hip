@@ -1,0 +1,494 @@
+// C ABI of the non-ideal DDF lattice Boltzmann library (declared in lbm.h):
+// context management, launches of the step kernels, moments, population
+// access, conservation sums and the stand-alone codec.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "lbm.h"
+#include "lbm_kernels.hpp"
+#include "lbm_internal.hpp"
+
+using namespace lbm;
+
+// ---------------------------------------------------------------------------
+// Deterministic FP64 reductions: per-block partials (wavefront shuffles, then
+// LDS), then a single block summing the partials in block order.
+// ---------------------------------------------------------------------------
+namespace lbm {
+constexpr int RED_BLOCK = 256;
+constexpr int RED_VALS = 6;  // rho, j_x, j_y, j_z, G, non-finite count
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int D, class C>
+__global__ void __launch_bounds__(RED_BLOCK) k_reduce_partials(long long N, Fields<C> fl, double *partials) {
+    __shared__ double sh[RED_VALS][RED_BLOCK / 64];
+    double acc[RED_VALS] = {0, 0, 0, 0, 0, 0};
+    for (long long c = blockIdx.x * (long long)RED_BLOCK + threadIdx.x; c < N; c += (long long)gridDim.x * RED_BLOCK) {
+        double rho = fl.rho[c];
+        double G = fl.G[c];
+        bool bad = !isfinite(rho) || !isfinite(G);
+        acc[0] += rho;
+        for (int a = 0; a < D; a++) {
+            double j = (double)fl.J[a * N + c] + 0.5 * (double)fl.F[a * N + c];
+            acc[1 + a] += j;
+            bad = bad || !isfinite(j);
+        }
+        acc[4] += G;
+        acc[5] += bad ? 1.0 : 0.0;
+    }
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int k = 0; k < RED_VALS; k++) {
+        double s = wave_sum(acc[k]);
+        if (lane == 0) sh[k][w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < RED_VALS) {
+        double s = 0;
+        for (int i = 0; i < RED_BLOCK / 64; i++) s += sh[threadIdx.x][i];
+        partials[(long long)blockIdx.x * RED_VALS + threadIdx.x] = s;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_reduce_final(int nblocks, const double *partials, double *out) {
+    // one wave; lane k < RED_VALS sums column k in block order
+    int k = threadIdx.x;
+    if (k < RED_VALS) {
+        double s = 0;
+        for (int b = 0; b < nblocks; b++) s += partials[(long long)b * RED_VALS + k];
+        out[k] = s;
+    }
+}
+
+// population decode / encode between the storage form and FP64
+template <int D, class S>
+__global__ void __launch_bounds__(BX) k_get_pops(Grid g, RefPops ref, const typename S::T *fi, const typename S::T *gi,
+                                                 double *fo, double *go) {
+    using C = typename S::C;
+    constexpr int Q = Lattice<D>::Q;
+    int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    long long c = cell_index<D>(g, x, y, z);
+    for (int i = 0; i < Q; i++) {
+        fo[i * g.N + c] = (double)S::load(fi, i * g.N + c, (C)ref.f[i]);
+        go[i * g.N + c] = (double)S::load(gi, i * g.N + c, (C)ref.g[i]);
+    }
+}
+template <int D, class S>
+__global__ void __launch_bounds__(BX) k_set_pops(Grid g, RefPops ref, const double *fi, const double *gi,
+                                                 typename S::T *fo, typename S::T *go) {
+    using C = typename S::C;
+    constexpr int Q = Lattice<D>::Q;
+    int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    long long c = cell_index<D>(g, x, y, z);
+    for (int i = 0; i < Q; i++) {
+        fo[i * g.N + c] = S::enc((C)fi[i * g.N + c], (C)ref.f[i]);
+        go[i * g.N + c] = S::enc((C)gi[i * g.N + c], (C)ref.g[i]);
+    }
+}
+template <int D, class C>
+__global__ void __launch_bounds__(BX) k_export_moments(Grid g, Fields<C> fl, double *rho, double *u, double *T,
+                                                       double *P) {
+    int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    long long c = cell_index<D>(g, x, y, z);
+    if (rho) rho[c] = fl.rho[c];
+    if (u)
+        for (int a = 0; a < D; a++) u[a * g.N + c] = fl.u[a * g.N + c];
+    if (T) T[c] = fl.T[c];
+    if (P) P[c] = fl.P[c];
+}
+
+__global__ void k_codec_encode(int kind, const float *x, const float *ref, uint16_t *out, long long n) {
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float d = x[i] - ref[i];
+    out[i] = kind == LBM_STORE_BF16 ? f32_to_bf16_rne(d) : f32_to_f16_rne(d);
+}
+__global__ void k_codec_decode(int kind, const uint16_t *code, const float *ref, float *out, long long n) {
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = ref[i] + (kind == LBM_STORE_BF16 ? bf16_to_f32(code[i]) : f16_to_f32(code[i]));
+}
+}  // namespace lbm
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+static dim3 cell_grid(const lbm_ctx *c) {
+    return dim3((unsigned)((c->p.nx + BX - 1) / BX), (unsigned)c->p.ny, (unsigned)c->p.nz);
+}
+
+static thread_local char g_last_error[256] = "";
+
+int lbm_note(hipError_t e) {
+    if (e == hipSuccess) return LBM_OK;
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", hipGetErrorName(e), hipGetErrorString(e));
+    return LBM_EDEVICE;
+}
+
+static int hip_status(hipError_t e) { return lbm_note(e); }
+
+static int last_launch() { return hip_status(hipGetLastError()); }
+
+template <class C> static Phys<C> make_phys(const lbm_params &p) {
+    Phys<C> ph;
+    ph.a = (C)p.a; ph.b = (C)p.b; ph.R = (C)p.R; ph.cv = (C)p.cv;
+    ph.mu = (C)p.mu; ph.eta = (C)p.eta; ph.k = (C)p.k; ph.kappa = (C)p.kappa;
+    ph.inv_cv = (C)(1.0 / p.cv);
+    ph.k_over_mu = (C)(p.k / p.mu);
+    ph.eta_over_mu = (C)(p.eta / p.mu);
+    return ph;
+}
+
+// reference populations of the 16-bit forms: rest equilibria at (ref_rho,
+// ref_T) (Psi(0) = 1 - theta, Psi(+-1) = theta/2 at u = 0), computed in FP64.
+static void make_ref(const lbm_params &p, int D, RefPops &ref) {
+    std::memset(&ref, 0, sizeof(ref));
+    if (p.storage != LBM_STORE_BF16 && p.storage != LBM_STORE_F16) return;
+    double r = p.ref_rho, t = p.ref_T;
+    double P = r * p.R * t / (1.0 - p.b * r) - p.a * r * r;
+    double th = P / r;
+    double e = p.cv * t - p.a * r;
+    int Q = D == 2 ? 9 : 27;
+    // per axis at u = 0: p(0) = 1 - th, p(+-1) = th/2; q(0) = th - 3 th^2,
+    // q(+-1) = 3 th^2 / 2
+    for (int i = 0; i < Q; i++) {
+        int cc[3] = {cx_of(i), cy_of(i), D == 3 ? cz_of(i) : 0};
+        double pa[3], qa[3];
+        for (int a = 0; a < D; a++) {
+            pa[a] = cc[a] ? 0.5 * th : 1.0 - th;
+            qa[a] = cc[a] ? 1.5 * th * th : th - 3.0 * th * th;
+        }
+        double prod = 1.0, s = 0.0;
+        for (int a = 0; a < D; a++) prod *= pa[a];
+        for (int b = 0; b < D; b++) {
+            double t2 = qa[b];
+            for (int a = 0; a < D; a++)
+                if (a != b) t2 *= pa[a];
+            s += t2;
+        }
+        double feq = r * prod;
+        ref.f[i] = (float)feq;
+        ref.g[i] = (float)(feq * (e - 0.5 * D * th) + 0.5 * r * s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch over (lattice, storage)
+// ---------------------------------------------------------------------------
+template <int D, class S> struct Impl {
+    using C = typename S::C;
+    using T = typename S::T;
+
+    static Fields<C> &fields(lbm_ctx *c);
+
+    static int init(lbm_ctx *c, const double *rho, const double *u, const double *Tf) {
+        hipLaunchKernelGGL((k_init<D, S>), cell_grid(c), dim3(BX), 0, c->stream, c->grid, make_phys<double>(c->p), c->ref,
+                           rho, u, Tf, (T *)c->f[c->cur], (T *)c->g[c->cur]);
+        return last_launch();
+    }
+    static int fields_pass(lbm_ctx *c) {
+        Fields<C> fl = get_fields<C>(c);
+        dim3 gr = cell_grid(c);
+        hipLaunchKernelGGL((k_moments<D, S>), gr, dim3(BX), 0, c->stream, c->grid, c->ref, (const T *)c->f[c->cur],
+                           (const T *)c->g[c->cur], fl);
+        hipLaunchKernelGGL((k_lap<D, C>), gr, dim3(BX), 0, c->stream, c->grid, fl);
+        if (c->p.eos == LBM_EOS_MLP) {
+            int rc = launch_fields_mlp<D, C>(c, fl);
+            if (rc) return rc;
+        } else {
+            hipLaunchKernelGGL((k_fields<D, C>), gr, dim3(BX), 0, c->stream, c->grid, make_phys<C>(c->p), fl);
+        }
+        return last_launch();
+    }
+    static int step(lbm_ctx *c, int n) {
+        Fields<C> fl = get_fields<C>(c);
+        dim3 gr = cell_grid(c);
+        for (int s = 0; s < n; s++) {
+            int rc = fields_pass(c);
+            if (rc) return rc;
+            int nxt = 1 - c->cur;
+            hipLaunchKernelGGL((k_collide<D, S>), gr, dim3(BX), 0, c->stream, c->grid, make_phys<C>(c->p), c->ref,
+                               (const T *)c->f[c->cur], (const T *)c->g[c->cur], fl, (T *)c->f[nxt], (T *)c->g[nxt]);
+            rc = last_launch();
+            if (rc) return rc;
+            c->cur = nxt;
+        }
+        return LBM_OK;
+    }
+    // n steps with events between the launches: host_ms[k] receives the
+    // average duration of kernel kind k (moments, laplacian, fields, collide)
+    static int step_timed(lbm_ctx *c, int n, double *host_ms) {
+        hipEvent_t ev[5];
+        for (int k = 0; k < 5; k++)
+            if (hipEventCreate(&ev[k]) != hipSuccess) return LBM_EDEVICE;
+        double acc[4] = {0, 0, 0, 0};
+        Fields<C> fl = get_fields<C>(c);
+        dim3 gr = cell_grid(c);
+        int rc = LBM_OK;
+        for (int s = 0; s < n && rc == LBM_OK; s++) {
+            (void)hipEventRecord(ev[0], c->stream);
+            hipLaunchKernelGGL((k_moments<D, S>), gr, dim3(BX), 0, c->stream, c->grid, c->ref,
+                               (const T *)c->f[c->cur], (const T *)c->g[c->cur], fl);
+            (void)hipEventRecord(ev[1], c->stream);
+            hipLaunchKernelGGL((k_lap<D, C>), gr, dim3(BX), 0, c->stream, c->grid, fl);
+            (void)hipEventRecord(ev[2], c->stream);
+            if (c->p.eos == LBM_EOS_MLP) rc = launch_fields_mlp<D, C>(c, fl);
+            else hipLaunchKernelGGL((k_fields<D, C>), gr, dim3(BX), 0, c->stream, c->grid, make_phys<C>(c->p), fl);
+            (void)hipEventRecord(ev[3], c->stream);
+            int nxt = 1 - c->cur;
+            hipLaunchKernelGGL((k_collide<D, S>), gr, dim3(BX), 0, c->stream, c->grid, make_phys<C>(c->p), c->ref,
+                               (const T *)c->f[c->cur], (const T *)c->g[c->cur], fl, (T *)c->f[nxt], (T *)c->g[nxt]);
+            (void)hipEventRecord(ev[4], c->stream);
+            if (rc == LBM_OK) rc = last_launch();
+            c->cur = nxt;
+            if (hipEventSynchronize(ev[4]) != hipSuccess) rc = LBM_EDEVICE;
+            for (int k = 0; k < 4 && rc == LBM_OK; k++) {
+                float ms = 0;
+                if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess) rc = LBM_EDEVICE;
+                acc[k] += ms;
+            }
+        }
+        for (int k = 0; k < 5; k++) (void)hipEventDestroy(ev[k]);
+        for (int k = 0; k < 4; k++) host_ms[k] = n > 0 ? acc[k] / n : 0.0;
+        return rc;
+    }
+    static int moments(lbm_ctx *c, double *rho, double *u, double *Tf, double *P) {
+        int rc = fields_pass(c);
+        if (rc) return rc;
+        hipLaunchKernelGGL((k_export_moments<D, C>), cell_grid(c), dim3(BX), 0, c->stream, c->grid, get_fields<C>(c),
+                           rho, u, Tf, P);
+        return last_launch();
+    }
+    static int get_pops(lbm_ctx *c, double *f, double *g) {
+        hipLaunchKernelGGL((k_get_pops<D, S>), cell_grid(c), dim3(BX), 0, c->stream, c->grid, c->ref,
+                           (const T *)c->f[c->cur], (const T *)c->g[c->cur], f, g);
+        return last_launch();
+    }
+    static int set_pops(lbm_ctx *c, const double *f, const double *g) {
+        hipLaunchKernelGGL((k_set_pops<D, S>), cell_grid(c), dim3(BX), 0, c->stream, c->grid, c->ref, f, g,
+                           (T *)c->f[c->cur], (T *)c->g[c->cur]);
+        return last_launch();
+    }
+    static int conservation(lbm_ctx *c, double *host_out) {
+        int rc = fields_pass(c);
+        if (rc) return rc;
+        hipLaunchKernelGGL((k_reduce_partials<D, C>), dim3(c->red_blocks), dim3(RED_BLOCK), 0, c->stream,
+                           (long long)c->grid.N, get_fields<C>(c), c->red_partials);
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, c->stream, c->red_blocks, c->red_partials,
+                           c->red_out);
+        rc = last_launch();
+        if (rc) return rc;
+        double tmp[RED_VALS];
+        if (hipMemcpyAsync(tmp, c->red_out, sizeof(tmp), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return LBM_EDEVICE;
+        host_out[0] = tmp[0];
+        for (int a = 0; a < D; a++) host_out[1 + a] = tmp[1 + a];
+        host_out[D + 1] = tmp[4];
+        host_out[D + 2] = tmp[5];
+        return tmp[5] > 0 ? LBM_ENAN : LBM_OK;
+    }
+};
+
+#define DISPATCH(ctx, CALL)                                                                    \
+    do {                                                                                       \
+        const int st_ = (ctx)->p.storage;                                                      \
+        if ((ctx)->D == 2) {                                                                   \
+            if (st_ == LBM_STORE_F64) return Impl<2, StoreF64>::CALL;                          \
+            if (st_ == LBM_STORE_F32) return Impl<2, StoreF32>::CALL;                          \
+            if (st_ == LBM_STORE_BF16) return Impl<2, StoreBF16>::CALL;                        \
+            return Impl<2, StoreF16>::CALL;                                                    \
+        }                                                                                      \
+        if (st_ == LBM_STORE_F64) return Impl<3, StoreF64>::CALL;                              \
+        if (st_ == LBM_STORE_F32) return Impl<3, StoreF32>::CALL;                              \
+        if (st_ == LBM_STORE_BF16) return Impl<3, StoreBF16>::CALL;                            \
+        return Impl<3, StoreF16>::CALL;                                                        \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// exported entry points
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *lbm_strerror(int s) {
+    switch (s) {
+        case LBM_OK: return "ok";
+        case LBM_EINVAL: return "invalid argument";
+        case LBM_ENOMEM: return "device allocation failed";
+        case LBM_EDEVICE: return "HIP runtime or kernel launch error";
+        case LBM_EUNSTABLE: return "state left the admissible set";
+        case LBM_ENAN: return "non-finite value in the state";
+        case LBM_ESTATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+static int validate(const lbm_params *p) {
+    if (!p) return LBM_EINVAL;
+    if (p->lattice != 2 && p->lattice != 3) return LBM_EINVAL;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return LBM_EINVAL;
+    if (p->lattice == 2 && p->nz != 1) return LBM_EINVAL;
+    if (p->ny > 65535 || p->nz > 65535) return LBM_EINVAL;
+    for (int a = 0; a < 3; a++)
+        if (p->bc[a] != LBM_BC_PERIODIC && p->bc[a] != LBM_BC_ZEROGRAD) return LBM_EINVAL;
+    if (p->storage < LBM_STORE_F64 || p->storage > LBM_STORE_F16) return LBM_EINVAL;
+    if (p->eos != LBM_EOS_VDW && p->eos != LBM_EOS_MLP) return LBM_EINVAL;
+    if (p->eos == LBM_EOS_MLP && p->storage == LBM_STORE_F64) return LBM_EINVAL;
+    if (!(p->cv > 0) || !(p->mu > 0) || !(p->R > 0)) return LBM_EINVAL;
+    if ((p->storage == LBM_STORE_BF16 || p->storage == LBM_STORE_F16) && !(p->ref_rho > 0 && p->ref_T > 0))
+        return LBM_EINVAL;
+    return LBM_OK;
+}
+
+int lbm_create(const lbm_params *params, lbm_ctx **out) {
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    int rc = validate(params);
+    if (rc) return rc;
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return LBM_ENOMEM;
+    c->p = *params;
+    c->D = params->lattice;
+    c->Q = c->D == 2 ? 9 : 27;
+    c->stream = (hipStream_t)params->stream;
+    c->grid.nx = params->nx; c->grid.ny = params->ny; c->grid.nz = params->nz;
+    c->grid.clampx = params->bc[0]; c->grid.clampy = params->bc[1]; c->grid.clampz = params->bc[2];
+    c->grid.N = (long long)params->nx * params->ny * params->nz;
+    const long long N = c->grid.N;
+    int sb = params->storage == LBM_STORE_F64 ? 8 : (params->storage == LBM_STORE_F32 ? 4 : 2);
+    c->store_bytes = sb;
+    int cb = params->storage == LBM_STORE_F64 ? 8 : 4;
+    make_ref(*params, c->D, c->ref);
+    size_t pop_bytes = (size_t)c->Q * N * sb;
+    // field arrays: rho, J[D], G, lap, u[D], F[D], Lam[D], T, P, h, cs2
+    size_t nfield = (size_t)(8 + 4 * c->D);
+    size_t field_bytes = nfield * N * cb;
+    c->red_blocks = 1024;
+    bool ok = hipMalloc(&c->f[0], pop_bytes) == hipSuccess && hipMalloc(&c->f[1], pop_bytes) == hipSuccess &&
+              hipMalloc(&c->g[0], pop_bytes) == hipSuccess && hipMalloc(&c->g[1], pop_bytes) == hipSuccess &&
+              hipMalloc(&c->work, field_bytes) == hipSuccess &&
+              hipMalloc((void **)&c->red_partials, sizeof(double) * RED_VALS * c->red_blocks) == hipSuccess &&
+              hipMalloc((void **)&c->red_out, sizeof(double) * RED_VALS) == hipSuccess &&
+              hipMalloc((void **)&c->mlp_counters, sizeof(unsigned long long) * 2) == hipSuccess &&
+              hipMalloc((void **)&c->mlp_params, sizeof(float) * (LBM_MLP_NPARAMS + 64)) == hipSuccess &&
+              hipMalloc((void **)&c->mlp_norm, sizeof(float) * 16) == hipSuccess;
+    if (!ok) {
+        lbm_note(hipGetLastError());
+        lbm_destroy(c);
+        return LBM_ENOMEM;
+    }
+    hipMemsetAsync(c->mlp_counters, 0, sizeof(unsigned long long) * 2, c->stream);
+    c->cur = 0;
+    c->initialized = false;
+    c->mlp_ready = false;
+    *out = c;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx *c) {
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+    void *ptrs[] = {c->f[0], c->f[1], c->g[0], c->g[1], c->work, c->red_partials, c->red_out,
+                    c->mlp_counters, c->mlp_params, c->mlp_norm};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    delete c;
+}
+
+int lbm_init(lbm_ctx *c, const double *rho, const double *u, const double *Tf) {
+    if (!c || !rho || !u || !Tf) return LBM_EINVAL;
+    c->cur = 0;
+    c->initialized = true;
+    DISPATCH(c, init(c, rho, u, Tf));
+}
+
+int lbm_step(lbm_ctx *c, int n) {
+    if (!c) return LBM_EINVAL;
+    if (!c->initialized) return LBM_ESTATE;
+    if (n < 0) return LBM_EINVAL;
+    if (c->p.eos == LBM_EOS_MLP && !c->mlp_ready) return LBM_ESTATE;
+    DISPATCH(c, step(c, n));
+}
+
+int lbm_moments(lbm_ctx *c, double *rho, double *u, double *Tf, double *P) {
+    if (!c) return LBM_EINVAL;
+    if (!c->initialized) return LBM_ESTATE;
+    if (c->p.eos == LBM_EOS_MLP && !c->mlp_ready) return LBM_ESTATE;
+    DISPATCH(c, moments(c, rho, u, Tf, P));
+}
+
+int lbm_get_populations(lbm_ctx *c, double *f, double *g) {
+    if (!c || !f || !g) return LBM_EINVAL;
+    if (!c->initialized) return LBM_ESTATE;
+    DISPATCH(c, get_pops(c, f, g));
+}
+
+int lbm_set_populations(lbm_ctx *c, const double *f, const double *g) {
+    if (!c || !f || !g) return LBM_EINVAL;
+    c->initialized = true;
+    DISPATCH(c, set_pops(c, f, g));
+}
+
+int lbm_conservation(lbm_ctx *c, double *host_out) {
+    if (!c || !host_out) return LBM_EINVAL;
+    if (!c->initialized) return LBM_ESTATE;
+    if (c->p.eos == LBM_EOS_MLP && !c->mlp_ready) return LBM_ESTATE;
+    DISPATCH(c, conservation(c, host_out));
+}
+
+int lbm_synchronize(lbm_ctx *c) {
+    if (!c) return LBM_EINVAL;
+    return hip_status(c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
+}
+
+int lbm_step_timed(lbm_ctx *c, int n, double *host_ms, int nslots) {
+    if (!c || !host_ms || n < 0) return LBM_EINVAL;
+    if (!c->initialized) return LBM_ESTATE;
+    if (c->p.eos == LBM_EOS_MLP && !c->mlp_ready) return LBM_ESTATE;
+    if (nslots < LBM_NUM_KERNELS) return LBM_EINVAL;
+    DISPATCH(c, step_timed(c, n, host_ms));
+}
+
+const char *lbm_last_error(void) { return g_last_error; }
+
+const char *lbm_kernel_name(int k) {
+    static const char *names[LBM_NUM_KERNELS] = {"k_moments", "k_lap", "k_fields", "k_collide"};
+    return k >= 0 && k < LBM_NUM_KERNELS ? names[k] : "";
+}
+
+double lbm_bytes_per_cell(const lbm_ctx *c) {
+    if (!c) return 0.0;
+    return 2.0 * 2.0 * c->Q * c->store_bytes;
+}
+
+int lbm_codec_encode(int kind, const float *x, const float *ref, uint16_t *out, int64_t n, void *stream) {
+    if ((kind != LBM_STORE_BF16 && kind != LBM_STORE_F16) || n < 0) return LBM_EINVAL;
+    if (n == 0) return LBM_OK;
+    if (!x || !ref || !out) return LBM_EINVAL;
+    hipLaunchKernelGGL(k_codec_encode, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, kind, x,
+                       ref, out, (long long)n);
+    return last_launch();
+}
+
+int lbm_codec_decode(int kind, const uint16_t *code, const float *ref, float *out, int64_t n, void *stream) {
+    if ((kind != LBM_STORE_BF16 && kind != LBM_STORE_F16) || n < 0) return LBM_EINVAL;
+    if (n == 0) return LBM_OK;
+    if (!code || !ref || !out) return LBM_EINVAL;
+    hipLaunchKernelGGL(k_codec_decode, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, kind,
+                       code, ref, out, (long long)n);
+    return last_launch();
+}
+
+}  // extern "C"

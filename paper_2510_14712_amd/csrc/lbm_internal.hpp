@@ -1,0 +1,53 @@
+// Library-private definitions shared by the host translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbm.h"
+#include "lbm_kernels.hpp"
+
+struct lbm_ctx {
+    lbm_params p;
+    lbm::Grid grid;
+    int D, Q, store_bytes;
+    void *f[2] = {nullptr, nullptr};  // population state buffers (ping-pong)
+    void *g[2] = {nullptr, nullptr};
+    int cur = 0;                      // index of the buffer holding the state
+    void *work = nullptr;             // per-cell field arrays
+    lbm::RefPops ref;
+    hipStream_t stream = nullptr;
+    bool initialized = false;
+    bool mlp_ready = false;
+    int red_blocks = 0;
+    double *red_partials = nullptr;
+    double *red_out = nullptr;
+    unsigned long long *mlp_counters = nullptr;  // [0] fallbacks, [1] evaluations
+    float *mlp_params = nullptr;                 // 4547 FP32 + BF16 copy of W2
+    float *mlp_norm = nullptr;
+};
+
+// carve the field arrays out of the work buffer
+template <class C> static inline lbm::Fields<C> get_fields(lbm_ctx *c) {
+    const long long N = c->grid.N;
+    const int D = c->D;
+    C *w = (C *)c->work;
+    lbm::Fields<C> fl;
+    fl.rho = w; w += N;
+    fl.J = w; w += D * N;
+    fl.G = w; w += N;
+    fl.lap = w; w += N;
+    fl.u = w; w += D * N;
+    fl.F = w; w += D * N;
+    fl.Lam = w; w += D * N;
+    fl.T = w; w += N;
+    fl.P = w; w += N;
+    fl.h = w; w += N;
+    fl.cs2 = w; w += N;
+    return fl;
+}
+
+// Record a failed HIP call's message for lbm_last_error(); returns the status.
+int lbm_note(hipError_t e);
+
+// surrogate-EOS variant of the per-cell fields pass (defined with the MLP code)
+template <int D, class C> int launch_fields_mlp(lbm_ctx *c, lbm::Fields<C> fl);

@@ -1,0 +1,288 @@
+// Kernels of the non-ideal DDF lattice Boltzmann step (arXiv 2510.14712,
+// Section 3.2 and its flowchart).  Structure-of-arrays populations, x fastest;
+// one thread per cell, grid (ceil(nx / BX), ny, nz).
+//
+// The stored state is the post-streaming population set at time t (what the
+// flowchart initialises to the equilibria).  One step is four launches:
+//   k_moments  rho, j = sum c_i f_i, G = sum g_i per cell           (eqs. def_h..)
+//   k_lap      discrete Laplacian of rho                             (eq. FK)
+//   k_fields   Korteweg force, u, E, T, P, h, c_s^2, Lambda per cell (eqs. FK,
+//              def_u, def_E, lbm_temp, Pvdw, enthalpy, correction)
+//   k_collide  gradients, shifts, attractors, relax, then stream by pushing
+//              f'_i(x) to x + c_i of the other buffer
+//              (eqs. fLBGK, gLBGK, LBMeq, LBMstar, LBMeqG, LBMgstar, sh_*, qc_1)
+#pragma once
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+constexpr int BX = 256;
+
+// field arrays of one step, compute precision C
+template <class C> struct Fields {
+    C *rho, *J, *G;      // moments (J has D components)
+    C *lap;              // Laplacian of rho
+    C *u, *F, *Lam;      // D components each
+    C *T, *P, *h, *cs2;  // scalars
+};
+
+template <int D> __device__ __forceinline__ long long cell_index(const Grid &g, int x, int y, int z) {
+    return (long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z);
+}
+
+// neighbour of (x, y, z) shifted by s along axis a (|s| <= 1)
+template <int D> __device__ __forceinline__ long long nb_axis(const Grid &g, int x, int y, int z, int a, int s) {
+    if (a == 0) x = wrap1(x + s, g.nx, g.clampx);
+    else if (a == 1) y = wrap1(y + s, g.ny, g.clampy);
+    else z = wrap1(z + s, g.nz, g.clampz);
+    return cell_index<D>(g, x, y, z);
+}
+
+// Streaming destinations along one axis of a population leaving coordinate
+// v with velocity component c.  Periodic: wrap(v + c).  Zero-gradient: v + c
+// when inside, and also v itself when v is the boundary cell and c points
+// inward (the cell outside the wall is the boundary cell's own copy).  Returns
+// the number of destinations (0, 1 or 2) written to d[].
+__device__ __forceinline__ int push_axis(int v, int c, int n, int clamp, int d[2]) {
+    int k = 0;
+    int p = v + c;
+    if (!clamp) {
+        d[k++] = p < 0 ? p + n : (p >= n ? p - n : p);
+        return k;
+    }
+    if (p >= 0 && p < n) d[k++] = p;
+    if ((v == 0 && c == 1) || (v == n - 1 && c == -1)) d[k++] = v;
+    return k;
+}
+
+// ---------------------------------------------------------------------------
+// Equilibria from per-axis factors.  p: Psi(c; u, theta + u^2) (f^eq factors);
+// q(0) = m2 - m4, q(+-1) = (m4 +- m3)/2 with the Gaussian raw moments
+// m2 = theta + u^2, m3 = u^3 + 3 theta u, m4 = u^4 + 6 theta u^2 + 3 theta^2
+// (the Psi weights applied to O^k(u^2) = m_{k+2} - theta m_k).  Applying the operators O_a of eq. Oa to
+// E = e + |u|^2/2 and collecting the product of eq. LBMeqG gives
+//   g_i = f_i (e - D theta / 2) + rho/2 sum_b q_b(c_ib) prod_{a != b} p_a(c_ia).
+// ---------------------------------------------------------------------------
+template <class C> struct AxisEq {
+    Axis3<C> p, q;
+};
+template <class C> __device__ __forceinline__ AxisEq<C> axis_eq(C u, C theta) {
+    AxisEq<C> r;
+    C u2 = u * u;
+    C m2 = theta + u2;
+    C m3 = u * (u2 + C(3) * theta);
+    C m4 = u2 * u2 + C(6) * theta * u2 + C(3) * theta * theta;
+    r.p = psi3(u, m2);
+    r.q.z = m2 - m4;
+    r.q.p = C(0.5) * (m4 + m3);
+    r.q.m = C(0.5) * (m4 - m3);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+template <int D, class S>
+__global__ void __launch_bounds__(BX) k_init(Grid g, Phys<double> ph, RefPops ref, const double *__restrict__ rho,
+                                             const double *__restrict__ u, const double *__restrict__ T,
+                                             typename S::T *__restrict__ fo, typename S::T *__restrict__ go) {
+    using C = typename S::C;
+    constexpr int Q = Lattice<D>::Q;
+    int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    long long c = cell_index<D>(g, x, y, z);
+    double r = rho[c], t = T[c];
+    double P = vdw_pressure(ph, r, t);
+    double theta = P / r;
+    double e = ph.cv * t - ph.a * r;
+    double eps = e - 0.5 * D * theta;
+    AxisEq<double> ax[3];
+    for (int a = 0; a < D; a++) ax[a] = axis_eq(u[a * g.N + c], theta);
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        double px = pick(ax[0].p, cx_of(i)), py = pick(ax[1].p, cy_of(i));
+        double qx = pick(ax[0].q, cx_of(i)), qy = pick(ax[1].q, cy_of(i));
+        double feq, gsum;
+        if (D == 2) {
+            feq = r * px * py;
+            gsum = qx * py + px * qy;
+        } else {
+            double pz = pick(ax[2].p, cz_of(i)), qz = pick(ax[2].q, cz_of(i));
+            feq = r * px * py * pz;
+            gsum = (qx * py + px * qy) * pz + px * py * qz;
+        }
+        double geq = feq * eps + 0.5 * r * gsum;
+        fo[i * g.N + c] = S::enc((C)feq, (C)ref.f[i]);
+        go[i * g.N + c] = S::enc((C)geq, (C)ref.g[i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <int D, class S>
+__global__ void __launch_bounds__(BX) k_moments(Grid g, RefPops ref, const typename S::T *__restrict__ fi,
+                                                const typename S::T *__restrict__ gi, Fields<typename S::C> fl) {
+    using C = typename S::C;
+    constexpr int Q = Lattice<D>::Q;
+    int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    long long c = cell_index<D>(g, x, y, z);
+    C rho = 0, J[3] = {0, 0, 0}, G = 0;
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        C f = S::load(fi, i * g.N + c, (C)ref.f[i]);
+        rho += f;
+        if (cx_of(i)) J[0] += cx_of(i) > 0 ? f : -f;
+        if (cy_of(i)) J[1] += cy_of(i) > 0 ? f : -f;
+        if (D == 3 && cz_of(i)) J[2] += cz_of(i) > 0 ? f : -f;
+        G += S::load(gi, i * g.N + c, (C)ref.g[i]);
+    }
+    fl.rho[c] = rho;
+    for (int a = 0; a < D; a++) fl.J[a * g.N + c] = J[a];
+    fl.G[c] = G;
+}
+
+template <int D, class C>
+__global__ void __launch_bounds__(BX) k_lap(Grid g, Fields<C> fl) {
+    int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    long long c = cell_index<D>(g, x, y, z);
+    C r0 = fl.rho[c], s = 0;
+    for (int a = 0; a < D; a++)
+        s += fl.rho[nb_axis<D>(g, x, y, z, a, 1)] + fl.rho[nb_axis<D>(g, x, y, z, a, -1)] - C(2) * r0;
+    fl.lap[c] = s;
+}
+
+// per-cell thermodynamic fields from the moments, the exact van der Waals
+// caloric inversion T = (E - u^2/2 + a rho)/c_v (eq. lbm_temp)
+template <int D, class C>
+__global__ void __launch_bounds__(BX) k_fields(Grid g, Phys<C> ph, Fields<C> fl) {
+    int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    long long c = cell_index<D>(g, x, y, z);
+    C rho = fl.rho[c];
+    C inv_rho = C(1) / rho;
+    C u[3], F[3], uF = 0, u2 = 0;
+    for (int a = 0; a < D; a++) {
+        C dl = C(0.5) * (fl.lap[nb_axis<D>(g, x, y, z, a, 1)] - fl.lap[nb_axis<D>(g, x, y, z, a, -1)]);
+        F[a] = ph.kappa * rho * dl;                          // eq. FK
+        u[a] = (fl.J[a * g.N + c] + C(0.5) * F[a]) * inv_rho;  // eq. def_u
+        uF += u[a] * F[a];
+        u2 += u[a] * u[a];
+    }
+    C E = (fl.G[c] + C(0.5) * uF) * inv_rho;                  // eq. def_E
+    C e = E - C(0.5) * u2;
+    C T = (e + ph.a * rho) * ph.inv_cv;                        // eq. lbm_temp
+    C P = vdw_pressure(ph, rho, T);                            // eq. Pvdw
+    C theta = P * inv_rho;
+    for (int a = 0; a < D; a++) {
+        fl.u[a * g.N + c] = u[a];
+        fl.F[a * g.N + c] = F[a];
+        // Lambda_a = rho u_a^3 + 3 rho u_a (theta - 1/3)   (eq. correction)
+        fl.Lam[a * g.N + c] = rho * u[a] * (u[a] * u[a] + C(3) * (theta - C(1.0 / 3.0)));
+    }
+    fl.T[c] = T;
+    fl.P[c] = P;
+    fl.h[c] = e + theta;                                       // eq. enthalpy
+    fl.cs2[c] = vdw_cs2(ph, rho, T);
+}
+
+// ---------------------------------------------------------------------------
+template <int D, class S>
+__global__ void __launch_bounds__(BX) k_collide(Grid g, Phys<typename S::C> ph, RefPops ref,
+                                                const typename S::T *__restrict__ fi,
+                                                const typename S::T *__restrict__ gi, Fields<typename S::C> fl,
+                                                typename S::T *__restrict__ fo, typename S::T *__restrict__ go) {
+    using C = typename S::C;
+    constexpr int Q = Lattice<D>::Q;
+    int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    const long long N = g.N;
+    long long c = cell_index<D>(g, x, y, z);
+    C rho = fl.rho[c], P = fl.P[c], T = fl.T[c];
+    C inv_rho = C(1) / rho;
+    C theta = P * inv_rho;
+    C u[3], F[3], divu = 0, qc[3], Phi[3], FF = 0;
+    for (int a = 0; a < D; a++) {
+        long long cp = nb_axis<D>(g, x, y, z, a, 1), cm = nb_axis<D>(g, x, y, z, a, -1);
+        u[a] = fl.u[a * N + c];
+        F[a] = fl.F[a * N + c];
+        FF += F[a] * F[a];
+        divu += C(0.5) * (fl.u[a * N + cp] - fl.u[a * N + cm]);
+        C dh = C(0.5) * (fl.h[cp] - fl.h[cm]);
+        C dT = C(0.5) * (fl.T[cp] - fl.T[cm]);
+        qc[a] = P * (dh - ph.k_over_mu * dT);                  // eq. qc_1
+        // upwind-biased d_a Lambda_a by sgn(u_a); sgn(0) = 0 gives the average
+        C L0 = fl.Lam[a * N + c];
+        C dL;
+        if (u[a] > C(0)) dL = L0 - fl.Lam[a * N + cm];
+        else if (u[a] < C(0)) dL = fl.Lam[a * N + cp] - L0;
+        else dL = C(0.5) * (fl.Lam[a * N + cp] - fl.Lam[a * N + cm]);
+        Phi[a] = -dL * inv_rho;                                // eq. correction
+    }
+    C beta = P / (P + C(2) * ph.mu);                           // eq. beta_main with tau = mu / P
+    C alpha = C(D + 2) / C(D) - rho * fl.cs2[c] / P - ph.eta_over_mu;  // eq. corr_bulk
+    C thetas = theta + alpha * theta * divu;                   // eq. sh_temp_1
+    C Ts = T - FF * inv_rho * inv_rho * C(0.5) * ph.inv_cv;    // eq. sh_T_1
+    C e = ph.cv * T - ph.a * rho;                              // e(rho, T), eq. de_vdW
+    C es = ph.cv * Ts - ph.a * rho;                            // e(rho, T*)
+    C eps_eq = e - C(0.5 * D) * theta;
+    C eps_st = es - C(0.5 * D) * thetas;
+
+    AxisEq<C> eq[3], st[3];
+    Axis3<C> pf[3];
+    for (int a = 0; a < D; a++) {
+        C us = u[a] + F[a] * inv_rho;                          // eq. sh_vel_1
+        eq[a] = axis_eq(u[a], theta);
+        st[a] = axis_eq(us, thetas);
+        pf[a] = psi3(us, thetas + us * us + Phi[a]);           // eq. zetastar
+    }
+    C w_keep = C(1) - C(2) * beta, w_eq = C(3) * beta - C(1), w_st = C(1) - beta;
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        const int ix = cx_of(i), iy = cy_of(i), iz = D == 3 ? cz_of(i) : 0;
+        C px = pick(eq[0].p, ix), py = pick(eq[1].p, iy);
+        C qx = pick(eq[0].q, ix), qy = pick(eq[1].q, iy);
+        C sx = pick(st[0].p, ix), sy = pick(st[1].p, iy);
+        C tx = pick(st[0].q, ix), ty = pick(st[1].q, iy);
+        C fsx = pick(pf[0], ix), fsy = pick(pf[1], iy);
+        C feq, geqs, fst, gsts;
+        if (D == 2) {
+            feq = rho * px * py;
+            geqs = qx * py + px * qy;
+            fst = rho * fsx * fsy;
+            gsts = tx * sy + sx * ty;
+        } else {
+            C pz = pick(eq[2].p, iz), qz = pick(eq[2].q, iz);
+            C sz = pick(st[2].p, iz), tz = pick(st[2].q, iz);
+            C fsz = pick(pf[2], iz);
+            feq = rho * px * py * pz;
+            geqs = (qx * py + px * qy) * pz + px * py * qz;
+            fst = rho * fsx * fsy * fsz;
+            gsts = (tx * sy + sx * ty) * sz + sx * sy * tz;
+        }
+        C geq = feq * eps_eq + C(0.5) * rho * geqs;
+        C gst = rho * (sx * sy * (D == 3 ? pick(st[2].p, iz) : C(1))) * eps_st + C(0.5) * rho * gsts;
+        if (csq_of<D>(i) == 1) {                               // eq. LBMgstar
+            C cq = ix ? (ix > 0 ? qc[0] : -qc[0]) : (iy ? (iy > 0 ? qc[1] : -qc[1]) : (iz > 0 ? qc[2] : -qc[2]));
+            gst += C(0.5) * cq;
+        }
+        C f = S::load(fi, i * N + c, (C)ref.f[i]);
+        C gg = S::load(gi, i * N + c, (C)ref.g[i]);
+        // eqs. fLBGK, gLBGK: f + 2 beta (f^eq - f) + (1 - beta)(f* - f^eq)
+        C fn = w_keep * f + w_eq * feq + w_st * fst;
+        C gn = w_keep * gg + w_eq * geq + w_st * gst;
+        typename S::T fe = S::enc(fn, (C)ref.f[i]), ge = S::enc(gn, (C)ref.g[i]);
+        int dx[2], dy[2], dz[2] = {0, 0};
+        int nxd = push_axis(x, ix, g.nx, g.clampx, dx);
+        int nyd = push_axis(y, iy, g.ny, g.clampy, dy);
+        int nzd = D == 3 ? push_axis(z, iz, g.nz, g.clampz, dz) : 1;
+        for (int a = 0; a < nxd; a++)
+            for (int b = 0; b < nyd; b++)
+                for (int cc = 0; cc < nzd; cc++) {
+                    long long d = cell_index<D>(g, dx[a], dy[b], dz[cc]);
+                    fo[i * N + d] = fe;
+                    go[i * N + d] = ge;
+                }
+    }
+}
+
+}  // namespace lbm

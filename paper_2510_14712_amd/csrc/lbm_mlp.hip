@@ -1,0 +1,563 @@
+// Learned equation-of-state surrogate (rho, e) -> (T, P, c_s^2): a
+// 2 -> 64 -> 64 -> 3 tanh network standing in for the caloric inversion of
+// Section 3.2 (explicit for van der Waals, eq. lbm_temp; iterative for a
+// general equation of state).  Inference runs inside the per-cell fields pass
+// with a residual check and an exact FP64 Newton fallback; training uses the
+// library's own forward, backward and Adam kernels.
+//
+// One wavefront handles 64 samples (cells).  The 64x64 hidden layer and the
+// two 64x64x64 products of the backward pass run through wave_gemm64: BF16
+// MFMA (v_mfma_f32_32x32x16_bf16, FP32 accumulate) or FP32 on the vector ALU,
+// both returning the result in the MFMA accumulator layout:
+//   tile (mt, nt) in {0,1}^2, accumulator v in 0..15, lane l holds
+//   row 32 mt + 8 (v / 4) + 4 (l / 32) + v % 4, column 32 nt + l % 32.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
+#include "lbm_internal.hpp"
+
+using namespace lbm;
+
+namespace lbm {
+namespace mlp {
+
+constexpr int H = 64;
+constexpr int OFF_W1 = 0, OFF_B1 = 128, OFF_W2 = 192, OFF_B2 = 4288, OFF_W3 = 4352, OFF_B3 = 4544;
+constexpr int NP = LBM_MLP_NPARAMS;
+constexpr int LD = 65;  // padded LDS row stride (floats) of a 64x64 activation tile
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float fast_tanh(float x) {
+    float ax = fminf(fabsf(x), 15.0f);
+    float e = __expf(-2.0f * ax);
+    float t = __fdividef(1.0f - e, 1.0f + e);
+    return copysignf(t, x);
+}
+
+__device__ __forceinline__ __bf16 to_bf16(float v) { return __builtin_bit_cast(__bf16, f32_to_bf16_rne(v)); }
+
+__device__ __forceinline__ int acc_row(int mt, int v, int lane) { return 32 * mt + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+__device__ __forceinline__ int acc_col(int nt, int lane) { return 32 * nt + (lane & 31); }
+
+// C(i, j) = sum_k A(i, k) B(k, j), i, j, k in [0, 64); A and B are strided
+// FP32 views: A(i, k) = A[i * ai + k * ak], B(k, j) = B[k * bk + j * bj].
+// acc[(mt * 2 + nt) * 16 + v] receives the entry at (acc_row, acc_col).
+template <bool MFMA>
+__device__ __forceinline__ void wave_gemm64(const float *A, int ai, int ak, const float *B, int bk, int bj,
+                                            float acc[64]) {
+    const int lane = threadIdx.x & 63;
+    if constexpr (MFMA) {
+        f32x16 c[4];
+        for (int t = 0; t < 4; t++)
+            for (int v = 0; v < 16; v++) c[t][v] = 0.0f;
+        for (int ks = 0; ks < 4; ks++) {
+            bf16x8 a[2], b[2];
+            const int k0 = 16 * ks + 8 * (lane >> 5);
+            for (int m = 0; m < 2; m++) {
+                const int i = 32 * m + (lane & 31);
+                for (int j = 0; j < 8; j++) {
+                    a[m][j] = to_bf16(A[i * ai + (k0 + j) * ak]);
+                    b[m][j] = to_bf16(B[(k0 + j) * bk + i * bj]);
+                }
+            }
+            for (int mt = 0; mt < 2; mt++)
+                for (int nt = 0; nt < 2; nt++)
+                    c[mt * 2 + nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mt], b[nt], c[mt * 2 + nt], 0, 0, 0);
+        }
+        for (int t = 0; t < 4; t++)
+            for (int v = 0; v < 16; v++) acc[t * 16 + v] = c[t][v];
+    } else {
+        for (int mt = 0; mt < 2; mt++)
+            for (int nt = 0; nt < 2; nt++)
+                for (int v = 0; v < 16; v++) {
+                    const int i = acc_row(mt, v, lane), j = acc_col(nt, lane);
+                    float s = 0.0f;
+                    for (int k = 0; k < 64; k++) s = fmaf(A[i * ai + k * ak], B[k * bk + j * bj], s);
+                    acc[(mt * 2 + nt) * 16 + v] = s;
+                }
+    }
+}
+
+// Forward pass of one wavefront.  x0, x1: normalised inputs of this lane's
+// sample; P: FP32 parameter vector; lds: 64 x LD floats private to the wave.
+// Returns the normalised outputs.  Every lane of the wave must call.
+template <bool MFMA>
+__device__ __forceinline__ void forward_wave(float x0, float x1, const float *__restrict__ P, float *lds,
+                                             float y[3]) {
+    const int lane = threadIdx.x & 63;
+    for (int j = 0; j < H; j++) {
+        float z = fmaf(P[OFF_W1 + 2 * j], x0, fmaf(P[OFF_W1 + 2 * j + 1], x1, P[OFF_B1 + j]));
+        lds[lane * LD + j] = fast_tanh(z);
+    }
+    __syncthreads();
+    float acc[64];
+    // Z2(b, n) = sum_k H1(b, k) W2(n, k)
+    wave_gemm64<MFMA>(lds, LD, 1, P + OFF_W2, 1, H, acc);
+    __syncthreads();
+    for (int t = 0; t < 4; t++)
+        for (int v = 0; v < 16; v++) {
+            const int r = acc_row(t >> 1, v, lane), cidx = acc_col(t & 1, lane);
+            lds[r * LD + cidx] = fast_tanh(acc[t * 16 + v] + P[OFF_B2 + cidx]);
+        }
+    __syncthreads();
+    for (int k = 0; k < 3; k++) {
+        float s = P[OFF_B3 + k];
+        for (int n = 0; n < H; n++) s = fmaf(P[OFF_W3 + k * H + n], lds[lane * LD + n], s);
+        y[k] = s;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void normalise(const float *norm, float rho, float e, float &x0, float &x1) {
+    x0 = 2.0f * (rho - norm[0]) / (norm[1] - norm[0]) - 1.0f;
+    x1 = 2.0f * (e - norm[2]) / (norm[3] - norm[2]) - 1.0f;
+}
+
+// ---------------------------------------------------------------------------
+// stand-alone forward: grid ceil(B / 64) blocks of one wave
+template <bool MFMA>
+__global__ void __launch_bounds__(64) k_forward(const float *P, const float *norm, const float *x, float *y, int B) {
+    __shared__ float lds[64 * LD];
+    const int b = blockIdx.x * 64 + threadIdx.x;
+    const int bc = b < B ? b : B - 1;
+    float x0, x1, o[3];
+    normalise(norm, x[2 * bc], x[2 * bc + 1], x0, x1);
+    forward_wave<MFMA>(x0, x1, P, lds, o);
+    if (b < B)
+        for (int k = 0; k < 3; k++) y[3 * b + k] = o[k] * norm[5 + 2 * k] + norm[4 + 2 * k];
+}
+
+// ---------------------------------------------------------------------------
+// Per-cell fields with the surrogate: as the exact fields pass, but T, P and
+// c_s^2 come from the network; a cell whose caloric residual
+// |e(rho, T_hat) - e| / (c_v T_hat) exceeds tol (or is not finite) takes one
+// FP64 Newton step on e(rho, T) = e from T_hat -- exact for van der Waals,
+// whose e is linear in T -- and the closed forms for P and c_s^2.
+constexpr int MLP_BLOCK = 128;  // two waves: 2 x 16.6 KB of LDS per workgroup
+
+template <int D>
+__global__ void __launch_bounds__(MLP_BLOCK) k_fields_mlp(Grid g, Phys<float> ph, Fields<float> fl, const float *P,
+                                                         const float *norm, float tol, unsigned long long *counters) {
+    __shared__ float lds[MLP_BLOCK / 64][64 * LD];
+    const int tid = threadIdx.x, wave = tid >> 6;
+    int x = blockIdx.x * MLP_BLOCK + tid, y = blockIdx.y, z = blockIdx.z;
+    const bool active = x < g.nx;
+    if (!active) x = g.nx - 1;
+    const long long c = cell_index<D>(g, x, y, z);
+    float rho = fl.rho[c];
+    float inv_rho = 1.0f / rho;
+    float u[3], F[3], uF = 0, u2 = 0;
+    for (int a = 0; a < D; a++) {
+        float dl = 0.5f * (fl.lap[nb_axis<D>(g, x, y, z, a, 1)] - fl.lap[nb_axis<D>(g, x, y, z, a, -1)]);
+        F[a] = ph.kappa * rho * dl;
+        u[a] = (fl.J[a * g.N + c] + 0.5f * F[a]) * inv_rho;
+        uF += u[a] * F[a];
+        u2 += u[a] * u[a];
+    }
+    float E = (fl.G[c] + 0.5f * uF) * inv_rho;
+    float e = E - 0.5f * u2;
+    float x0, x1, yh[3];
+    normalise(norm, rho, e, x0, x1);
+    forward_wave<true>(x0, x1, P, lds[wave], yh);
+    float T = yh[0] * norm[5] + norm[4];
+    float Pr = yh[1] * norm[7] + norm[6];
+    float c2 = yh[2] * norm[9] + norm[8];
+    float r = fabsf(ph.cv * T - ph.a * rho - e) / (ph.cv * fabsf(T));
+    const bool fb = !(r <= tol);
+    if (fb) {
+        double Td = (double)T, rd = (double)rho, cv = (double)ph.cv, a = (double)ph.a;
+        Td = Td - (cv * Td - a * rd - (double)e) / cv;  // Newton on e(rho, T) - e = 0
+        double omb = 1.0 - (double)ph.b * rd;
+        T = (float)Td;
+        Pr = (float)(rd * (double)ph.R * Td / omb - a * rd * rd);
+        c2 = (float)((double)ph.R * Td * (1.0 + (double)ph.R / cv) / (omb * omb) - 2.0 * a * rd);
+    }
+    unsigned long long nfb = __popcll(__ballot(fb && active));
+    unsigned long long nact = __popcll(__ballot(active));
+    if ((tid & 63) == 0) {
+        atomicAdd(&counters[0], nfb);
+        atomicAdd(&counters[1], nact);
+    }
+    if (!active) return;
+    float theta = Pr * inv_rho;
+    for (int a = 0; a < D; a++) {
+        fl.u[a * g.N + c] = u[a];
+        fl.F[a * g.N + c] = F[a];
+        fl.Lam[a * g.N + c] = rho * u[a] * (u[a] * u[a] + 3.0f * (theta - 1.0f / 3.0f));
+    }
+    fl.T[c] = T;
+    fl.P[c] = Pr;
+    fl.h[c] = e + theta;
+    fl.cs2[c] = c2;
+}
+
+// ---------------------------------------------------------------------------
+// Training.  One wave per block processes 64 samples of the batch and writes
+// its partial gradient (NP values) and partial squared error; a second kernel
+// sums the partials in block order.  Loss L = 1/(3B) sum (yhat - that)^2.
+template <bool MFMA>
+__global__ void __launch_bounds__(64) k_train_partial(const float *__restrict__ P, const float *__restrict__ xn,
+                                                     const float *__restrict__ tn, int B, float *__restrict__ gpart,
+                                                     float *__restrict__ lpart) {
+    __shared__ float H1[64 * LD], H2[64 * LD], DZ[64 * LD], X[64 * 2], DY[64 * 3];
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x * 64 + lane;
+    float *G = gpart + (long long)blockIdx.x * NP;
+    const float x0 = xn[2 * b], x1 = xn[2 * b + 1];
+    X[2 * lane] = x0;
+    X[2 * lane + 1] = x1;
+    for (int j = 0; j < H; j++)
+        H1[lane * LD + j] = fast_tanh(fmaf(P[OFF_W1 + 2 * j], x0, fmaf(P[OFF_W1 + 2 * j + 1], x1, P[OFF_B1 + j])));
+    __syncthreads();
+    float acc[64];
+    wave_gemm64<MFMA>(H1, LD, 1, P + OFF_W2, 1, H, acc);   // Z2 = H1 W2^T
+    for (int t = 0; t < 4; t++)
+        for (int v = 0; v < 16; v++) {
+            const int r = acc_row(t >> 1, v, lane), cc = acc_col(t & 1, lane);
+            H2[r * LD + cc] = fast_tanh(acc[t * 16 + v] + P[OFF_B2 + cc]);
+        }
+    __syncthreads();
+    const float scale = 2.0f / (3.0f * (float)B);
+    float sq = 0.0f;
+    for (int k = 0; k < 3; k++) {
+        float s = P[OFF_B3 + k];
+        for (int n = 0; n < H; n++) s = fmaf(P[OFF_W3 + k * H + n], H2[lane * LD + n], s);
+        float r = s - tn[3 * b + k];
+        sq += r * r;
+        DY[3 * lane + k] = scale * r;   // dL / dyhat
+    }
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+    if (lane == 0) lpart[blockIdx.x] = sq;
+    __syncthreads();
+    // output layer: dW3[k][n] = sum_b DY[b][k] H2[b][n]; db3[k] = sum_b DY[b][k]
+    for (int k = 0; k < 3; k++) {
+        float s = 0.0f;
+        for (int bb = 0; bb < 64; bb++) s = fmaf(DY[3 * bb + k], H2[bb * LD + lane], s);
+        G[OFF_W3 + k * H + lane] = s;
+    }
+    if (lane < 3) {
+        float s = 0.0f;
+        for (int bb = 0; bb < 64; bb++) s += DY[3 * bb + lane];
+        G[OFF_B3 + lane] = s;
+    }
+    // dZ2[b][n] = (sum_k DY[b][k] W3[k][n]) (1 - H2^2), lane n over all b
+    for (int bb = 0; bb < 64; bb++) {
+        float h2 = H2[bb * LD + lane];
+        float d = DY[3 * bb] * P[OFF_W3 + lane] + DY[3 * bb + 1] * P[OFF_W3 + H + lane] +
+                  DY[3 * bb + 2] * P[OFF_W3 + 2 * H + lane];
+        DZ[bb * LD + lane] = d * (1.0f - h2 * h2);
+    }
+    __syncthreads();
+    {   // db2[n] = sum_b dZ2[b][n]
+        float s = 0.0f;
+        for (int bb = 0; bb < 64; bb++) s += DZ[bb * LD + lane];
+        G[OFF_B2 + lane] = s;
+    }
+    // dW2[n][k] = sum_b dZ2[b][n] H1[b][k]
+    wave_gemm64<MFMA>(DZ, 1, LD, H1, LD, 1, acc);
+    for (int t = 0; t < 4; t++)
+        for (int v = 0; v < 16; v++)
+            G[OFF_W2 + acc_row(t >> 1, v, lane) * H + acc_col(t & 1, lane)] = acc[t * 16 + v];
+    // dH1[b][k] = sum_n dZ2[b][n] W2[n][k]
+    wave_gemm64<MFMA>(DZ, LD, 1, P + OFF_W2, H, 1, acc);
+    __syncthreads();
+    for (int t = 0; t < 4; t++)
+        for (int v = 0; v < 16; v++) {
+            const int r = acc_row(t >> 1, v, lane), cc = acc_col(t & 1, lane);
+            float h1 = H1[r * LD + cc];
+            H2[r * LD + cc] = acc[t * 16 + v] * (1.0f - h1 * h1);  // dZ1, reusing H2
+        }
+    __syncthreads();
+    {   // dW1[j][i] = sum_b dZ1[b][j] X[b][i]; db1[j] = sum_b dZ1[b][j]
+        float s0 = 0.0f, s1 = 0.0f, sb = 0.0f;
+        for (int bb = 0; bb < 64; bb++) {
+            float d = H2[bb * LD + lane];
+            s0 = fmaf(d, X[2 * bb], s0);
+            s1 = fmaf(d, X[2 * bb + 1], s1);
+            sb += d;
+        }
+        G[OFF_W1 + 2 * lane] = s0;
+        G[OFF_W1 + 2 * lane + 1] = s1;
+        G[OFF_B1 + lane] = sb;
+    }
+}
+
+__global__ void k_sum_partials(const float *gpart, const float *lpart, int nblk, int B, float *grad, float *loss) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < NP) {
+        float s = 0.0f;
+        for (int k = 0; k < nblk; k++) s += gpart[(long long)k * NP + p];
+        grad[p] = s;
+    }
+    if (p == 0 && loss) {
+        double s = 0.0;
+        for (int k = 0; k < nblk; k++) s += (double)lpart[k];
+        loss[0] = (float)(s / (3.0 * (double)B));
+    }
+}
+
+__global__ void k_adam(float *P, const float *grad, float *m, float *v, float lr, float bc1, float bc2) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= NP) return;
+    const float gp = grad[p];
+    float mm = 0.9f * m[p] + 0.1f * gp;
+    float vv = 0.999f * v[p] + 0.001f * gp * gp;
+    m[p] = mm;
+    v[p] = vv;
+    P[p] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + 1e-8f);
+}
+
+__global__ void k_accumulate_loss(const float *loss, double *acc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) acc[0] += (double)loss[0];
+}
+
+// counter-based uniform doubles: splitmix64 of (seed, stream, index)
+__device__ __forceinline__ double uniform01(unsigned long long seed, unsigned long long k) {
+    unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (k + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// samples (rho, T) uniform in the box; x = (rho, e), t = (T, P, c_s^2)
+__global__ void k_make_samples(int n, unsigned long long seed, Phys<double> ph, double r0, double r1, double T0,
+                               double T1, float *x, double *t) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double rho = r0 + (r1 - r0) * uniform01(seed, 2ull * i);
+    double T = T0 + (T1 - T0) * uniform01(seed, 2ull * i + 1);
+    double e = ph.cv * T - ph.a * rho;
+    double omb = 1.0 - ph.b * rho;
+    x[2 * i] = (float)rho;
+    x[2 * i + 1] = (float)e;
+    t[3 * i] = T;
+    t[3 * i + 1] = rho * ph.R * T / omb - ph.a * rho * rho;
+    t[3 * i + 2] = ph.R * T * (1.0 + ph.R / ph.cv) / (omb * omb) - 2.0 * ph.a * rho;
+}
+
+// per-output mean and standard deviation, FP64, deterministic (one block)
+__global__ void __launch_bounds__(256) k_target_stats(int n, const double *t, double *stats) {
+    __shared__ double sh[256];
+    for (int k = 0; k < 3; k++) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < n; i += 256) s += t[3 * i + k];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        double mean = sh[0] / n;
+        __syncthreads();
+        double q = 0.0;
+        for (int i = threadIdx.x; i < n; i += 256) {
+            double d = t[3 * i + k] - mean;
+            q += d * d;
+        }
+        sh[threadIdx.x] = q;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            stats[2 * k] = mean;
+            stats[2 * k + 1] = sqrt(sh[0] / n);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_normalise_samples(int n, const float *x, const double *t, const float *norm, float *xn, float *tn) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float a, b;
+    normalise(norm, x[2 * i], x[2 * i + 1], a, b);
+    xn[2 * i] = a;
+    xn[2 * i + 1] = b;
+    for (int k = 0; k < 3; k++) tn[3 * i + k] = (float)((t[3 * i + k] - (double)norm[4 + 2 * k]) / (double)norm[5 + 2 * k]);
+}
+
+}  // namespace mlp
+}  // namespace lbm
+
+// ---------------------------------------------------------------------------
+template <int D, class C> int launch_fields_mlp(lbm_ctx *c, Fields<C> fl) {
+    if constexpr (!std::is_same<C, float>::value) {
+        (void)c;
+        (void)fl;
+        return LBM_EINVAL;
+    } else {
+        Phys<float> ph;
+        const lbm_params &p = c->p;
+        ph.a = (float)p.a; ph.b = (float)p.b; ph.R = (float)p.R; ph.cv = (float)p.cv;
+        ph.mu = (float)p.mu; ph.eta = (float)p.eta; ph.k = (float)p.k; ph.kappa = (float)p.kappa;
+        ph.inv_cv = (float)(1.0 / p.cv); ph.k_over_mu = (float)(p.k / p.mu); ph.eta_over_mu = (float)(p.eta / p.mu);
+        dim3 gr((unsigned)((p.nx + mlp::MLP_BLOCK - 1) / mlp::MLP_BLOCK), (unsigned)p.ny, (unsigned)p.nz);
+        hipLaunchKernelGGL((mlp::k_fields_mlp<D>), gr, dim3(mlp::MLP_BLOCK), 0, c->stream, c->grid, ph, fl, c->mlp_params,
+                           c->mlp_norm, (float)p.mlp_tol, c->mlp_counters);
+        return lbm_note(hipGetLastError());
+    }
+}
+template int launch_fields_mlp<2, float>(lbm_ctx *, Fields<float>);
+template int launch_fields_mlp<3, float>(lbm_ctx *, Fields<float>);
+template int launch_fields_mlp<2, double>(lbm_ctx *, Fields<double>);
+template int launch_fields_mlp<3, double>(lbm_ctx *, Fields<double>);
+
+// ---------------------------------------------------------------------------
+namespace {
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    bool alloc(size_t n) { return lbm_note(hipMalloc(&p, n)) == LBM_OK; }
+    template <class T> T *as() { return (T *)p; }
+};
+}  // namespace
+
+extern "C" {
+
+int lbm_mlp_forward(const float *params, const float *norm, const float *x, float *y, int B, int precision,
+                    void *stream) {
+    if (B < 0 || (precision != LBM_MLP_BF16 && precision != LBM_MLP_F32)) return LBM_EINVAL;
+    if (B == 0) return LBM_OK;
+    if (!params || !norm || !x || !y) return LBM_EINVAL;
+    dim3 gr((unsigned)((B + 63) / 64));
+    if (precision == LBM_MLP_BF16)
+        hipLaunchKernelGGL(mlp::k_forward<true>, gr, dim3(64), 0, (hipStream_t)stream, params, norm, x, y, B);
+    else
+        hipLaunchKernelGGL(mlp::k_forward<false>, gr, dim3(64), 0, (hipStream_t)stream, params, norm, x, y, B);
+    return lbm_note(hipGetLastError());
+}
+
+static int loss_grad_impl(const float *params, const float *xn, const float *tn, int B, float *grad, float *loss,
+                          int precision, hipStream_t s, float *gpart, float *lpart) {
+    const int nblk = B / 64;
+    if (precision == LBM_MLP_BF16)
+        hipLaunchKernelGGL(mlp::k_train_partial<true>, dim3(nblk), dim3(64), 0, s, params, xn, tn, B, gpart, lpart);
+    else
+        hipLaunchKernelGGL(mlp::k_train_partial<false>, dim3(nblk), dim3(64), 0, s, params, xn, tn, B, gpart, lpart);
+    hipLaunchKernelGGL(mlp::k_sum_partials, dim3((mlp::NP + 255) / 256), dim3(256), 0, s, gpart, lpart, nblk, B,
+                       grad, loss);
+    return lbm_note(hipGetLastError());
+}
+
+int lbm_mlp_loss_grad(const float *params, const float *xn, const float *tn, int B, float *grad, float *loss,
+                      int precision, void *stream) {
+    if (B <= 0 || B % 64 || (precision != LBM_MLP_BF16 && precision != LBM_MLP_F32)) return LBM_EINVAL;
+    if (!params || !xn || !tn || !grad || !loss) return LBM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf gp, lp;
+    if (!gp.alloc(sizeof(float) * (size_t)(B / 64) * mlp::NP) || !lp.alloc(sizeof(float) * (size_t)(B / 64)))
+        return LBM_ENOMEM;
+    int rc = loss_grad_impl(params, xn, tn, B, grad, loss, precision, s, gp.as<float>(), lp.as<float>());
+    // the scratch buffers are released when this call returns
+    if (hipStreamSynchronize(s) != hipSuccess) return LBM_EDEVICE;
+    return rc;
+}
+
+int lbm_mlp_train(const lbm_params *prm, const double *box, int n, uint64_t seed, int epochs, int batch, float lr,
+                  int precision, float *host_params, float *host_norm, double *host_loss) {
+    if (!prm || !box || !host_params || !host_norm) return LBM_EINVAL;
+    if (batch <= 0 || batch % 64 || n < batch || epochs < 1 || !(lr > 0)) return LBM_EINVAL;
+    if (precision != LBM_MLP_BF16 && precision != LBM_MLP_F32) return LBM_EINVAL;
+    if (!(box[1] > box[0] && box[3] > box[2] && box[0] > 0 && box[2] > 0)) return LBM_EINVAL;
+    if (!(prm->cv > 0) || !(prm->b * box[1] < 1.0)) return LBM_EINVAL;
+    hipStream_t s = nullptr;
+    const int nbat = n / batch;
+    DevBuf x, t, xn, tn, P, m, v, grad, loss, gpart, lpart, stats, norm, lacc;
+    bool ok = x.alloc(sizeof(float) * 2 * (size_t)n) && t.alloc(sizeof(double) * 3 * (size_t)n) &&
+              xn.alloc(sizeof(float) * 2 * (size_t)n) && tn.alloc(sizeof(float) * 3 * (size_t)n) &&
+              P.alloc(sizeof(float) * mlp::NP) && m.alloc(sizeof(float) * mlp::NP) &&
+              v.alloc(sizeof(float) * mlp::NP) && grad.alloc(sizeof(float) * mlp::NP) && loss.alloc(sizeof(float)) &&
+              gpart.alloc(sizeof(float) * (size_t)(batch / 64) * mlp::NP) &&
+              lpart.alloc(sizeof(float) * (size_t)(batch / 64)) && stats.alloc(sizeof(double) * 6) &&
+              norm.alloc(sizeof(float) * 16) && lacc.alloc(sizeof(double));
+    if (!ok) return LBM_ENOMEM;
+    Phys<double> ph;
+    ph.a = prm->a; ph.b = prm->b; ph.R = prm->R; ph.cv = prm->cv;
+    ph.mu = ph.eta = ph.k = ph.kappa = 0; ph.inv_cv = 1.0 / prm->cv; ph.k_over_mu = ph.eta_over_mu = 0;
+    hipLaunchKernelGGL(mlp::k_make_samples, dim3((n + 255) / 256), dim3(256), 0, s, n, (unsigned long long)seed, ph,
+                       box[0], box[1], box[2], box[3], x.as<float>(), t.as<double>());
+    hipLaunchKernelGGL(mlp::k_target_stats, dim3(1), dim3(256), 0, s, n, t.as<double>(), stats.as<double>());
+    double st[6];
+    if (hipMemcpy(st, stats.p, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return LBM_EDEVICE;
+    // input ranges of the box: rho in [r0, r1]; e = c_v T - a rho in
+    // [c_v T0 - a r1, c_v T1 - a r0]
+    float nh[16] = {0};
+    nh[0] = (float)box[0];
+    nh[1] = (float)box[1];
+    nh[2] = (float)(prm->cv * box[2] - prm->a * box[1]);
+    nh[3] = (float)(prm->cv * box[3] - prm->a * box[0]);
+    for (int k = 0; k < 3; k++) {
+        nh[4 + 2 * k] = (float)st[2 * k];
+        nh[5 + 2 * k] = (float)(st[2 * k + 1] > 0 ? st[2 * k + 1] : 1.0);
+    }
+    if (hipMemcpy(norm.p, nh, sizeof(float) * 16, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P.p, host_params, sizeof(float) * mlp::NP, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(m.p, 0, sizeof(float) * mlp::NP) != hipSuccess ||
+        hipMemset(v.p, 0, sizeof(float) * mlp::NP) != hipSuccess)
+        return LBM_EDEVICE;
+    hipLaunchKernelGGL(mlp::k_normalise_samples, dim3((n + 255) / 256), dim3(256), 0, s, n, x.as<float>(),
+                       t.as<double>(), norm.as<float>(), xn.as<float>(), tn.as<float>());
+    long long it = 0;
+    const long long total = (long long)epochs * nbat;
+    for (int ep = 0; ep < epochs; ep++) {
+        if (ep == epochs - 1 && hipMemset(lacc.p, 0, sizeof(double)) != hipSuccess) return LBM_EDEVICE;
+        for (int bi = 0; bi < nbat; bi++, it++) {
+            const float *xb = xn.as<float>() + 2LL * bi * batch;
+            const float *tb = tn.as<float>() + 3LL * bi * batch;
+            int rc = loss_grad_impl(P.as<float>(), xb, tb, batch, grad.as<float>(), loss.as<float>(), precision, s,
+                                    gpart.as<float>(), lpart.as<float>());
+            if (rc) return rc;
+            if (ep == epochs - 1)
+                hipLaunchKernelGGL(mlp::k_accumulate_loss, dim3(1), dim3(64), 0, s, loss.as<float>(), lacc.as<double>());
+            const double lr_t = 0.5 * lr * (1.0 + cos(M_PI * (double)it / (double)total));  // cosine decay
+            const double t1 = (double)(it + 1);
+            hipLaunchKernelGGL(mlp::k_adam, dim3((mlp::NP + 255) / 256), dim3(256), 0, s, P.as<float>(),
+                               grad.as<float>(), m.as<float>(), v.as<float>(), (float)lr_t,
+                               (float)(1.0 - pow(0.9, t1)), (float)(1.0 - pow(0.999, t1)));
+        }
+    }
+    if (lbm_note(hipGetLastError())) return LBM_EDEVICE;
+    double la = 0;
+    if (hipMemcpy(host_params, P.p, sizeof(float) * mlp::NP, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(&la, lacc.p, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return LBM_EDEVICE;
+    std::memcpy(host_norm, nh, sizeof(float) * LBM_MLP_NNORM);
+    if (host_loss) *host_loss = la / nbat;
+    return LBM_OK;
+}
+
+int lbm_mlp_set(lbm_ctx *c, const float *host_params, const float *host_norm) {
+    if (!c || !host_params || !host_norm) return LBM_EINVAL;
+    if (c->p.eos != LBM_EOS_MLP) return LBM_EINVAL;
+    if (hipMemcpyAsync(c->mlp_params, host_params, sizeof(float) * LBM_MLP_NPARAMS, hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->mlp_norm, host_norm, sizeof(float) * LBM_MLP_NNORM, hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return LBM_EDEVICE;
+    c->mlp_ready = true;
+    return LBM_OK;
+}
+
+int lbm_mlp_stats(lbm_ctx *c, double *frac) {
+    if (!c || !frac) return LBM_EINVAL;
+    unsigned long long h[2];
+    if (hipMemcpyAsync(h, c->mlp_counters, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return LBM_EDEVICE;
+    *frac = h[1] ? (double)h[0] / (double)h[1] : 0.0;
+    if (hipMemsetAsync(c->mlp_counters, 0, sizeof(h), c->stream) != hipSuccess) return LBM_EDEVICE;
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,300 @@
+"""ctypes binding of ``liblbm_hip.so`` (C ABI in ``include/lbm.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels.
+Device arrays are torch CUDA tensors (PyTorch supplies device memory and the
+stream); host numpy inputs are copied to the device first.  A missing or
+unloadable library raises immediately -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm_hip.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ENAN, LBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
+STORAGE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+EOS = {"vdw": 0, "mlp": 1}
+MLP_BF16, MLP_F32 = 0, 1
+MLP_NPARAMS, MLP_NNORM = 4547, 10
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, what):
+        detail = load().lbm_last_error().decode() if status in (LBM_EDEVICE, LBM_ENOMEM) else ""
+        super().__init__(f"{what}: {strerror(status)} ({status}) {detail}".rstrip())
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("bc", ctypes.c_int * 3),
+                ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double), ("cv", ctypes.c_double),
+                ("mu", ctypes.c_double), ("eta", ctypes.c_double), ("k", ctypes.c_double),
+                ("kappa", ctypes.c_double),
+                ("storage", ctypes.c_int), ("eos", ctypes.c_int), ("mlp_tol", ctypes.c_double),
+                ("ref_rho", ctypes.c_double), ("ref_T", ctypes.c_double), ("stream", ctypes.c_void_p)]
+
+
+_lib = None
+_VP, _DP, _FP = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)
+
+
+def load():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    PP = ctypes.POINTER(_Params)
+    sig = {
+        "lbm_create": ([PP, ctypes.POINTER(_VP)], ctypes.c_int),
+        "lbm_destroy": ([_VP], None),
+        "lbm_init": ([_VP, _VP, _VP, _VP], ctypes.c_int),
+        "lbm_step": ([_VP, ctypes.c_int], ctypes.c_int),
+        "lbm_moments": ([_VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+        "lbm_get_populations": ([_VP, _VP, _VP], ctypes.c_int),
+        "lbm_set_populations": ([_VP, _VP, _VP], ctypes.c_int),
+        "lbm_conservation": ([_VP, _DP], ctypes.c_int),
+        "lbm_synchronize": ([_VP], ctypes.c_int),
+        "lbm_bytes_per_cell": ([_VP], ctypes.c_double),
+        "lbm_step_timed": ([_VP, ctypes.c_int, _DP, ctypes.c_int], ctypes.c_int),
+        "lbm_kernel_name": ([ctypes.c_int], ctypes.c_char_p),
+        "lbm_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "lbm_last_error": ([], ctypes.c_char_p),
+        "lbm_mlp_train": ([PP, _DP, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                           ctypes.c_int, _FP, _FP, _DP], ctypes.c_int),
+        "lbm_mlp_set": ([_VP, _FP, _FP], ctypes.c_int),
+        "lbm_mlp_stats": ([_VP, _DP], ctypes.c_int),
+        "lbm_mlp_forward": ([_VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP], ctypes.c_int),
+        "lbm_mlp_loss_grad": ([_VP, _VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
+        "lbm_codec_encode": ([ctypes.c_int, _VP, _VP, _VP, ctypes.c_int64, _VP], ctypes.c_int),
+        "lbm_codec_decode": ([ctypes.c_int, _VP, _VP, _VP, ctypes.c_int64, _VP], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    return load().lbm_strerror(int(status)).decode()
+
+
+def _check(status, what):
+    if status != LBM_OK:
+        raise LbmError(status, what)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(arr, dtype, n=None):
+    """Contiguous CUDA tensor of the given torch dtype (copies host arrays)."""
+    torch = _torch()
+    if isinstance(arr, torch.Tensor):
+        t = arr.to(device="cuda", dtype=dtype).contiguous()
+    else:
+        t = torch.as_tensor(np.ascontiguousarray(arr)).to(device="cuda", dtype=dtype).contiguous()
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} values, got {t.numel()}")
+    return t
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Lattice:
+    """One lattice Boltzmann context (lbm_create ... lbm_destroy)."""
+
+    def __init__(self, lattice, shape, bc=(0, 0, 0), a=3.0 / 49.0, b=2.0 / 21.0, R=1.0, cv=2.5, mu=0.05,
+                 eta=0.05, k=None, kappa=0.01, storage="f32", eos="vdw", mlp_tol=1e-6, ref_rho=0.0, ref_T=0.0,
+                 stream=None):
+        L = load()
+        self.D = int(lattice)
+        nx, ny = int(shape[0]), int(shape[1])
+        nz = int(shape[2]) if self.D == 3 else 1
+        self.shape = (nx, ny, nz)
+        self.N = nx * ny * nz
+        self.Q = 9 if self.D == 2 else 27
+        p = _Params()
+        p.lattice, p.nx, p.ny, p.nz = self.D, nx, ny, nz
+        for i in range(3):
+            p.bc[i] = int(bc[i])
+        p.a, p.b, p.R, p.cv = a, b, R, cv
+        p.mu, p.eta = mu, eta
+        p.k = mu * (cv + R) if k is None else k
+        p.kappa = kappa
+        p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        p.eos = EOS[eos] if isinstance(eos, str) else int(eos)
+        p.mlp_tol = mlp_tol
+        p.ref_rho, p.ref_T = ref_rho, ref_T
+        self._stream = stream
+        p.stream = _stream_ptr(stream).value if _torch().cuda.is_available() else None
+        self.params = p
+        h = _VP()
+        _check(L.lbm_create(ctypes.byref(p), ctypes.byref(h)), "lbm_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- the ABI calls -----------------------------------------------------
+    def init(self, rho, u, T):
+        torch = _torch()
+        r = _dev(rho, torch.float64, self.N)
+        uu = _dev(u, torch.float64, self.D * self.N)
+        t = _dev(T, torch.float64, self.N)
+        _check(load().lbm_init(self._h, _ptr(r), _ptr(uu), _ptr(t)), "lbm_init")
+        self._keep = (r, uu, t)  # alive until the stream has consumed them
+        return self
+
+    def step(self, n=1):
+        _check(load().lbm_step(self._h, int(n)), "lbm_step")
+        return self
+
+    def step_timed(self, n):
+        """Average per-launch duration (ms) of each kernel of the step over n steps."""
+        out = (ctypes.c_double * 8)()
+        _check(load().lbm_step_timed(self._h, int(n), out, 8), "lbm_step_timed")
+        return {load().lbm_kernel_name(k).decode(): out[k] for k in range(8) if load().lbm_kernel_name(k)}
+
+    def moments(self):
+        torch = _torch()
+        out = {k: torch.empty(self.N * (self.D if k == "u" else 1), dtype=torch.float64, device="cuda")
+               for k in ("rho", "u", "T", "P")}
+        _check(load().lbm_moments(self._h, _ptr(out["rho"]), _ptr(out["u"]), _ptr(out["T"]), _ptr(out["P"])),
+               "lbm_moments")
+        return out
+
+    def get_populations(self):
+        torch = _torch()
+        f = torch.empty(self.Q * self.N, dtype=torch.float64, device="cuda")
+        g = torch.empty_like(f)
+        _check(load().lbm_get_populations(self._h, _ptr(f), _ptr(g)), "lbm_get_populations")
+        return f, g
+
+    def set_populations(self, f, g):
+        torch = _torch()
+        ft = _dev(f, torch.float64, self.Q * self.N)
+        gt = _dev(g, torch.float64, self.Q * self.N)
+        _check(load().lbm_set_populations(self._h, _ptr(ft), _ptr(gt)), "lbm_set_populations")
+        self._keep = (ft, gt)
+        return self
+
+    def conservation(self, raise_on_nan=True):
+        out = (ctypes.c_double * 6)()
+        rc = load().lbm_conservation(self._h, out)
+        if rc != LBM_OK and (rc != LBM_ENAN or raise_on_nan):
+            _check(rc, "lbm_conservation")
+        return np.array(out[: self.D + 3])
+
+    def synchronize(self):
+        _check(load().lbm_synchronize(self._h), "lbm_synchronize")
+
+    @property
+    def bytes_per_cell(self):
+        return load().lbm_bytes_per_cell(self._h)
+
+    def mlp_set(self, params, norm):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        n = np.ascontiguousarray(norm, dtype=np.float32)
+        assert p.size == MLP_NPARAMS and n.size == MLP_NNORM
+        _check(load().lbm_mlp_set(self._h, p.ctypes.data_as(_FP), n.ctypes.data_as(_FP)), "lbm_mlp_set")
+
+    def mlp_stats(self):
+        v = ctypes.c_double()
+        _check(load().lbm_mlp_stats(self._h, ctypes.byref(v)), "lbm_mlp_stats")
+        return v.value
+
+
+def mlp_train(box, n_samples, seed, epochs, batch, lr, params0, precision=MLP_BF16, a=3.0 / 49.0, b=2.0 / 21.0,
+              R=1.0, cv=2.5):
+    """lbm_mlp_train: returns (params[4547], norm[10], final_loss)."""
+    p = _Params()
+    p.lattice, p.nx, p.ny, p.nz = 2, 1, 1, 1
+    p.a, p.b, p.R, p.cv = a, b, R, cv
+    p.mu = 1.0
+    bx = np.ascontiguousarray(box, dtype=np.float64)
+    prm = np.ascontiguousarray(params0, dtype=np.float32).copy()
+    norm = np.zeros(MLP_NNORM, dtype=np.float32)
+    loss = ctypes.c_double()
+    _check(load().lbm_mlp_train(ctypes.byref(p), bx.ctypes.data_as(_DP), int(n_samples), int(seed), int(epochs),
+                                int(batch), float(lr), int(precision), prm.ctypes.data_as(_FP),
+                                norm.ctypes.data_as(_FP), ctypes.byref(loss)), "lbm_mlp_train")
+    return prm, norm, loss.value
+
+
+def mlp_forward(params, norm, x, precision=MLP_BF16, stream=None):
+    torch = _torch()
+    pt = _dev(params, torch.float32, MLP_NPARAMS)
+    nt = _dev(norm, torch.float32, MLP_NNORM)
+    xt = _dev(x, torch.float32)
+    B = xt.numel() // 2
+    y = torch.empty(3 * B, dtype=torch.float32, device="cuda")
+    _check(load().lbm_mlp_forward(_ptr(pt), _ptr(nt), _ptr(xt), _ptr(y), B, int(precision), _stream_ptr(stream)),
+           "lbm_mlp_forward")
+    return y.view(B, 3)
+
+
+def mlp_loss_grad(params, xn, tn, precision=MLP_BF16, stream=None):
+    torch = _torch()
+    pt = _dev(params, torch.float32, MLP_NPARAMS)
+    xt = _dev(xn, torch.float32)
+    tt = _dev(tn, torch.float32)
+    B = xt.numel() // 2
+    grad = torch.empty(MLP_NPARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(load().lbm_mlp_loss_grad(_ptr(pt), _ptr(xt), _ptr(tt), B, _ptr(grad), _ptr(loss), int(precision),
+                                    _stream_ptr(stream)), "lbm_mlp_loss_grad")
+    return loss, grad
+
+
+def codec_encode(kind, x, ref, stream=None):
+    torch = _torch()
+    xt = _dev(x, torch.float32)
+    rt = _dev(ref, torch.float32, xt.numel())
+    out = torch.empty(xt.numel(), dtype=torch.int16, device="cuda")
+    _check(load().lbm_codec_encode(STORAGE[kind], _ptr(xt), _ptr(rt), _ptr(out), xt.numel(), _stream_ptr(stream)),
+           "lbm_codec_encode")
+    return out
+
+
+def codec_decode(kind, code, ref, stream=None):
+    torch = _torch()
+    ct = _dev(code, torch.int16)
+    rt = _dev(ref, torch.float32, ct.numel())
+    out = torch.empty(ct.numel(), dtype=torch.float32, device="cuda")
+    _check(load().lbm_codec_decode(STORAGE[kind], _ptr(ct), _ptr(rt), _ptr(out), ct.numel(), _stream_ptr(stream)),
+           "lbm_codec_decode")
+    return out

@@ -1,0 +1,160 @@
+"""GPU checks of the two changed forms of the method.
+
+Surrogate EOS: the library's forward pass and loss gradient against the FP64
+oracle (FP32 path tight, BF16-MFMA path to the bound its rounding allows),
+GPU training reaching a small held-out error against the van der Waals closed
+forms, and the step with the surrogate plus residual check and Newton
+fallback.  Precision: BF16/FP16 deviation storage with FP32 arithmetic
+against the FP64 oracle, error stated per field.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as om
+from oracle import thermo as th
+from paper_2510_14712_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+ST = inputs.states()
+CONST = ST["constants"]
+KW = dict(a=CONST["a"], b=CONST["b"], R=CONST["R"], cv=CONST["cv"], mu=CONST["mu"], eta=CONST["eta"],
+          k=CONST["k"], kappa=CONST["kappa"])
+A, B, R, CV = CONST["a"], CONST["b"], CONST["R"], CONST["cv"]
+RHOC, TC = ST["critical"]["rho"], ST["critical"]["T"]
+BOX = ST["shock_drop_3d"]["mlp_box"]
+
+
+def _lbm():
+    from paper_2510_14712_amd import lbm
+    lbm.load()
+    return lbm
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(x, ref):
+    return np.linalg.norm(np.asarray(x, np.float64) - ref) / max(np.linalg.norm(ref), 1e-300)
+
+
+def _norm_vec():
+    r0, r1 = BOX["rho"]
+    T0, T1 = BOX["T"]
+    return np.array([r0, r1, CV * T0 - A * r1, CV * T1 - A * r0, 0.2, 0.03, 0.3, 0.2, 0.3, 0.3], np.float32)
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 2e-5), (0, 3e-2)])
+def test_forward_matches_oracle(precision, tol):
+    lbm = _lbm()
+    params = inputs.mlp_params(21).astype(np.float32)
+    norm = _norm_vec()
+    rho, T = inputs.mlp_samples(1000, 22, BOX["rho"], BOX["T"])   # 1000: ragged last wave
+    x = np.stack([rho, CV * T - A * rho], 1).astype(np.float32)
+    _say(f"case mlp forward precision={precision}")
+    y = lbm.mlp_forward(params, norm, x, precision=precision).cpu().numpy()
+    xn = om.normalize_inputs(x.astype(np.float64), norm[[0, 2]], norm[[1, 3]])
+    yh, _ = om.forward(params.astype(np.float64), xn)
+    ref = yh * norm[[5, 7, 9]] + norm[[4, 6, 8]]
+    for k in range(3):
+        e = np.max(np.abs(y[:, k] - ref[:, k])) / (np.abs(yh[:, k]).max() * norm[5 + 2 * k])
+        _say(f"  output {k}: max err / scale {e:.2e}")
+        assert e < tol
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 1e-4), (0, 5e-2)])
+def test_loss_grad_matches_oracle(precision, tol):
+    lbm = _lbm()
+    params = inputs.mlp_params(31, scale=1.3).astype(np.float32)
+    rng = np.random.default_rng(32)
+    Bn = 512
+    xn = rng.uniform(-1, 1, (Bn, 2)).astype(np.float32)
+    tn = rng.normal(size=(Bn, 3)).astype(np.float32)
+    _say(f"case mlp loss_grad precision={precision}")
+    loss, grad = lbm.mlp_loss_grad(params, xn, tn, precision=precision)
+    L_ref, g_ref = om.loss_grad(params.astype(np.float64), xn.astype(np.float64), tn.astype(np.float64))
+    assert abs(float(loss.cpu()) / L_ref - 1) < tol
+    e = rel_l2(grad.cpu().numpy(), g_ref)
+    _say(f"  gradient rel-L2 {e:.2e}")
+    assert e < tol
+    # every parameter block receives a gradient
+    g = grad.cpu().numpy()
+    for lo, hi in ((0, 128), (128, 192), (192, 4288), (4288, 4352), (4352, 4544), (4544, 4547)):
+        assert np.abs(g[lo:hi]).max() > 0
+
+
+def _train(precision=0, n=131072, epochs=40, batch=4096, seed=4):
+    lbm = _lbm()
+    p0 = inputs.mlp_params(seed).astype(np.float32)
+    box = [BOX["rho"][0], BOX["rho"][1], BOX["T"][0], BOX["T"][1]]
+    return lbm.mlp_train(box, n, seed, epochs, batch, 3e-3, p0, precision=precision, a=A, b=B, R=R, cv=CV)
+
+
+def test_training_reduces_heldout_error():
+    lbm = _lbm()
+    _say("case mlp training bf16")
+    params, norm, loss = _train()
+    _say(f"  final loss {loss:.3e}")
+    assert loss < 2e-3
+    rho, T = inputs.mlp_samples(4096, 99, BOX["rho"], BOX["T"])
+    x = np.stack([rho, CV * T - A * rho], 1).astype(np.float32)
+    y = lbm.mlp_forward(params, norm, x).cpu().numpy().astype(np.float64)
+    errT = np.abs(y[:, 0] - T) / T
+    errP = np.abs(y[:, 1] - th.pressure(rho, T, A, B, R)) / np.abs(th.pressure(rho, T, A, B, R)).max()
+    _say(f"  held-out: T max rel {errT.max():.2e} mean {errT.mean():.2e}; P max/scale {errP.max():.2e}")
+    assert errT.mean() < 1e-2 and errP.mean() < 2e-2
+    # the oracle's forward pass on the trained weights agrees with the GPU's
+    xn = om.normalize_inputs(x.astype(np.float64), norm[[0, 2]], norm[[1, 3]])
+    yh, _ = om.forward(params.astype(np.float64), xn)
+    yref = yh * norm[[5, 7, 9]] + norm[[4, 6, 8]]
+    assert np.max(np.abs(y[:, 0] - yref[:, 0]) / T) < 5e-2
+
+
+def test_step_with_surrogate_and_fallback():
+    """Taylor-Green 40x32x24, FP32 storage, surrogate EOS with residual
+    threshold 1e-6: cells failing the check take the exact Newton step, so the
+    run matches the FP64 oracle to the FP32 bar."""
+    lbm = _lbm()
+    params, norm, _ = _train(epochs=10)
+    c = ST["tgv_3d_256"]
+    shape = (40, 32, 24)
+    rho, u, T = inputs.taylor_green(shape, c["seed"], c["rho0"], c["T0"], c["U0"], c["noise"])
+    _say("case step eos=mlp f32")
+    with lbm.Lattice(3, shape, storage="f32", eos="mlp", mlp_tol=1e-6, **KW) as lat:
+        lat.mlp_set(params, norm)
+        lat.init(rho, u, T).step(50)
+        mom = {k: v.cpu().numpy() for k, v in lat.moments().items()}
+        frac = lat.mlp_stats()
+    p = oracle.Params(3, shape, **KW)
+    fr, gr = oracle.run(p, *oracle.init(p, rho, u, T), 50)
+    ref = oracle.fields(p, fr, gr)
+    _say(f"  fallback fraction {frac:.4f}")
+    assert 0.0 <= frac <= 1.0
+    for k in ("rho", "u", "T"):
+        e = rel_l2(mom[k], ref[k])
+        _say(f"  {k} rel-L2 {e:.2e}")
+        assert e <= 1e-5
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_deviation_storage_error_per_field(storage):
+    lbm = _lbm()
+    c = ST["tgv_3d_256"]
+    shape = (40, 32, 24)
+    steps = 200
+    rho, u, T = inputs.taylor_green(shape, c["seed"], c["rho0"], c["T0"], c["U0"], c["noise"])
+    _say(f"case deviation storage {storage}, {steps} steps")
+    with lbm.Lattice(3, shape, storage=storage, ref_rho=c["rho0"], ref_T=c["T0"], **KW) as lat:
+        lat.init(rho, u, T).step(steps)
+        mom = {k: v.cpu().numpy() for k, v in lat.moments().items()}
+    p = oracle.Params(3, shape, **KW)
+    fr, gr = oracle.run(p, *oracle.init(p, rho, u, T), steps)
+    ref = oracle.fields(p, fr, gr)
+    errs = {k: rel_l2(mom[k], ref[k]) for k in ("rho", "u", "T")}
+    _say(f"  per-field rel-L2 {errs}")
+    assert errs["rho"] <= 1e-3

@@ -1,0 +1,254 @@
+"""GPU parity of the HIP step against the FP64 oracle (called through the C ABI).
+
+Bars (fixed by the method's targets): FP64 storage and arithmetic match the
+oracle to relative L2 <= 1e-12 per field after 200 steps; FP32 to <= 1e-5.
+Element-wise comparisons use small ragged lattices that span several thread
+blocks with a partial last block; full-size workloads are checked on sampled
+cells against the oracle evaluated on a local patch.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_14712_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+ST = inputs.states()
+CONST = ST["constants"]
+KW = dict(a=CONST["a"], b=CONST["b"], R=CONST["R"], cv=CONST["cv"], mu=CONST["mu"], eta=CONST["eta"],
+          k=CONST["k"], kappa=CONST["kappa"])
+RHOC, TC = ST["critical"]["rho"], ST["critical"]["T"]
+
+
+def _lbm():
+    import torch
+    from paper_2510_14712_amd import lbm
+    assert torch.cuda.is_available()
+    lbm.load()
+    return lbm
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(x, ref):
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return np.linalg.norm(x - ref) / max(np.linalg.norm(ref), 1e-300)
+
+
+def _run_both(D, shape, bc, rho, u, T, steps, storage="f64", kw=None):
+    lbm = _lbm()
+    kw = dict(KW, **(kw or {}))
+    _say(f"case D={D} shape={shape} bc={bc} storage={storage} steps={steps}")
+    with lbm.Lattice(D, shape, bc=bc, storage=storage, **kw) as lat:
+        lat.init(rho, u, T).step(steps)
+        f, g = (t.cpu().numpy() for t in lat.get_populations())
+        mom = {k: v.cpu().numpy() for k, v in lat.moments().items()}
+    p = oracle.Params(D, shape, bc=bc, **kw)
+    fr, gr = oracle.run(p, *oracle.init(p, rho, u, T), steps)
+    ref = oracle.fields(p, fr, gr)
+    return (f, g, mom), (fr, gr, ref)
+
+
+@pytest.mark.parametrize("D,shape,bc", [(2, (37, 5), (1, 0, 0)), (3, (19, 6, 5), (0, 1, 0))])
+def test_init_matches_oracle(D, shape, bc):
+    rho, u, T = inputs.random_state(D, shape, 3, RHOC, 1.1 * TC, drho=0.05, du=0.1, dT=0.03)
+    (f, g, _), (fr, gr, _) = _run_both(D, shape, bc, rho, u, T, 0)
+    assert np.max(np.abs(f - fr)) <= 1e-14 * np.abs(fr).max()
+    assert np.max(np.abs(g - gr)) <= 1e-14 * np.abs(gr).max()
+
+
+@pytest.mark.parametrize("D,shape,bc,steps", [
+    (2, (300, 37), (1, 1, 0), 25),
+    (2, (513, 3), (0, 0, 0), 25),
+    (3, (70, 9, 7), (1, 0, 1), 8),
+    (3, (33, 12, 10), (0, 0, 0), 8),
+])
+def test_fp64_elementwise(D, shape, bc, steps):
+    rho, u, T = inputs.random_state(D, shape, 11, RHOC, 1.1 * TC, drho=0.04, du=0.08, dT=0.03, white=0.002)
+    (f, g, mom), (fr, gr, ref) = _run_both(D, shape, bc, rho, u, T, steps)
+    assert np.max(np.abs(f - fr)) <= 1e-12 * np.abs(fr).max()
+    assert np.max(np.abs(g - gr)) <= 1e-12 * np.abs(gr).max()
+    for k in ("rho", "u", "T", "P"):
+        assert rel_l2(mom[k], ref[k]) <= 1e-12, k
+
+
+@pytest.mark.parametrize("variant", ["vdw", "ideal"])
+def test_shock_tube_fp64_200_steps(variant):
+    """512x4 D2Q9 shock tube at T = 0.9 T_c, rho = 0.9 / 0.3 rho_c; the ideal
+    variant sets a = b = kappa = 0."""
+    c = ST["shock_tube_2d"]
+    shape = tuple(c["shape"])
+    rho, u, T = inputs.shock_tube(shape, c["rho_left"], c["rho_right"], c["T"])
+    kw = dict(c["ideal"]) if variant == "ideal" else {}
+    (f, g, mom), (fr, gr, ref) = _run_both(2, shape, tuple(c["bc"]), rho, u, T, 200, kw=kw)
+    for k in ("rho", "u", "T", "P"):
+        assert rel_l2(mom[k], ref[k]) <= 1e-12, (k, rel_l2(mom[k], ref[k]))
+    assert rel_l2(f, fr) <= 1e-12 and rel_l2(g, gr) <= 1e-12
+
+
+def test_taylor_green_fp32_200_steps():
+    """Near-critical Taylor-Green vortex (rho_c, 1.1 T_c, Ma 0.5, 1 % noise) on
+    a reduced 40x32x24 periodic lattice, FP32 vs FP64 oracle."""
+    c = ST["tgv_3d_256"]
+    shape = (40, 32, 24)
+    rho, u, T = inputs.taylor_green(shape, c["seed"], c["rho0"], c["T0"], c["U0"], c["noise"])
+    (f, g, mom), (fr, gr, ref) = _run_both(3, shape, (0, 0, 0), rho, u, T, 200, storage="f32")
+    for k in ("rho", "u", "T"):
+        e = rel_l2(mom[k], ref[k])
+        _say(f"  TGV FP32 {k} rel-L2 {e:.3e}")
+        assert e <= 1e-5, (k, e)
+
+
+def test_shock_drop_2d_fp32():
+    """Shock-drop geometry (Maxwell drop at 0.85 T_c, Ma 1.47 Rankine-Hugoniot
+    shock) reduced to 192x96.  The liquid's lattice checkerboard mode grows
+    (see the stability test of the oracle), so parity is taken at 30 steps."""
+    c = ST["shock_drop_2d"]
+    shape = (192, 96)
+    rho, u, T = inputs.shock_drop(shape, (70, 48), 20, c["width"], c["rho_liquid"], c["rho_vapour"], c["T1"],
+                                  20, c["rho2"], c["T2"], c["u2"])
+    (f, g, mom), (fr, gr, ref) = _run_both(2, shape, (1, 0, 0), rho, u, T, 30, storage="f32")
+    for k in ("rho", "u", "T"):
+        e = rel_l2(mom[k], ref[k])
+        _say(f"  shock-drop FP32 {k} rel-L2 {e:.3e}")
+        assert e <= 1e-5, (k, e)
+
+
+@pytest.mark.parametrize("D,shape", [(2, (1, 1)), (2, (2, 1)), (3, (1, 1, 1)), (3, (3, 1, 2)), (2, (257, 1))])
+def test_degenerate_sizes(D, shape):
+    rho, u, T = inputs.random_state(D, shape, 5, RHOC, 1.1 * TC, drho=0.02, du=0.05, dT=0.02)
+    for bc in ((0, 0, 0), (1, 1, 1)):
+        (f, g, _), (fr, gr, _) = _run_both(D, shape, bc, rho, u, T, 6)
+        assert np.max(np.abs(f - fr)) <= 1e-12 * np.abs(fr).max()
+        assert np.max(np.abs(g - gr)) <= 1e-12 * np.abs(gr).max()
+
+
+def test_uniform_state_fixed_point():
+    lbm = _lbm()
+    shape = (67, 5, 4)
+    N = int(np.prod(shape))
+    u = np.repeat([0.11, -0.07, 0.05], N)
+    with lbm.Lattice(3, shape, storage="f64", **KW) as lat:
+        lat.init(np.full(N, 2.7), u, np.full(N, 1.05 * TC))
+        f0, g0 = (t.cpu().numpy() for t in lat.get_populations())
+        lat.step(10)
+        f1, g1 = (t.cpu().numpy() for t in lat.get_populations())
+    assert np.max(np.abs(f1 - f0)) <= 1e-14 * 2.7
+    assert np.max(np.abs(g1 - g0)) <= 1e-14 * np.abs(g0).max()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_checkpoint_resume_bitwise(storage):
+    lbm = _lbm()
+    D, shape = 3, (21, 10, 6)
+    rho, u, T = inputs.random_state(D, shape, 8, RHOC, 1.1 * TC)
+    with lbm.Lattice(D, shape, storage=storage, **KW) as a, lbm.Lattice(D, shape, storage=storage, **KW) as b:
+        a.init(rho, u, T).step(5)
+        f, g = a.get_populations()
+        b.set_populations(f, g)
+        a.step(7)
+        b.step(7)
+        fa, ga = a.get_populations()
+        fb, gb = b.get_populations()
+        assert bool((fa == fb).all()) and bool((ga == gb).all())
+
+
+def test_conservation_sums():
+    lbm = _lbm()
+    D, shape = 3, (24, 10, 8)
+    rho, u, T = inputs.random_state(D, shape, 9, RHOC, 1.1 * TC, drho=0.03, du=0.06, dT=0.02)
+    kw = dict(KW)
+    with lbm.Lattice(D, shape, storage="f64", **kw) as lat:
+        lat.init(rho, u, T)
+        s0 = lat.conservation()
+        lat.step(30)
+        s1 = lat.conservation()
+    p = oracle.Params(D, shape, **kw)
+    f0, g0 = oracle.init(p, rho, u, T)
+    fl0 = oracle.fields(p, f0, g0)
+    assert s0[0] == pytest.approx(fl0["rho"].sum(), rel=1e-14)
+    mom0 = (fl0["rho"] * fl0["u"].reshape(D, -1)).sum(1)
+    np.testing.assert_allclose(s0[1:1 + D], mom0, rtol=0, atol=1e-12 * fl0["rho"].sum())
+    assert s0[D + 1] == pytest.approx(g0.sum(), rel=1e-14)
+    assert s0[D + 2] == 0
+    # periodic: mass and momentum conserved to round-off over 30 steps
+    assert abs(s1[0] - s0[0]) <= 1e-13 * s0[0]
+    assert np.max(np.abs(s1[1:1 + D] - s0[1:1 + D])) <= 1e-12 * s0[0]
+
+
+def test_nonfinite_detected():
+    lbm = _lbm()
+    shape = (16, 8)
+    N = 128
+    rho = np.full(N, RHOC)
+    rho[37] = np.nan
+    with lbm.Lattice(2, shape, storage="f64", **KW) as lat:
+        lat.init(rho, np.zeros(2 * N), np.full(N, 1.1 * TC))
+        s = lat.conservation(raise_on_nan=False)
+        assert s[2 + 2] >= 1
+        with pytest.raises(lbm.LbmError):
+            lat.conservation()
+
+
+@pytest.mark.parametrize("kind", ["bf16", "f16"])
+def test_codec_bitwise(kind):
+    from oracle import mlp as om
+    lbm = _lbm()
+    rng = np.random.default_rng(17)
+    n = 100_003
+    ref = rng.uniform(0.0, 3.0, n).astype(np.float32)
+    x = (ref + rng.normal(size=n) * 10.0 ** rng.uniform(-8, 0, n)).astype(np.float32)
+    x[:4] = [np.inf, -np.inf, 0.0, -0.0]
+    ref[:4] = 0.0
+    code = lbm.codec_encode(kind, x, ref).cpu().numpy().view(np.uint16)
+    expect = om.encode_deviation(x, ref, kind)
+    np.testing.assert_array_equal(code, expect)
+    back = lbm.codec_decode(kind, code.view(np.int16), ref).cpu().numpy()
+    np.testing.assert_array_equal(back.view(np.uint32), om.decode_deviation(expect, ref, kind).view(np.uint32))
+
+
+def test_full_size_tgv_256_sampled_cells():
+    """256^3 Taylor-Green, FP32, one step in the benchmark's launch shape;
+    24 sampled interior cells checked against the oracle on local patches."""
+    import torch
+    lbm = _lbm()
+    c = ST["tgv_3d_256"]
+    shape = tuple(c["shape"])
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    rho, u, T = inputs.taylor_green(shape, c["seed"], c["rho0"], c["T0"], c["U0"], c["noise"])
+    rng = np.random.default_rng(1)
+    cells = [tuple(rng.integers(5, n - 5) for n in shape) for _ in range(24)]
+    _say("case full-size TGV 256^3 f32, 1 step")
+    with lbm.Lattice(3, shape, storage="f32", **KW) as lat:
+        lat.init(rho, u, T)
+        f0, g0 = lat.get_populations()
+        # gather patches before stepping
+        patches = []
+        for (x, y, z) in cells:
+            R = 4
+            xs, ys, zs = (torch.arange(-R, R + 1, device="cuda") + v for v in (x, y, z))
+            Z, Y, X = torch.meshgrid(zs, ys, xs, indexing="ij")
+            idx = (X + nx * (Y + ny * Z)).reshape(-1)
+            patches.append((f0.view(27, N)[:, idx].cpu().numpy(), g0.view(27, N)[:, idx].cpu().numpy()))
+        del f0, g0
+        lat.step(1)
+        f1, g1 = lat.get_populations()
+        cvec = oracle.velocities(3)
+        for (x, y, z), (fp, gp) in zip(cells, patches):
+            p = oracle.Params(3, (9, 9, 9), **KW)
+            fo, go, _ = oracle.collide(p, np.ascontiguousarray(fp).reshape(-1), np.ascontiguousarray(gp).reshape(-1))
+            mid = (729 - 1) // 2
+            for i in range(27):
+                d = (x + cvec[i, 0]) + nx * ((y + cvec[i, 1]) + ny * (z + cvec[i, 2]))
+                fg = float(f1[i * N + d])
+                gg = float(g1[i * N + d])
+                assert abs(fg - fo[i * 729 + mid]) <= 2e-6 * abs(fo).max()
+                assert abs(gg - go[i * 729 + mid]) <= 2e-6 * abs(go).max()
