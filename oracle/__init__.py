@@ -41,7 +41,7 @@ class _Params(ctypes.Structure):
                 ("nz", ctypes.c_int), ("bc", ctypes.c_int * 3),
                 ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double),
                 ("cv", ctypes.c_double), ("mu", ctypes.c_double), ("eta", ctypes.c_double),
-                ("k", ctypes.c_double), ("kappa", ctypes.c_double)]
+                ("k", ctypes.c_double), ("kappa", ctypes.c_double), ("upwind_eps", ctypes.c_double)]
 
 
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -87,6 +87,12 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(_DP)
 
 
+# |u| at or below this takes the central average in the upwind-biased
+# derivative of the Galilean correction (the tie sgn(0) = 0 widened to a
+# round-off dead zone)
+UPWIND_EPS = 1e-6
+
+
 def num_vel(D: int) -> int:
     return 9 if D == 2 else 27
 
@@ -107,7 +113,7 @@ class Params:
     """Lattice and physical parameters (lattice units)."""
 
     def __init__(self, D, shape, bc=(0, 0, 0), a=3.0 / 49.0, b=2.0 / 21.0, R=1.0, cv=2.5,
-                 mu=0.05, eta=0.05, k=None, kappa=0.01):
+                 mu=0.05, eta=0.05, k=None, kappa=0.01, upwind_eps=UPWIND_EPS):
         nx, ny = shape[0], shape[1]
         nz = shape[2] if D == 3 else 1
         self.D, self.nx, self.ny, self.nz = D, nx, ny, nz
@@ -116,6 +122,7 @@ class Params:
         self.mu, self.eta = mu, eta
         self.k = mu * (cv + R) if k is None else k
         self.kappa = kappa
+        self.upwind_eps = upwind_eps
 
     @property
     def N(self):
@@ -132,6 +139,7 @@ class Params:
             s.bc[i] = int(self.bc[i])
         s.a, s.b, s.R, s.cv = self.a, self.b, self.R, self.cv
         s.mu, s.eta, s.k, s.kappa = self.mu, self.eta, self.k, self.kappa
+        s.upwind_eps = self.upwind_eps
         return s
 
 

@@ -309,8 +309,10 @@ static void export_fields(const oracle_params *p, const work_fields *w, oracle_f
 #undef CP
 }
 
-/* sgn with sgn(0) = 0 (reading: a zero velocity takes the central average) */
-static double sgn(double v) { return v > 0.0 ? 1.0 : (v < 0.0 ? -1.0 : 0.0); }
+/* sgn with a dead zone: |v| <= eps counts as zero, which takes the central
+ * average (reading of the tie sgn(0); the upwind switch is discontinuous at
+ * u = 0, so velocities at round-off level must not pick a side) */
+static double sgn(double v, double eps) { return v > eps ? 1.0 : (v < -eps ? -1.0 : 0.0); }
 
 /* ---------------------------------------------------------------------- */
 /* Collision (eqs. fLBGK, gLBGK with LBMeq, LBMstar, LBMeqG, LBMgstar)     */
@@ -335,7 +337,7 @@ static void collide_all(const oracle_params *p, const double *f, const double *g
             gT[a] = 0.5 * (w->T[xp] - w->T[xm]);
             /* upwind-biased derivative of Lambda_a by the sign of u_a at x,
              * then Phi_aa = -(1/rho) d_a Lambda_a (eq. correction) */
-            double s = sgn(u[a]);
+            double s = sgn(u[a], p->upwind_eps);
             double dL = 0.5 * (1.0 + s) * (w->Lam[a * N + x] - w->Lam[a * N + xm])
                       + 0.5 * (1.0 - s) * (w->Lam[a * N + xp] - w->Lam[a * N + x]);
             Phi[a] = -dL / rho;

@@ -32,6 +32,8 @@ typedef struct {
     double a, b, R, cv; /* van der Waals constants and isochoric heat */
     double mu, eta, k;  /* shear, bulk viscosity, thermal conductivity */
     double kappa;       /* capillarity coefficient */
+    double upwind_eps;  /* |u_a| <= upwind_eps takes the central average in the
+                           upwind-biased derivative of Lambda (sgn(u) = 0) */
 } oracle_params;
 
 /* Per-cell fields produced while evaluating one step (all length N or D*N). */
