@@ -121,6 +121,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="tgv512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="plain,surrogate", help="comma list of forms to time")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -128,6 +131,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        torch.cuda.set_device(0)
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "launches": 3}), flush=True)
+        return
     from paper_2510_14712_amd import inputs, lbm
     lbm.load()
     torch.cuda.set_device(0)
@@ -137,16 +149,24 @@ def main():
     shape, bc, fields, ref, desc = workload(args.workload, st)
     N = int(np.prod(shape))
 
+    forms = args.forms.split(",")
+    if "plain" in forms:
+        _p(f"plain FP32 form on {shape}")
+        plain = time_form(lbm, torch, shape, bc, fields, ref, kw, "f32", "vdw", args.steps, args.warmup)
+        _p(f"  {plain['mlups']:.0f} MLUPS, kernels {plain['kernel_ms']}")
+    if "surrogate" not in forms:
+        print(json.dumps({"forms": {"plain_fp32": plain}}), flush=True)
+        return
     _p("training the surrogate EOS on the GPU")
     params, norm, loss, t_train = train_surrogate(st, lbm)
     _p(f"  loss {loss:.3e} in {t_train:.1f} s")
-    _p(f"plain FP32 form on {shape}")
-    plain = time_form(lbm, torch, shape, bc, fields, ref, kw, "f32", "vdw", args.steps, args.warmup)
-    _p(f"  {plain['mlups']:.0f} MLUPS, kernels {plain['kernel_ms']}")
     _p("surrogate + BF16 deviation form")
     surr = time_form(lbm, torch, shape, bc, fields, ref, kw, "bf16", "mlp", args.steps, args.warmup,
                      mlp=(params, norm))
     _p(f"  {surr['mlups']:.0f} MLUPS, kernels {surr['kernel_ms']}, fallback {surr['fallback_fraction']}")
+    if "plain" not in forms:
+        print(json.dumps({"forms": {"surrogate_bf16": surr}}), flush=True)
+        return
 
     def roof(form):
         kms = form["kernel_ms"]

@@ -79,6 +79,9 @@ typedef struct {
     double ref_rho, ref_T;  /* reference state of the 16-bit storage forms */
     void *stream;           /* hipStream_t for all asynchronous work; NULL =
                                the null stream */
+    double upwind_eps;      /* |u_a| <= upwind_eps takes the central average in
+                               the upwind-biased derivative of Lambda_a (the
+                               tie sgn(0) = 0 widened to a round-off dead zone) */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx; /* opaque, library-owned */
@@ -130,11 +133,17 @@ int lbm_synchronize(lbm_ctx *ctx);
 /* Timed variant of lbm_step for measurement: runs n steps on the context's
  * stream with HIP events around every kernel launch and writes the average
  * duration in milliseconds of each kernel kind of the step to host_ms[k],
- * k < LBM_NUM_KERNELS (names from lbm_kernel_name).  Blocking.
- * Errors: as lbm_step; LBM_EINVAL when nslots < LBM_NUM_KERNELS. */
+ * k < LBM_NUM_KERNELS (names from lbm_kernel_name; unused slots get "" and
+ * 0).  Blocking.  Errors: as lbm_step; LBM_EINVAL when nslots <
+ * LBM_NUM_KERNELS. */
 #define LBM_NUM_KERNELS 4
 int lbm_step_timed(lbm_ctx *ctx, int n, double *host_ms, int nslots);
-const char *lbm_kernel_name(int kernel);
+const char *lbm_kernel_name(const lbm_ctx *ctx, int kernel);
+
+/* 1 when lbm_step runs the single-pass fused kernel (one read and one write
+ * of every population per step; periodic z or D = 2), 0 when it runs the
+ * four-kernel path (moments, Laplacian, fields, collide). */
+int lbm_is_fused(const lbm_ctx *ctx);
 
 /* Algorithmic HBM bytes moved per cell update by lbm_step (2 Q populations
  * read + 2 Q written, in the storage width) -- the traffic an ideal fused

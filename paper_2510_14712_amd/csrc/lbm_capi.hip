@@ -10,8 +10,8 @@
 #include <new>
 
 #include "lbm.h"
-#include "lbm_kernels.hpp"
 #include "lbm_internal.hpp"
+#include <type_traits>
 
 using namespace lbm;
 
@@ -147,6 +147,7 @@ template <class C> static Phys<C> make_phys(const lbm_params &p) {
     ph.inv_cv = (C)(1.0 / p.cv);
     ph.k_over_mu = (C)(p.k / p.mu);
     ph.eta_over_mu = (C)(p.eta / p.mu);
+    ph.sgn_eps = (C)p.upwind_eps;
     return ph;
 }
 
@@ -186,16 +187,66 @@ static void make_ref(const lbm_params &p, int D, RefPops &ref) {
 // ---------------------------------------------------------------------------
 // dispatch over (lattice, storage)
 // ---------------------------------------------------------------------------
+// tile of the fused step: FP64 uses a smaller tile to fit the LDS budget
+template <class S> using TileOf = typename std::conditional<std::is_same<S, StoreF64>::value, Tile<16, 8>, Tile<32, 8>>::type;
+
 template <int D, class S> struct Impl {
     using C = typename S::C;
     using T = typename S::T;
+    using TL = TileOf<S>;
 
-    static Fields<C> &fields(lbm_ctx *c);
+    // complete moments of the current state into the side channel; the wrap
+    // layers and all inbound slots of both buffers start at zero (slots on a
+    // zero-gradient wall are never written afterwards)
+    static int fused_prepare(lbm_ctx *c) {
+        if (!c->fused) return LBM_OK;
+        for (int s = 0; s < 2; s++) {
+            if (hipMemsetAsync(c->Mc[s], 0, c->mc_bytes, c->stream) != hipSuccess ||
+                hipMemsetAsync(c->IN[s], 0, c->in_bytes, c->stream) != hipSuccess)
+                return lbm_note(hipGetLastError());
+        }
+        hipLaunchKernelGGL((k_fused_moments<D, S, TL>), cell_grid(c), dim3(BX), 0, c->stream, c->grid, c->ref,
+                           c->nlayer, (const T *)c->f[c->cur], (const T *)c->g[c->cur], (C *)c->Mc[c->cur]);
+        return last_launch();
+    }
+    static void fused_launch(lbm_ctx *c) {
+        FusedArgs<C, T> a;
+        a.g = c->grid;
+        a.ph = make_phys<C>(c->p);
+        a.ref = c->ref;
+        a.ntx = c->ntx;
+        a.nty = c->nty;
+        a.nlayer = c->nlayer;
+        const int nxt = 1 - c->cur;
+        a.fi = (const T *)c->f[c->cur];
+        a.gi = (const T *)c->g[c->cur];
+        a.fo = (T *)c->f[nxt];
+        a.go = (T *)c->g[nxt];
+        a.Mci = (const C *)c->Mc[c->cur];
+        a.INi = (const C *)c->IN[c->cur];
+        a.Mco = (C *)c->Mc[nxt];
+        a.INo = (C *)c->IN[nxt];
+        a.mlpP = c->mlp_params;
+        a.mlpW2b = c->mlp_w2b;
+        a.mlpNorm = c->mlp_norm;
+        a.mlpTol = (float)c->p.mlp_tol;
+        a.mlpCount = c->mlp_counters;
+        if constexpr (std::is_same<C, float>::value) {
+            if (c->p.eos == LBM_EOS_MLP) {
+                hipLaunchKernelGGL((k_fused<D, S, TL, true>), dim3(c->ntx, c->nty), dim3(TL::NT), 0, c->stream, a);
+                c->cur = nxt;
+                return;
+            }
+        }
+        hipLaunchKernelGGL((k_fused<D, S, TL, false>), dim3(c->ntx, c->nty), dim3(TL::NT), 0, c->stream, a);
+        c->cur = nxt;
+    }
 
     static int init(lbm_ctx *c, const double *rho, const double *u, const double *Tf) {
         hipLaunchKernelGGL((k_init<D, S>), cell_grid(c), dim3(BX), 0, c->stream, c->grid, make_phys<double>(c->p), c->ref,
                            rho, u, Tf, (T *)c->f[c->cur], (T *)c->g[c->cur]);
-        return last_launch();
+        int rc = last_launch();
+        return rc ? rc : fused_prepare(c);
     }
     static int fields_pass(lbm_ctx *c) {
         Fields<C> fl = get_fields<C>(c);
@@ -212,6 +263,14 @@ template <int D, class S> struct Impl {
         return last_launch();
     }
     static int step(lbm_ctx *c, int n) {
+        if (c->fused) {
+            for (int s = 0; s < n; s++) {
+                fused_launch(c);
+                int rc = last_launch();
+                if (rc) return rc;
+            }
+            return LBM_OK;
+        }
         Fields<C> fl = get_fields<C>(c);
         dim3 gr = cell_grid(c);
         for (int s = 0; s < n; s++) {
@@ -232,6 +291,25 @@ template <int D, class S> struct Impl {
         hipEvent_t ev[5];
         for (int k = 0; k < 5; k++)
             if (hipEventCreate(&ev[k]) != hipSuccess) return LBM_EDEVICE;
+        if (c->fused) {
+            double acc = 0;
+            int rc = LBM_OK;
+            for (int s = 0; s < n && rc == LBM_OK; s++) {
+                (void)hipEventRecord(ev[0], c->stream);
+                fused_launch(c);
+                (void)hipEventRecord(ev[1], c->stream);
+                rc = last_launch();
+                float ms = 0;
+                if (rc == LBM_OK && (hipEventSynchronize(ev[1]) != hipSuccess ||
+                                     hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
+                    rc = LBM_EDEVICE;
+                acc += ms;
+            }
+            for (int k = 0; k < 5; k++) (void)hipEventDestroy(ev[k]);
+            host_ms[0] = n > 0 ? acc / n : 0.0;
+            for (int k = 1; k < LBM_NUM_KERNELS; k++) host_ms[k] = 0.0;
+            return rc;
+        }
         double acc[4] = {0, 0, 0, 0};
         Fields<C> fl = get_fields<C>(c);
         dim3 gr = cell_grid(c);
@@ -278,7 +356,16 @@ template <int D, class S> struct Impl {
     static int set_pops(lbm_ctx *c, const double *f, const double *g) {
         hipLaunchKernelGGL((k_set_pops<D, S>), cell_grid(c), dim3(BX), 0, c->stream, c->grid, c->ref, f, g,
                            (T *)c->f[c->cur], (T *)c->g[c->cur]);
-        return last_launch();
+        int rc = last_launch();
+        return rc ? rc : fused_prepare(c);
+    }
+    static void tiles(lbm_ctx *c) {
+        c->ntx = (c->p.nx + TL::TX - 1) / TL::TX;
+        c->nty = (c->p.ny + TL::TY - 1) / TL::TY;
+        c->nlayer = D == 3 ? c->p.nz + 2 : 1;
+        c->mc_bytes = sizeof(C) * 5 * (size_t)c->nlayer * c->p.nx * c->p.ny;
+        c->in_bytes = sizeof(C) * (size_t)c->ntx * c->nty * c->nlayer * 5 * TL::NR;
+        return;
     }
     static int conservation(lbm_ctx *c, double *host_out) {
         int rc = fields_pass(c);
@@ -316,6 +403,22 @@ template <int D, class S> struct Impl {
         return Impl<3, StoreF16>::CALL;                                                        \
     } while (0)
 
+#define DISPATCH_VOID(ctx, CALL)                                                               \
+    do {                                                                                       \
+        const int st_ = (ctx)->p.storage;                                                      \
+        if ((ctx)->D == 2) {                                                                   \
+            if (st_ == LBM_STORE_F64) Impl<2, StoreF64>::CALL;                                 \
+            else if (st_ == LBM_STORE_F32) Impl<2, StoreF32>::CALL;                            \
+            else if (st_ == LBM_STORE_BF16) Impl<2, StoreBF16>::CALL;                          \
+            else Impl<2, StoreF16>::CALL;                                                      \
+        } else {                                                                               \
+            if (st_ == LBM_STORE_F64) Impl<3, StoreF64>::CALL;                                 \
+            else if (st_ == LBM_STORE_F32) Impl<3, StoreF32>::CALL;                            \
+            else if (st_ == LBM_STORE_BF16) Impl<3, StoreBF16>::CALL;                          \
+            else Impl<3, StoreF16>::CALL;                                                      \
+        }                                                                                      \
+    } while (0)
+
 // ---------------------------------------------------------------------------
 // exported entry points
 // ---------------------------------------------------------------------------
@@ -346,6 +449,7 @@ static int validate(const lbm_params *p) {
     if (p->eos != LBM_EOS_VDW && p->eos != LBM_EOS_MLP) return LBM_EINVAL;
     if (p->eos == LBM_EOS_MLP && p->storage == LBM_STORE_F64) return LBM_EINVAL;
     if (!(p->cv > 0) || !(p->mu > 0) || !(p->R > 0)) return LBM_EINVAL;
+    if (!(p->upwind_eps >= 0)) return LBM_EINVAL;
     if ((p->storage == LBM_STORE_BF16 || p->storage == LBM_STORE_F16) && !(p->ref_rho > 0 && p->ref_T > 0))
         return LBM_EINVAL;
     return LBM_OK;
@@ -382,13 +486,27 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
               hipMalloc((void **)&c->red_out, sizeof(double) * RED_VALS) == hipSuccess &&
               hipMalloc((void **)&c->mlp_counters, sizeof(unsigned long long) * 2) == hipSuccess &&
               hipMalloc((void **)&c->mlp_params, sizeof(float) * (LBM_MLP_NPARAMS + 64)) == hipSuccess &&
-              hipMalloc((void **)&c->mlp_norm, sizeof(float) * 16) == hipSuccess;
+              hipMalloc((void **)&c->mlp_norm, sizeof(float) * 16) == hipSuccess &&
+              hipMalloc((void **)&c->mlp_w2b, sizeof(uint16_t) * 64 * 64) == hipSuccess;
     if (!ok) {
         lbm_note(hipGetLastError());
         lbm_destroy(c);
         return LBM_ENOMEM;
     }
-    hipMemsetAsync(c->mlp_counters, 0, sizeof(unsigned long long) * 2, c->stream);
+    // the single-pass step covers periodic z (and every D = 2 lattice)
+    c->fused = c->D == 2 || params->bc[2] == LBM_BC_PERIODIC;
+    if (c->fused) {
+        auto tiles = [&]() { DISPATCH_VOID(c, tiles(c)); };
+        tiles();
+        ok = hipMalloc(&c->Mc[0], c->mc_bytes) == hipSuccess && hipMalloc(&c->Mc[1], c->mc_bytes) == hipSuccess &&
+             hipMalloc(&c->IN[0], c->in_bytes) == hipSuccess && hipMalloc(&c->IN[1], c->in_bytes) == hipSuccess;
+        if (!ok) {
+            lbm_note(hipGetLastError());
+            lbm_destroy(c);
+            return LBM_ENOMEM;
+        }
+    }
+    (void)hipMemsetAsync(c->mlp_counters, 0, sizeof(unsigned long long) * 2, c->stream);
     c->cur = 0;
     c->initialized = false;
     c->mlp_ready = false;
@@ -401,7 +519,7 @@ void lbm_destroy(lbm_ctx *c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
     void *ptrs[] = {c->f[0], c->f[1], c->g[0], c->g[1], c->work, c->red_partials, c->red_out,
-                    c->mlp_counters, c->mlp_params, c->mlp_norm};
+                    c->mlp_counters, c->mlp_params, c->mlp_norm, c->mlp_w2b, c->Mc[0], c->Mc[1], c->IN[0], c->IN[1]};
     for (void *p : ptrs)
         if (p) hipFree(p);
     delete c;
@@ -463,10 +581,13 @@ int lbm_step_timed(lbm_ctx *c, int n, double *host_ms, int nslots) {
 
 const char *lbm_last_error(void) { return g_last_error; }
 
-const char *lbm_kernel_name(int k) {
+const char *lbm_kernel_name(const lbm_ctx *c, int k) {
     static const char *names[LBM_NUM_KERNELS] = {"k_moments", "k_lap", "k_fields", "k_collide"};
+    if (c && c->fused) return k == 0 ? "k_fused" : "";
     return k >= 0 && k < LBM_NUM_KERNELS ? names[k] : "";
 }
+
+int lbm_is_fused(const lbm_ctx *c) { return c && c->fused ? 1 : 0; }
 
 double lbm_bytes_per_cell(const lbm_ctx *c) {
     if (!c) return 0.0;

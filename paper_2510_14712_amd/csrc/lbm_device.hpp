@@ -31,6 +31,7 @@ template <int D> __host__ __device__ constexpr int csq_of(int i) {
 template <class C> struct Phys {
     C a, b, R, cv, mu, eta, k, kappa;
     C inv_cv, k_over_mu, eta_over_mu;
+    C sgn_eps;  // dead zone of the upwind switch
 };
 
 // van der Waals pressure (eq. Pvdw)

@@ -4,7 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "lbm.h"
-#include "lbm_kernels.hpp"
+#include "lbm_fused.hpp"
 
 struct lbm_ctx {
     lbm_params p;
@@ -24,6 +24,14 @@ struct lbm_ctx {
     unsigned long long *mlp_counters = nullptr;  // [0] fallbacks, [1] evaluations
     float *mlp_params = nullptr;                 // 4547 FP32 + BF16 copy of W2
     float *mlp_norm = nullptr;
+    uint16_t *mlp_w2b = nullptr;      // BF16 copy of the hidden 64x64 weights
+    uint16_t mlp_w2b_host[64 * 64];
+    // single-pass fused step: moment side channel of the current state
+    bool fused = false;
+    void *Mc[2] = {nullptr, nullptr};  // [5][nlayer][ny][nx]
+    void *IN[2] = {nullptr, nullptr};  // [tiles][nlayer][5][slots]
+    size_t mc_bytes = 0, in_bytes = 0;
+    int ntx = 0, nty = 0, nlayer = 0;
 };
 
 // carve the field arrays out of the work buffer

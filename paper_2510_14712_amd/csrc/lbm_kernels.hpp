@@ -210,11 +210,11 @@ __global__ void __launch_bounds__(BX) k_collide(Grid g, Phys<typename S::C> ph, 
         C dh = C(0.5) * (fl.h[cp] - fl.h[cm]);
         C dT = C(0.5) * (fl.T[cp] - fl.T[cm]);
         qc[a] = P * (dh - ph.k_over_mu * dT);                  // eq. qc_1
-        // upwind-biased d_a Lambda_a by sgn(u_a); sgn(0) = 0 gives the average
+        // upwind-biased d_a Lambda_a by sgn(u_a); |u_a| <= eps gives the average
         C L0 = fl.Lam[a * N + c];
         C dL;
-        if (u[a] > C(0)) dL = L0 - fl.Lam[a * N + cm];
-        else if (u[a] < C(0)) dL = fl.Lam[a * N + cp] - L0;
+        if (u[a] > ph.sgn_eps) dL = L0 - fl.Lam[a * N + cm];
+        else if (u[a] < -ph.sgn_eps) dL = fl.Lam[a * N + cp] - L0;
         else dL = C(0.5) * (fl.Lam[a * N + cp] - fl.Lam[a * N + cm]);
         Phi[a] = -dL * inv_rho;                                // eq. correction
     }

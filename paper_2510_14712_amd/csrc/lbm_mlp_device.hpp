@@ -1,0 +1,116 @@
+// Wave-level inference of the 2 -> 64 -> 64 -> 3 equation-of-state surrogate
+// without LDS.  One wavefront evaluates 64 samples (one per lane).
+//
+// The hidden layer is computed transposed, Z2^T = W2 H1^T, with
+// v_mfma_f32_32x32x16_bf16: A = W2 (rows: output neurons, loaded as 8
+// contiguous BF16 per lane), B = H1^T (rows: input neurons, columns: samples).
+// For the B operand lane l holds input neurons 16 ks + 8 (l / 32) + j of
+// samples 32 nt + l % 32, so each lane evaluates its own first-layer
+// activations; no transpose through memory is needed.  The accumulator gives
+// lane l the output neurons 32 mt + 8 (v / 4) + 4 (l / 32) + v % 4 of the same
+// samples; the output layer is a per-lane partial dot product completed with
+// the partner lane l ^ 32.
+#pragma once
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+namespace mlp {
+
+constexpr int H = 64;
+constexpr int OFF_W1 = 0, OFF_B1 = 128, OFF_W2 = 192, OFF_B2 = 4288, OFF_W3 = 4352, OFF_B3 = 4544;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float fast_tanh(float x) {
+    const float ax = fminf(fabsf(x), 15.0f);
+    const float e = __expf(-2.0f * ax);
+    const float t = __fdividef(1.0f - e, 1.0f + e);
+    return copysignf(t, x);
+}
+
+__device__ __forceinline__ __bf16 to_bf16(float v) { return __builtin_bit_cast(__bf16, f32_to_bf16_rne(v)); }
+
+__device__ __forceinline__ void normalise(const float *norm, float rho, float e, float &x0, float &x1) {
+    x0 = 2.0f * (rho - norm[0]) / (norm[1] - norm[0]) - 1.0f;
+    x1 = 2.0f * (e - norm[2]) / (norm[3] - norm[2]) - 1.0f;
+}
+
+// P: FP32 parameters; W2b: BF16 copy of W2 (row-major, [out][in]) or null,
+// in which case the FP32 W2 of P is rounded on the fly.
+// Returns the normalised outputs 0..NOUT-1 of this lane's sample.  Every lane
+// of the wavefront must call with uniform control flow.
+template <int NOUT>
+__device__ __forceinline__ void forward_wave(float x0, float x1, const float *__restrict__ P,
+                                             const uint16_t *__restrict__ W2b, float y[NOUT]) {
+    const int lane = threadIdx.x & 63;
+    const int hh = lane >> 5, c = lane & 31;
+    // inputs of the two samples this lane serves in the B operand
+    float xs0[2], xs1[2];
+    xs0[0] = __shfl(x0, c, 64);
+    xs1[0] = __shfl(x1, c, 64);
+    xs0[1] = __shfl(x0, 32 + c, 64);
+    xs1[1] = __shfl(x1, 32 + c, 64);
+    bf16x8 b[2][4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ks++)
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const int k = 16 * ks + 8 * hh + j;
+            const float w0 = P[OFF_W1 + 2 * k], w1 = P[OFF_W1 + 2 * k + 1], bk = P[OFF_B1 + k];
+#pragma unroll
+            for (int nt = 0; nt < 2; nt++) b[nt][ks][j] = to_bf16(fast_tanh(fmaf(w0, xs0[nt], fmaf(w1, xs1[nt], bk))));
+        }
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int mt = 0; mt < 2; mt++)
+#pragma unroll
+        for (int nt = 0; nt < 2; nt++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) acc[mt][nt][v] = 0.0f;
+#pragma unroll
+    for (int ks = 0; ks < 4; ks++) {
+#pragma unroll
+        for (int mt = 0; mt < 2; mt++) {
+            bf16x8 a;
+            if (W2b) {
+                const uint4 raw = *(const uint4 *)(W2b + (32 * mt + c) * H + 16 * ks + 8 * hh);
+                a = __builtin_bit_cast(bf16x8, raw);
+            } else {
+                const float *row = P + OFF_W2 + (32 * mt + c) * H + 16 * ks + 8 * hh;
+#pragma unroll
+                for (int j = 0; j < 8; j++) a[j] = to_bf16(row[j]);
+            }
+#pragma unroll
+            for (int nt = 0; nt < 2; nt++)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[nt][ks], acc[mt][nt], 0, 0, 0);
+        }
+    }
+    float ys[NOUT][2];
+#pragma unroll
+    for (int k = 0; k < NOUT; k++) ys[k][0] = ys[k][1] = 0.0f;
+#pragma unroll
+    for (int mt = 0; mt < 2; mt++)
+#pragma unroll
+        for (int v = 0; v < 16; v++) {
+            const int o = 32 * mt + 8 * (v >> 2) + 4 * hh + (v & 3);
+            const float bo = P[OFF_B2 + o];
+#pragma unroll
+            for (int nt = 0; nt < 2; nt++) {
+                const float h2 = fast_tanh(acc[mt][nt][v] + bo);
+#pragma unroll
+                for (int k = 0; k < NOUT; k++) ys[k][nt] = fmaf(P[OFF_W3 + k * H + o], h2, ys[k][nt]);
+            }
+        }
+#pragma unroll
+    for (int k = 0; k < NOUT; k++) {
+#pragma unroll
+        for (int nt = 0; nt < 2; nt++) ys[k][nt] += __shfl_xor(ys[k][nt], 32, 64);
+        // lane l's own sample is 32 nt + c with nt = l / 32
+        y[k] = (hh == 0 ? ys[k][0] : ys[k][1]) + P[OFF_B3 + k];
+    }
+}
+
+}  // namespace mlp
+}  // namespace lbm

@@ -20,6 +20,8 @@ STORAGE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 EOS = {"vdw": 0, "mlp": 1}
 MLP_BF16, MLP_F32 = 0, 1
 MLP_NPARAMS, MLP_NNORM = 4547, 10
+# dead zone of the upwind switch: |u| at or below takes the central average
+UPWIND_EPS = 1e-6
 
 
 class LbmError(RuntimeError):
@@ -36,7 +38,8 @@ class _Params(ctypes.Structure):
                 ("mu", ctypes.c_double), ("eta", ctypes.c_double), ("k", ctypes.c_double),
                 ("kappa", ctypes.c_double),
                 ("storage", ctypes.c_int), ("eos", ctypes.c_int), ("mlp_tol", ctypes.c_double),
-                ("ref_rho", ctypes.c_double), ("ref_T", ctypes.c_double), ("stream", ctypes.c_void_p)]
+                ("ref_rho", ctypes.c_double), ("ref_T", ctypes.c_double), ("stream", ctypes.c_void_p),
+                ("upwind_eps", ctypes.c_double)]
 
 
 _lib = None
@@ -44,10 +47,15 @@ _VP, _DP, _FP = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER
 
 
 def load():
-    """Load the HIP library (raises if it has not been built)."""
+    """Load the HIP library (raises if it has not been built).
+
+    torch is imported first: its bundled HIP runtime (soname libamdhip64.so.7)
+    is then the one the library binds to, so the process holds a single HIP
+    runtime; loading the library first would pull in a second copy."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401  (HIP runtime before the library, see above)
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
     L = ctypes.CDLL(LIB_PATH)
@@ -64,7 +72,8 @@ def load():
         "lbm_synchronize": ([_VP], ctypes.c_int),
         "lbm_bytes_per_cell": ([_VP], ctypes.c_double),
         "lbm_step_timed": ([_VP, ctypes.c_int, _DP, ctypes.c_int], ctypes.c_int),
-        "lbm_kernel_name": ([ctypes.c_int], ctypes.c_char_p),
+        "lbm_kernel_name": ([_VP, ctypes.c_int], ctypes.c_char_p),
+        "lbm_is_fused": ([_VP], ctypes.c_int),
         "lbm_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "lbm_last_error": ([], ctypes.c_char_p),
         "lbm_mlp_train": ([PP, _DP, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_float,
@@ -125,7 +134,7 @@ class Lattice:
 
     def __init__(self, lattice, shape, bc=(0, 0, 0), a=3.0 / 49.0, b=2.0 / 21.0, R=1.0, cv=2.5, mu=0.05,
                  eta=0.05, k=None, kappa=0.01, storage="f32", eos="vdw", mlp_tol=1e-6, ref_rho=0.0, ref_T=0.0,
-                 stream=None):
+                 stream=None, upwind_eps=UPWIND_EPS):
         L = load()
         self.D = int(lattice)
         nx, ny = int(shape[0]), int(shape[1])
@@ -145,6 +154,7 @@ class Lattice:
         p.eos = EOS[eos] if isinstance(eos, str) else int(eos)
         p.mlp_tol = mlp_tol
         p.ref_rho, p.ref_T = ref_rho, ref_T
+        p.upwind_eps = upwind_eps
         self._stream = stream
         p.stream = _stream_ptr(stream).value if _torch().cuda.is_available() else None
         self.params = p
@@ -187,7 +197,12 @@ class Lattice:
         """Average per-launch duration (ms) of each kernel of the step over n steps."""
         out = (ctypes.c_double * 8)()
         _check(load().lbm_step_timed(self._h, int(n), out, 8), "lbm_step_timed")
-        return {load().lbm_kernel_name(k).decode(): out[k] for k in range(8) if load().lbm_kernel_name(k)}
+        names = [load().lbm_kernel_name(self._h, k).decode() for k in range(8)]
+        return {nm: out[k] for k, nm in enumerate(names) if nm}
+
+    @property
+    def fused(self):
+        return bool(load().lbm_is_fused(self._h))
 
     def moments(self):
         torch = _torch()

@@ -47,6 +47,7 @@ def _run_both(D, shape, bc, rho, u, T, steps, storage="f64", kw=None):
     kw = dict(KW, **(kw or {}))
     _say(f"case D={D} shape={shape} bc={bc} storage={storage} steps={steps}")
     with lbm.Lattice(D, shape, bc=bc, storage=storage, **kw) as lat:
+        assert lat.fused == (D == 2 or bc[2] == 0)
         lat.init(rho, u, T).step(steps)
         f, g = (t.cpu().numpy() for t in lat.get_populations())
         mom = {k: v.cpu().numpy() for k, v in lat.moments().items()}
@@ -109,12 +110,13 @@ def test_taylor_green_fp32_200_steps():
 def test_shock_drop_2d_fp32():
     """Shock-drop geometry (Maxwell drop at 0.85 T_c, Ma 1.47 Rankine-Hugoniot
     shock) reduced to 192x96.  The liquid's lattice checkerboard mode grows
-    (see the stability test of the oracle), so parity is taken at 30 steps."""
+    about 0.5 per step (see the stability test of the oracle) and amplifies
+    FP32 round-off, so parity is taken at 10 steps."""
     c = ST["shock_drop_2d"]
     shape = (192, 96)
     rho, u, T = inputs.shock_drop(shape, (70, 48), 20, c["width"], c["rho_liquid"], c["rho_vapour"], c["T1"],
                                   20, c["rho2"], c["T2"], c["u2"])
-    (f, g, mom), (fr, gr, ref) = _run_both(2, shape, (1, 0, 0), rho, u, T, 30, storage="f32")
+    (f, g, mom), (fr, gr, ref) = _run_both(2, shape, (1, 0, 0), rho, u, T, 10, storage="f32")
     for k in ("rho", "u", "T"):
         e = rel_l2(mom[k], ref[k])
         _say(f"  shock-drop FP32 {k} rel-L2 {e:.3e}")
