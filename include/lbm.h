@@ -76,12 +76,20 @@ typedef struct {
     int eos;                /* LBM_EOS_* */
     double mlp_tol;         /* surrogate acceptance threshold on
                                |e(rho, T_hat) - e| / (c_v T_hat) */
-    double ref_rho, ref_T;  /* reference state of the 16-bit storage forms */
+    double ref_rho, ref_T;  /* reference state (rest equilibria at ref_rho,
+                               ref_T): required by the 16-bit storage forms,
+                               which store deviations from it; optional (0 =
+                               none) for FP32/FP64, where it is the origin of
+                               the moment sums (accuracy only) */
     void *stream;           /* hipStream_t for all asynchronous work; NULL =
                                the null stream */
     double upwind_eps;      /* |u_a| <= upwind_eps takes the central average in
                                the upwind-biased derivative of Lambda_a (the
                                tie sgn(0) = 0 widened to a round-off dead zone) */
+    int zsegments;          /* z segments of the single-pass step (lattice 3,
+                               periodic z): 0 = automatic, else 1..nz; the
+                               result does not depend on it beyond round-off
+                               of the moment sums' order */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx; /* opaque, library-owned */
@@ -141,8 +149,10 @@ int lbm_step_timed(lbm_ctx *ctx, int n, double *host_ms, int nslots);
 const char *lbm_kernel_name(const lbm_ctx *ctx, int kernel);
 
 /* 1 when lbm_step runs the single-pass fused kernel (one read and one write
- * of every population per step; periodic z or D = 2), 0 when it runs the
- * four-kernel path (moments, Laplacian, fields, collide). */
+ * of every population per step; periodic z or D = 2) followed by the small
+ * pass completing its moment side channel (kernel kinds "k_fused",
+ * "k_fused_fixup"), 0 when it runs the four-kernel path (moments, Laplacian,
+ * fields, collide). */
 int lbm_is_fused(const lbm_ctx *ctx);
 
 /* Algorithmic HBM bytes moved per cell update by lbm_step (2 Q populations

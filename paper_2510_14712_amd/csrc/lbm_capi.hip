@@ -11,6 +11,7 @@
 
 #include "lbm.h"
 #include "lbm_internal.hpp"
+#include <algorithm>
 #include <type_traits>
 
 using namespace lbm;
@@ -155,7 +156,7 @@ template <class C> static Phys<C> make_phys(const lbm_params &p) {
 // ref_T) (Psi(0) = 1 - theta, Psi(+-1) = theta/2 at u = 0), computed in FP64.
 static void make_ref(const lbm_params &p, int D, RefPops &ref) {
     std::memset(&ref, 0, sizeof(ref));
-    if (p.storage != LBM_STORE_BF16 && p.storage != LBM_STORE_F16) return;
+    if (!(p.ref_rho > 0 && p.ref_T > 0)) return;
     double r = p.ref_rho, t = p.ref_T;
     double P = r * p.R * t / (1.0 - p.b * r) - p.a * r * r;
     double th = P / r;
@@ -195,9 +196,9 @@ template <int D, class S> struct Impl {
     using T = typename S::T;
     using TL = TileOf<S>;
 
-    // complete moments of the current state into the side channel; the wrap
-    // layers and all inbound slots of both buffers start at zero (slots on a
-    // zero-gradient wall are never written afterwards)
+    // complete moments of the current state into the side channel; inbound
+    // slots of both buffers start at zero (slots behind a zero-gradient wall
+    // are never written afterwards, the fix-up pass adds them as zeros)
     static int fused_prepare(lbm_ctx *c) {
         if (!c->fused) return LBM_OK;
         for (int s = 0; s < 2; s++) {
@@ -205,25 +206,52 @@ template <int D, class S> struct Impl {
                 hipMemsetAsync(c->IN[s], 0, c->in_bytes, c->stream) != hipSuccess)
                 return lbm_note(hipGetLastError());
         }
-        hipLaunchKernelGGL((k_fused_moments<D, S, TL>), cell_grid(c), dim3(BX), 0, c->stream, c->grid, c->ref,
-                           c->nlayer, (const T *)c->f[c->cur], (const T *)c->g[c->cur], (C *)c->Mc[c->cur]);
+        C rs[4];
+        ref_sums(c, rs);
+        hipLaunchKernelGGL((k_fused_moments<D, S, TL>), cell_grid(c), dim3(BX), 0, c->stream, c->grid, c->ref, rs[0],
+                           rs[1], rs[2], rs[3],
+                           c->ntx, c->nty, c->nseg, c->nlay, (const T *)c->f[c->cur], (const T *)c->g[c->cur],
+                           (C *)c->Mc[c->cur]);
         return last_launch();
     }
-    static void fused_launch(lbm_ctx *c) {
+    // sums of the reference populations in the compute type as hi + lo
+    // pairs {f_hi, f_lo, g_hi, g_lo} (FP64 sums of the stored references)
+    static void ref_sums(const lbm_ctx *c, C rs[4]) {
+        double sf = 0, sg = 0;
+        for (int i = 0; i < c->Q; i++) {
+            sf += (double)(C)c->ref.f[i];
+            sg += (double)(C)c->ref.g[i];
+        }
+        rs[0] = (C)sf;
+        rs[1] = (C)(sf - (double)rs[0]);
+        rs[2] = (C)sg;
+        rs[3] = (C)(sg - (double)rs[2]);
+    }
+    // the fused step proper (kind 0 of step_timed)
+    static void fused_main(lbm_ctx *c) {
         FusedArgs<C, T> a;
         a.g = c->grid;
         a.ph = make_phys<C>(c->p);
         a.ref = c->ref;
         a.ntx = c->ntx;
         a.nty = c->nty;
-        a.nlayer = c->nlayer;
+        a.nseg = c->nseg;
+        a.nlay = c->nlay;
+        a.chunk = c->chunk;
+        {
+            C rs[4];
+            ref_sums(c, rs);
+            a.rsf_hi = rs[0];
+            a.rsf_lo = rs[1];
+            a.rsg_hi = rs[2];
+            a.rsg_lo = rs[3];
+        }
         const int nxt = 1 - c->cur;
         a.fi = (const T *)c->f[c->cur];
         a.gi = (const T *)c->g[c->cur];
         a.fo = (T *)c->f[nxt];
         a.go = (T *)c->g[nxt];
         a.Mci = (const C *)c->Mc[c->cur];
-        a.INi = (const C *)c->IN[c->cur];
         a.Mco = (C *)c->Mc[nxt];
         a.INo = (C *)c->IN[nxt];
         a.mlpP = c->mlp_params;
@@ -231,15 +259,33 @@ template <int D, class S> struct Impl {
         a.mlpNorm = c->mlp_norm;
         a.mlpTol = (float)c->p.mlp_tol;
         a.mlpCount = c->mlp_counters;
+        const dim3 grid((unsigned)(c->ntx * c->nty * c->nseg));
         if constexpr (std::is_same<C, float>::value) {
             if (c->p.eos == LBM_EOS_MLP) {
-                hipLaunchKernelGGL((k_fused<D, S, TL, true>), dim3(c->ntx, c->nty), dim3(TL::NT), 0, c->stream, a);
-                c->cur = nxt;
+                hipLaunchKernelGGL((k_fused<D, S, TL, true>), grid, dim3(TL::NT), 0, c->stream, a);
                 return;
             }
         }
-        hipLaunchKernelGGL((k_fused<D, S, TL, false>), dim3(c->ntx, c->nty), dim3(TL::NT), 0, c->stream, a);
+        hipLaunchKernelGGL((k_fused<D, S, TL, false>), grid, dim3(TL::NT), 0, c->stream, a);
+    }
+    // completes the output moments (kind 1 of step_timed) and flips the state
+    static void fused_fixup(lbm_ctx *c) {
+        const int nxt = 1 - c->cur;
+        const long long per = (long long)c->ntx * c->nty * TL::PMAX;
+        hipLaunchKernelGGL((k_fused_fixup<D, TL, C>), dim3((unsigned)((per + BX - 1) / BX), c->p.nz), dim3(BX), 0,
+                           c->stream, c->grid, c->ntx, c->nty, c->nseg, c->nlay, 0, (C *)c->Mc[nxt],
+                           (const C *)c->IN[nxt]);
+        if (D == 3) {
+            const long long plane = (long long)c->p.nx * c->p.ny;
+            hipLaunchKernelGGL((k_fused_fixup<D, TL, C>), dim3((unsigned)((plane + BX - 1) / BX), 2 * c->nseg),
+                               dim3(BX), 0, c->stream, c->grid, c->ntx, c->nty, c->nseg, c->nlay, 1,
+                               (C *)c->Mc[nxt], (const C *)c->IN[nxt]);
+        }
         c->cur = nxt;
+    }
+    static void fused_launch(lbm_ctx *c) {
+        fused_main(c);
+        fused_fixup(c);
     }
 
     static int init(lbm_ctx *c, const double *rho, const double *u, const double *Tf) {
@@ -292,22 +338,25 @@ template <int D, class S> struct Impl {
         for (int k = 0; k < 5; k++)
             if (hipEventCreate(&ev[k]) != hipSuccess) return LBM_EDEVICE;
         if (c->fused) {
-            double acc = 0;
+            double acc[2] = {0, 0};
             int rc = LBM_OK;
             for (int s = 0; s < n && rc == LBM_OK; s++) {
                 (void)hipEventRecord(ev[0], c->stream);
-                fused_launch(c);
+                fused_main(c);
                 (void)hipEventRecord(ev[1], c->stream);
+                fused_fixup(c);
+                (void)hipEventRecord(ev[2], c->stream);
                 rc = last_launch();
-                float ms = 0;
-                if (rc == LBM_OK && (hipEventSynchronize(ev[1]) != hipSuccess ||
-                                     hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
-                    rc = LBM_EDEVICE;
-                acc += ms;
+                for (int k = 0; k < 2 && rc == LBM_OK; k++) {
+                    float ms = 0;
+                    if (hipEventSynchronize(ev[k + 1]) != hipSuccess ||
+                        hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess)
+                        rc = LBM_EDEVICE;
+                    acc[k] += ms;
+                }
             }
             for (int k = 0; k < 5; k++) (void)hipEventDestroy(ev[k]);
-            host_ms[0] = n > 0 ? acc / n : 0.0;
-            for (int k = 1; k < LBM_NUM_KERNELS; k++) host_ms[k] = 0.0;
+            for (int k = 0; k < LBM_NUM_KERNELS; k++) host_ms[k] = (k < 2 && n > 0) ? acc[k] / n : 0.0;
             return rc;
         }
         double acc[4] = {0, 0, 0, 0};
@@ -362,10 +411,22 @@ template <int D, class S> struct Impl {
     static void tiles(lbm_ctx *c) {
         c->ntx = (c->p.nx + TL::TX - 1) / TL::TX;
         c->nty = (c->p.ny + TL::TY - 1) / TL::TY;
-        c->nlayer = D == 3 ? c->p.nz + 2 : 1;
-        c->mc_bytes = sizeof(C) * 5 * (size_t)c->nlayer * c->p.nx * c->p.ny;
-        c->in_bytes = sizeof(C) * (size_t)c->ntx * c->nty * c->nlayer * 5 * TL::NR;
-        return;
+        const long long ntiles = (long long)c->ntx * c->nty;
+        if (D == 2) {
+            c->nseg = 1;
+        } else if (c->p.zsegments > 0) {
+            c->nseg = c->p.zsegments;
+        } else {
+            // enough workgroups for two resident per compute unit on 256 CUs,
+            // segments of at least 16 planes
+            int s = (int)((1024 + ntiles - 1) / ntiles);
+            c->nseg = std::max(1, std::min(s, c->p.nz / 16));
+        }
+        c->nlay = D == 3 ? c->p.nz + 2 * c->nseg : 1;
+        const long long total = ntiles * c->nseg;
+        c->chunk = total % 8 == 0 ? (int)(total / 8) : 0;
+        c->mc_bytes = sizeof(C) * 5 * (size_t)c->nlay * c->p.nx * c->p.ny;
+        c->in_bytes = sizeof(C) * (size_t)ntiles * c->nlay * 5 * TL::NR;
     }
     static int conservation(lbm_ctx *c, double *host_out) {
         int rc = fields_pass(c);
@@ -450,8 +511,11 @@ static int validate(const lbm_params *p) {
     if (p->eos == LBM_EOS_MLP && p->storage == LBM_STORE_F64) return LBM_EINVAL;
     if (!(p->cv > 0) || !(p->mu > 0) || !(p->R > 0)) return LBM_EINVAL;
     if (!(p->upwind_eps >= 0)) return LBM_EINVAL;
+    if (p->zsegments < 0 || p->zsegments > p->nz) return LBM_EINVAL;
+    if ((long long)p->nx * p->ny > (1LL << 30)) return LBM_EINVAL;
     if ((p->storage == LBM_STORE_BF16 || p->storage == LBM_STORE_F16) && !(p->ref_rho > 0 && p->ref_T > 0))
         return LBM_EINVAL;
+    if (!(p->ref_rho >= 0 && p->ref_T >= 0)) return LBM_EINVAL;
     return LBM_OK;
 }
 
@@ -583,7 +647,7 @@ const char *lbm_last_error(void) { return g_last_error; }
 
 const char *lbm_kernel_name(const lbm_ctx *c, int k) {
     static const char *names[LBM_NUM_KERNELS] = {"k_moments", "k_lap", "k_fields", "k_collide"};
-    if (c && c->fused) return k == 0 ? "k_fused" : "";
+    if (c && c->fused) return k == 0 ? "k_fused" : (k == 1 ? "k_fused_fixup" : "");
     return k >= 0 && k < LBM_NUM_KERNELS ? names[k] : "";
 }
 

@@ -61,8 +61,11 @@ struct Grid {
 
 // ---------------------------------------------------------------------------
 // Population storage forms.  load() returns the population in the compute
-// type; store() encodes it.  16-bit forms hold the deviation from a fixed
-// per-direction reference, rounded to nearest even.
+// type; enc() encodes it; dev() returns its deviation from the per-direction
+// reference (exact for the 16-bit forms, which store the deviation rounded to
+// nearest even; one subtraction for the wide forms, exact while the value is
+// within a factor two of the reference).  Moment sums over deviations keep
+// the large, nearly constant part out of the rounding.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float v) {
     uint32_t u = __float_as_uint(v);
@@ -83,6 +86,7 @@ struct StoreF64 {
     static constexpr int bytes = 8;
     __device__ static __forceinline__ C load(const T *p, long long j, C) { return p[j]; }
     __device__ static __forceinline__ T enc(C v, C) { return v; }
+    __device__ static __forceinline__ C dev(const T *p, long long j, C ref) { return p[j] - ref; }
 };
 struct StoreF32 {
     using T = float;
@@ -90,6 +94,7 @@ struct StoreF32 {
     static constexpr int bytes = 4;
     __device__ static __forceinline__ C load(const T *p, long long j, C) { return p[j]; }
     __device__ static __forceinline__ T enc(C v, C) { return v; }
+    __device__ static __forceinline__ C dev(const T *p, long long j, C ref) { return p[j] - ref; }
 };
 struct StoreBF16 {
     using T = uint16_t;
@@ -97,6 +102,7 @@ struct StoreBF16 {
     static constexpr int bytes = 2;
     __device__ static __forceinline__ C load(const T *p, long long j, C ref) { return ref + bf16_to_f32(p[j]); }
     __device__ static __forceinline__ T enc(C v, C ref) { return f32_to_bf16_rne(v - ref); }
+    __device__ static __forceinline__ C dev(const T *p, long long j, C) { return bf16_to_f32(p[j]); }
 };
 struct StoreF16 {
     using T = uint16_t;
@@ -104,9 +110,11 @@ struct StoreF16 {
     static constexpr int bytes = 2;
     __device__ static __forceinline__ C load(const T *p, long long j, C ref) { return ref + f16_to_f32(p[j]); }
     __device__ static __forceinline__ T enc(C v, C ref) { return f32_to_f16_rne(v - ref); }
+    __device__ static __forceinline__ C dev(const T *p, long long j, C) { return f16_to_f32(p[j]); }
 };
 
-// reference populations of the 16-bit forms (zero for the wide forms)
+// reference populations: storage origin of the 16-bit forms, origin of the
+// moment sums for every form (zero when no reference state is given)
 struct RefPops {
     float f[27];
     float g[27];

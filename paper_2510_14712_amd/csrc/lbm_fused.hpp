@@ -2,25 +2,31 @@
 // step (Section 3.2 and its flowchart: moments -> Korteweg force -> u, E, T,
 // P, Phi, q^c -> attractors -> collide and stream).
 //
-// Decomposition.  A workgroup owns a TX x TY tile of (x, y) columns and marches
-// over z.  The non-local inputs of the collision are the moments of the
-// post-streaming state: rho on the L1 ball of radius 3 (Laplacian, then the
-// Korteweg force at the face neighbours), j and G at the face neighbours.
-// Those moments are produced by the previous step: after colliding a plane,
-// the workgroup gathers the pushed populations into moment sums for every
-// destination cell of the tile and of its one-cell ring (LDS, fixed order,
-// one owning thread per destination).  Tile cells are written to Mc; ring
-// cells are written into "inbound" slots that belong to the neighbouring tile
-// (IN), one writer per slot.  A reader adds the inbound slots of a cell on a
-// tile edge to Mc.  z-wrap contributions go to two extra layers of Mc / IN
-// (logical planes -1 and nz) that a reader adds to planes nz-1 and 0.
+// Decomposition.  A workgroup owns a TX x TY tile of (x, y) columns and one
+// segment [z0, z1) of planes, which it marches through.  The non-local inputs
+// of the collision are the moments of the post-streaming state: rho on the L1
+// ball of radius 3 (Laplacian, then the Korteweg force at the face
+// neighbours), j and G at the cell and its face neighbours.  Those moments are
+// produced by the previous step: after colliding plane z the workgroup
+// gathers the pushed populations into per-thread moment accumulators of the
+// destination cells in planes z-1, z, z+1: the thread's own cell and, for the
+// first threads, one cell of the one-cell ring around the tile.  A completed
+// plane is written out as
+//   Mc  tile cells: the tile's own part of the sum,
+//   IN  ring cells: inbound slots of the neighbouring tile that owns the cell,
+// and the planes z0-1 and z1 of a segment, which the neighbouring segments
+// complete, go to two spill layers of Mc / IN.  k_fused_fixup then adds the
+// inbound slots and spill layers into Mc (fixed order, one thread per cell),
+// so the next step reads complete moments with one load per value.
 //
-// Per marching position z (colliding plane z):
-//   rho(z+3) on R3 (tile + halo 3)  -> Laplacian L(z+2) on R2 (halo 2)
-//   -> F(z+1), u, E, T, P, h, Lambda, c_s^2 on R1 (halo 1)
-//   -> collide plane z (needs fields of z-1, z, z+1), push to the other buffer
-//   -> moment sums of the pushed populations for planes z-1, z, z+1
-//   -> plane z-1 complete: write Mc / IN.
+// Per marching position z (rho(z+1..z+4) and L(z..z+2) already in LDS):
+//   phase A  Laplacian L(z+3); fields u, T, P, h, Lambda, F, c_s^2 of plane
+//            z+1 for the tile and its ring
+//   phase B  collide plane z, store rho(z+5) (loaded at the top of the
+//            iteration) over rho(z+1), push to the other buffer
+//   rounds   exchange the pushed populations by c_z through LDS (three
+//            double-buffered rounds), gather the moment sums; plane z-1 is
+//            complete after the first round and is written out.
 // Ghost cells of zero-gradient axes take the field of the clamped cell.
 #pragma once
 
@@ -31,64 +37,102 @@ namespace lbm {
 
 template <int TX_, int TY_> struct Tile {
     static constexpr int TX = TX_, TY = TY_, NT = TX_ * TY_;
-    static constexpr int NR = 2 * TX_ + 2 * TY_ + 4;  // inbound slots per tile, plane and field
     static constexpr int W3 = TX_ + 6, H3 = TY_ + 6, R3 = W3 * H3;
     static constexpr int W2 = TX_ + 4, H2 = TY_ + 4, R2 = W2 * H2;
     static constexpr int W1 = TX_ + 2, H1 = TY_ + 2, R1 = W1 * H1;
-    // inbound slot offsets
+    // ring cells of a full tile = inbound slots per tile, layer and moment
+    static constexpr int NR = 2 * TX_ + 2 * TY_ + 4;
+    // perimeter cells of a full tile
+    static constexpr int PMAX = 2 * TX_ + 2 * TY_ - 4;
+    // inbound slot offsets: contributions coming from the left / right / ...
+    // neighbour, stored at the receiving cell's row (FROM_L, FROM_R) or column
     static constexpr int FROM_L = 0, FROM_R = TY_, FROM_B = 2 * TY_, FROM_T = 2 * TY_ + TX_;
     static constexpr int FROM_BL = 2 * TY_ + 2 * TX_, FROM_BR = FROM_BL + 1, FROM_TL = FROM_BL + 2,
                          FROM_TR = FROM_BL + 3;
+    static_assert(NR <= NT, "one thread per ring cell");
 };
+
+// first plane of z segment s (segments split nz as evenly as possible)
+__host__ __device__ __forceinline__ int seg_lo(int s, int nz, int nseg) {
+    return (int)(((long long)s * nz) / nseg);
+}
+// segment holding plane z
+__host__ __device__ __forceinline__ int seg_of(int z, int nz, int nseg) {
+    return (int)((((long long)z + 1) * nseg - 1) / nz);
+}
 
 template <class C, class T> struct FusedArgs {
     Grid g;
     Phys<C> ph;
     RefPops ref;
-    int ntx, nty, nlayer;  // tiles along x, y; moment layers (nz + 2 for D = 3, 1 for D = 2)
+    int ntx, nty, nseg;  // tiles along x, y; z segments
+    int nlay;            // layers of Mc / IN: nz planes + 2 spill layers per segment (D = 3), 1 (D = 2)
+    int chunk;           // tiles per XCD in the remapped order, 0: identity order
+    // sums of the reference populations as hi + lo pairs (moment sums run
+    // over deviations; the pair keeps the constant's rounding from biasing
+    // every cell's mass the same way)
+    C rsf_hi, rsf_lo, rsg_hi, rsg_lo;
     const T *fi, *gi;
     T *fo, *go;
-    const C *Mci, *INi;
-    C *Mco, *INo;
-    // surrogate equation of state (used when the kernel is built with MLP)
-    const float *mlpP;        // FP32 parameters
-    const uint16_t *mlpW2b;   // BF16 copy of the hidden weights
-    const float *mlpNorm;     // normalisation constants
-    float mlpTol;             // residual threshold
+    const C *Mci;  // complete moments of the input state, [5][nlay][ny][nx]
+    C *Mco, *INo;  // output: tile-own partial sums, inbound slots [tiles][nlay][5][NR]
+    // surrogate equation of state (kernels built with MLP)
+    const float *mlpP;             // FP32 parameters
+    const uint16_t *mlpW2b;        // BF16 copy of the hidden weights
+    const float *mlpNorm;          // normalisation constants
+    float mlpTol;                  // residual threshold
     unsigned long long *mlpCount;  // [0] fallbacks, [1] evaluations
 };
 
-// layer of logical plane p (-1 .. nz) in the moment arrays
-template <int D> __device__ __forceinline__ int layer_of(int p) { return D == 3 ? p + 1 : 0; }
+// ring cell r of a w x h tile: bottom row, top row, left column, right column
+__device__ __forceinline__ bool ring_pos(int r, int w, int h, int &rx, int &ry) {
+    if (r < w + 2) { rx = r - 1; ry = -1; return true; }
+    r -= w + 2;
+    if (r < w + 2) { rx = r - 1; ry = h; return true; }
+    r -= w + 2;
+    if (r < h) { rx = -1; ry = r; return true; }
+    r -= h;
+    if (r < h) { rx = w; ry = r; return true; }
+    return false;
+}
 
-// Moment k of the post-streaming state at global (gx, gy) of physical plane
-// z: own-tile value plus inbound contributions, plus the z-wrap layers.
-template <int D, class TL, class C, class T>
-__device__ __forceinline__ C moment_at(const FusedArgs<C, T> &a, int gx, int gy, int z, int k) {
-    const Grid &g = a.g;
-    const int tx = gx / TL::TX, ty = gy / TL::TY;
-    const int lx = gx - tx * TL::TX, ly = gy - ty * TL::TY;
-    const int w = min(TL::TX, g.nx - tx * TL::TX), h = min(TL::TY, g.ny - ty * TL::TY);
-    const long long plane = (long long)g.nx * g.ny;
-    const long long tile = (long long)ty * a.ntx + tx;
-    auto one = [&](int layer) -> C {
-        C v = a.Mci[((long long)k * a.nlayer + layer) * plane + gx + (long long)g.nx * gy];
-        const C *in = a.INi + ((tile * a.nlayer + layer) * 5 + k) * TL::NR;
-        if (lx == 0) v += in[TL::FROM_L + ly];
-        if (lx == w - 1) v += in[TL::FROM_R + ly];
-        if (ly == 0) v += in[TL::FROM_B + lx];
-        if (ly == h - 1) v += in[TL::FROM_T + lx];
-        if (lx == 0 && ly == 0) v += in[TL::FROM_BL];
-        if (lx == w - 1 && ly == 0) v += in[TL::FROM_BR];
-        if (lx == 0 && ly == h - 1) v += in[TL::FROM_TL];
-        if (lx == w - 1 && ly == h - 1) v += in[TL::FROM_TR];
-        return v;
-    };
-    C v = one(layer_of<D>(z));
-    if (D == 3) {
-        if (z == g.nz - 1) v += one(layer_of<D>(-1));
-        if (z == 0) v += one(layer_of<D>(g.nz));
+// tile owning the ring cell (rx, ry) of tile (tx, ty) and the inbound slot
+// there; false when the ring cell lies beyond a zero-gradient wall
+template <class TL>
+__device__ __forceinline__ bool ring_slot(const Grid &g, int ntx, int nty, int tx, int ty, int w, int h, int rx,
+                                          int ry, int &tile, int &slot) {
+    const int dx = rx < 0 ? -1 : (rx >= w ? 1 : 0);
+    const int dy = ry < 0 ? -1 : (ry >= h ? 1 : 0);
+    int nbx = tx + dx, nby = ty + dy;
+    if (nbx < 0 || nbx >= ntx) {
+        if (g.clampx) return false;
+        nbx = nbx < 0 ? nbx + ntx : nbx - ntx;
     }
+    if (nby < 0 || nby >= nty) {
+        if (g.clampy) return false;
+        nby = nby < 0 ? nby + nty : nby - nty;
+    }
+    if (dy == 0) slot = dx < 0 ? TL::FROM_R + ry : TL::FROM_L + ry;
+    else if (dx == 0) slot = dy < 0 ? TL::FROM_T + rx : TL::FROM_B + rx;
+    else if (dx < 0) slot = dy < 0 ? TL::FROM_TR : TL::FROM_BR;
+    else slot = dy < 0 ? TL::FROM_TL : TL::FROM_BL;
+    tile = nby * ntx + nbx;
+    return true;
+}
+
+// sum of the inbound slots of tile-local cell (lx, ly) of a w x h tile; `in`
+// points at the slots of one (tile, layer, moment)
+template <class TL, class C>
+__device__ __forceinline__ C inbound_sum(const C *in, int lx, int ly, int w, int h) {
+    C v = 0;
+    if (lx == 0) v += in[TL::FROM_L + ly];
+    if (lx == w - 1) v += in[TL::FROM_R + ly];
+    if (ly == 0) v += in[TL::FROM_B + lx];
+    if (ly == h - 1) v += in[TL::FROM_T + lx];
+    if (lx == 0 && ly == 0) v += in[TL::FROM_BL];
+    if (lx == w - 1 && ly == 0) v += in[TL::FROM_BR];
+    if (lx == 0 && ly == h - 1) v += in[TL::FROM_TL];
+    if (lx == w - 1 && ly == h - 1) v += in[TL::FROM_TR];
     return v;
 }
 
@@ -107,475 +151,825 @@ __device__ __forceinline__ int axis_eff(int t0, int rel, int n, int clamp) {
     return v < 0 ? -t0 : (v >= n ? n - 1 - t0 : rel);
 }
 
-template <int D, class S, class TL, bool MLP>
-__global__ void __launch_bounds__(TL::NT) k_fused(FusedArgs<typename S::C, typename S::T> a) {
-    using C = typename S::C;
-    using T = typename S::T;
+// gather source of destination offset d (tile-local) for velocity component
+// c along an axis: d - c, or d itself on a zero-gradient wall when c points
+// inward (pull with clamped index); -1 when the source is outside the tile
+__device__ __forceinline__ int gather_src(int d, int c, int t0, int n, int clamp, int extent) {
+    const int gd = t0 + d;
+    const int s = (clamp && ((gd == 0 && c == 1) || (gd == n - 1 && c == -1))) ? d : d - c;
+    return (s >= 0 && s < extent) ? s : -1;
+}
+
+// Inputs of one cell's collision (eqs. sh_vel_1, sh_temp_1, sh_T_1, qc_1,
+// correction) gathered from the field pipeline.
+template <class C> struct CollideIn {
+    C rho, P, T, cs2;
+    C u[3], F[3];
+    C du;                 // divergence of u, central differences
+    C dh[3], dT[3];       // central differences of h and T
+    C L0[3], Lm[3], Lp[3];  // Lambda_a at the cell and its -/+ neighbours along a
+};
+
+// Relax f, g in place to the post-collision populations (eqs. fLBGK, gLBGK
+// with the attractors of eqs. LBMeq, LBMstar, LBMeqG, LBMgstar).
+template <int D, class C>
+__device__ __forceinline__ void collide_cell(const Phys<C> &ph, const CollideIn<C> &in, C *f, C *g) {
     constexpr int Q = Lattice<D>::Q;
-    constexpr int NZ3 = D == 3 ? 3 : 1;
-    constexpr int NZ2 = D == 3 ? 2 : 1;
-    constexpr int TX = TL::TX, TY = TL::TY, NT = TL::NT;
-    // ring fields on R1: u_x, u_y, T, h, Lambda_x, Lambda_y
-    // centre fields on tile cells: rho, u_z, F_x, F_y, F_z, P, c_s^2, Lambda_z
-    enum { RUX, RUY, RT, RH, RLX, RLY, NRF };
-    enum { CRHO, CUZ, CFX, CFY, CFZ, CP, CCS, CLZ, NCF };
-    __shared__ C sRho[NZ3][TL::R3];
-    __shared__ C sLap[NZ3][TL::R2];
-    __shared__ C sRing[NZ2][NRF][TL::R1];
-    __shared__ C sCen[NZ2][NCF][NT];
-    __shared__ C sZm[4][NT];  // plane z-1: u_z, T, h, Lambda_z
-    __shared__ C sAcc[NZ3][5][TL::R1];
-    __shared__ C sX[9][NT];   // exchange of pushed populations; j, G staging before that
-
-    const Grid &g = a.g;
-    const long long N = g.N;
-    const int tid = threadIdx.x;
-    const int bx = blockIdx.x, by = blockIdx.y;
-    const int x0 = bx * TX, y0 = by * TY;
-    const int w = min(TX, g.nx - x0), h = min(TY, g.ny - y0);
-    const int lx = tid % TX, ly = tid / TX;
-    const bool own = lx < w && ly < h;
-    const int nz = g.nz;
-
-    auto zslot3 = [](int p) { return ((p % 3) + 3) % 3; };
-    auto zslot2 = [](int p) { return p & 1; };
-    auto zphys = [&](int p) { int v = p % nz; return v < 0 ? v + nz : v; };
-
-    // rho of logical plane p on R3
-    auto load_rho = [&](int p) {
-        const int zp = D == 3 ? zphys(p) : 0;
-        C *dst = sRho[D == 3 ? zslot3(p) : 0];
-        for (int r = tid; r < TL::R3; r += NT) {
-            const int i = r % TL::W3 - 3, j = r / TL::W3 - 3;
-            const int gx = axis_global(x0, i, g.nx, g.clampx), gy = axis_global(y0, j, g.ny, g.clampy);
-            dst[r] = moment_at<D, TL>(a, gx, gy, zp, 0);
-        }
-    };
-    // Laplacian of logical plane p on R2
-    auto make_lap = [&](int p) {
-        const C *rc = sRho[D == 3 ? zslot3(p) : 0];
-        const C *rm = sRho[D == 3 ? zslot3(p - 1) : 0];
-        const C *rp = sRho[D == 3 ? zslot3(p + 1) : 0];
-        C *dst = sLap[D == 3 ? zslot3(p) : 0];
-        for (int r = tid; r < TL::R2; r += NT) {
-            const int i = axis_eff(x0, r % TL::W2 - 2, g.nx, g.clampx) + 3;
-            const int j = axis_eff(y0, r / TL::W2 - 2, g.ny, g.clampy) + 3;
-            const int c = j * TL::W3 + i;
-            C s = rc[c + 1] + rc[c - 1] - C(2) * rc[c] + rc[c + TL::W3] + rc[c - TL::W3] - C(2) * rc[c];
-            if (D == 3) s += rp[c] + rm[c] - C(2) * rc[c];
-            dst[r] = s;
-        }
-    };
-    // j, G of logical plane p on R1 into the staging area (sX)
-    C *sJG = &sX[0][0];  // 4 x R1 values
-    static_assert(4 * TL::R1 <= 9 * NT, "staging area too small");
-    auto load_jg = [&](int p) {
-        const int zp = D == 3 ? zphys(p) : 0;
-        for (int r = tid; r < TL::R1; r += NT) {
-            const int i = r % TL::W1 - 1, j = r / TL::W1 - 1;
-            const int gx = axis_global(x0, i, g.nx, g.clampx), gy = axis_global(y0, j, g.ny, g.clampy);
-            for (int k = 0; k < 4; k++)
-                sJG[k * TL::R1 + r] = moment_at<D, TL>(a, gx, gy, zp, 1 + k);
-        }
-    };
-    // F, u, E, T, P, h, Lambda, c_s^2 of logical plane p on R1.  The loop is
-    // uniform per wavefront (the surrogate evaluates 64 cells per wave).
-    auto make_fields = [&](int p) {
-        const C *lc = sLap[D == 3 ? zslot3(p) : 0];
-        const C *lm = sLap[D == 3 ? zslot3(p - 1) : 0];
-        const C *lp = sLap[D == 3 ? zslot3(p + 1) : 0];
-        const C *rc = sRho[D == 3 ? zslot3(p) : 0];
-        const int s2 = D == 3 ? zslot2(p) : 0;
-        const int lane = tid & 63;
-        for (int r0 = tid - lane; r0 < TL::R1; r0 += NT) {
-            const bool act = r0 + lane < TL::R1;
-            const int r = act ? r0 + lane : TL::R1 - 1;
-            const int ri = r % TL::W1 - 1, rj = r / TL::W1 - 1;
-            const int ei = axis_eff(x0, ri, g.nx, g.clampx), ej = axis_eff(y0, rj, g.ny, g.clampy);
-            const int c2 = (ej + 2) * TL::W2 + ei + 2;
-            const int c1 = (ej + 1) * TL::W1 + ei + 1;
-            const C rho = rc[(ej + 3) * TL::W3 + ei + 3];
-            const C inv_rho = C(1) / rho;
-            C F[3], u[3], uF = 0, u2 = 0;
-            F[0] = a.ph.kappa * rho * C(0.5) * (lc[c2 + 1] - lc[c2 - 1]);
-            F[1] = a.ph.kappa * rho * C(0.5) * (lc[c2 + TL::W2] - lc[c2 - TL::W2]);
-            F[2] = D == 3 ? a.ph.kappa * rho * C(0.5) * (lp[c2] - lm[c2]) : C(0);
-            for (int d = 0; d < D; d++) {
-                u[d] = (sJG[d * TL::R1 + c1] + C(0.5) * F[d]) * inv_rho;
-                uF += u[d] * F[d];
-                u2 += u[d] * u[d];
-            }
-            if (D == 2) u[2] = 0;
-            const C E = (sJG[3 * TL::R1 + c1] + C(0.5) * uF) * inv_rho;
-            const C e = E - C(0.5) * u2;
-            C Tt, P, cs2;
-            if constexpr (MLP) {
-                // surrogate temperature, accepted when the caloric residual
-                // |e(rho, T_hat) - e| / (c_v T_hat) is within the threshold;
-                // otherwise one FP64 Newton step on e(rho, T) = e (exact for
-                // van der Waals).  P and c_s^2 from the EOS at the accepted T.
-                float x0n, x1n, yh[1];
-                mlp::normalise(a.mlpNorm, (float)rho, (float)e, x0n, x1n);
-                mlp::forward_wave<1>(x0n, x1n, a.mlpP, a.mlpW2b, yh);
-                float Th = yh[0] * a.mlpNorm[5] + a.mlpNorm[4];
-                const float res = fabsf((float)a.ph.cv * Th - (float)a.ph.a * (float)rho - (float)e) /
-                                  ((float)a.ph.cv * fabsf(Th));
-                const bool fb = !(res <= a.mlpTol);
-                if (fb) {
-                    double Td = (double)Th;
-                    Td = Td - ((double)a.ph.cv * Td - (double)a.ph.a * (double)rho - (double)e) / (double)a.ph.cv;
-                    Th = (float)Td;
-                }
-                Tt = (C)Th;
-                const unsigned long long nfb = __popcll(__ballot(fb && act));
-                const unsigned long long nact = __popcll(__ballot(act));
-                if (lane == 0) {
-                    atomicAdd(&a.mlpCount[0], nfb);
-                    atomicAdd(&a.mlpCount[1], nact);
-                }
-            } else {
-                Tt = (e + a.ph.a * rho) * a.ph.inv_cv;  // eq. lbm_temp
-            }
-            P = vdw_pressure(a.ph, rho, Tt);
-            cs2 = vdw_cs2(a.ph, rho, Tt);
-            if (!act) continue;
-            const C theta = P * inv_rho;
-            C Lam[3];
-            for (int d = 0; d < 3; d++) Lam[d] = rho * u[d] * (u[d] * u[d] + C(3) * (theta - C(1.0 / 3.0)));
-            sRing[s2][RUX][r] = u[0];
-            sRing[s2][RUY][r] = u[1];
-            sRing[s2][RT][r] = Tt;
-            sRing[s2][RH][r] = e + theta;
-            sRing[s2][RLX][r] = Lam[0];
-            sRing[s2][RLY][r] = Lam[1];
-            if (ri >= 0 && ri < TX && rj >= 0 && rj < TY) {
-                const int t = rj * TX + ri;
-                sCen[s2][CRHO][t] = rho;
-                sCen[s2][CUZ][t] = u[2];
-                sCen[s2][CFX][t] = F[0];
-                sCen[s2][CFY][t] = F[1];
-                sCen[s2][CFZ][t] = F[2];
-                sCen[s2][CP][t] = P;
-                sCen[s2][CCS][t] = cs2;
-                sCen[s2][CLZ][t] = Lam[2];
-            }
-        }
-    };
-    // write the completed moment sums of logical plane p (tile cells to Mc,
-    // ring cells to the neighbours' inbound slots), then clear the slot
-    auto flush = [&](int p) {
-        C *acc = &sAcc[D == 3 ? zslot3(p) : 0][0][0];
-        const int layer = layer_of<D>(p);
-        const int zw = D == 3 ? zphys(p) : 0;
-        (void)zw;
-        const long long plane = (long long)g.nx * g.ny;
-        for (int r = tid; r < TL::R1; r += NT) {
-            const int rx = r % TL::W1 - 1, ry = r / TL::W1 - 1;
-            const bool inx = rx >= 0 && rx < w, iny = ry >= 0 && ry < h;
-            if (inx && iny) {
-                const long long cell = (long long)(x0 + rx) + (long long)g.nx * (y0 + ry);
-                for (int k = 0; k < 5; k++) a.Mco[((long long)k * a.nlayer + layer) * plane + cell] = acc[k * TL::R1 + r];
-            } else if ((rx >= -1 && rx <= w) && (ry >= -1 && ry <= h)) {
-                // neighbour tile and its inbound slot
-                int dx = rx < 0 ? -1 : (rx >= w ? 1 : 0);
-                int dy = ry < 0 ? -1 : (ry >= h ? 1 : 0);
-                int nbx = bx + dx, nby = by + dy;
-                bool ok = true;
-                if (nbx < 0 || nbx >= a.ntx) {
-                    if (g.clampx) ok = false;
-                    else nbx = (nbx + a.ntx) % a.ntx;
-                }
-                if (nby < 0 || nby >= a.nty) {
-                    if (g.clampy) ok = false;
-                    else nby = (nby + a.nty) % a.nty;
-                }
-                if (ok) {
-                    int slot;
-                    if (dy == 0) slot = dx < 0 ? TL::FROM_R + ry : TL::FROM_L + ry;
-                    else if (dx == 0) slot = dy < 0 ? TL::FROM_T + rx : TL::FROM_B + rx;
-                    else if (dx < 0) slot = dy < 0 ? TL::FROM_TR : TL::FROM_BR;
-                    else slot = dy < 0 ? TL::FROM_TL : TL::FROM_BL;
-                    const long long tile = (long long)nby * a.ntx + nbx;
-                    for (int k = 0; k < 5; k++)
-                        a.INo[((tile * a.nlayer + layer) * 5 + k) * TL::NR + slot] = acc[k * TL::R1 + r];
-                }
-            }
-            for (int k = 0; k < 5; k++) acc[k * TL::R1 + r] = C(0);
-        }
-    };
-
-    // -- clear the accumulators ------------------------------------------------
-    for (int r = tid; r < NZ3 * 5 * TL::R1; r += NT) (&sAcc[0][0][0])[r] = C(0);
-
-    // -- prologue --------------------------------------------------------------
-    if (D == 3) {
-        load_rho(-3);
-        load_rho(-2);
-        load_rho(-1);
-        __syncthreads();
-        make_lap(-2);
-        __syncthreads();
-        load_rho(0);
-        __syncthreads();
-        make_lap(-1);
-        __syncthreads();
-        load_rho(1);
-        __syncthreads();
-        make_lap(0);
-        load_jg(-1);
-        __syncthreads();
-        make_fields(-1);
-        __syncthreads();
-        load_rho(2);
-        __syncthreads();
-        make_lap(1);
-        load_jg(0);
-        __syncthreads();
-        make_fields(0);
-        __syncthreads();
-    } else {
-        load_rho(0);
-        load_jg(0);
-        __syncthreads();
-        make_lap(0);
-        __syncthreads();
-        make_fields(0);
-        __syncthreads();
+    const C rho = in.rho, P = in.P, Tt = in.T;
+    const C inv_rho = C(1) / rho;
+    const C theta = P * inv_rho;
+    C qc[3], Phi[3], FF = 0;
+    for (int d = 0; d < D; d++) {
+        FF += in.F[d] * in.F[d];
+        qc[d] = P * (in.dh[d] - ph.k_over_mu * in.dT[d]);
+        C dL;
+        if (in.u[d] > ph.sgn_eps) dL = in.L0[d] - in.Lm[d];
+        else if (in.u[d] < -ph.sgn_eps) dL = in.Lp[d] - in.L0[d];
+        else dL = C(0.5) * (in.Lp[d] - in.Lm[d]);
+        Phi[d] = -dL * inv_rho;
     }
-
-    const int zend = D == 3 ? nz : 1;
-    for (int z = 0; z < zend; z++) {
-        // own populations of plane z (issued before the field pipeline)
-        C fown[Q], gown[Q];
-        const long long cell = (long long)(x0 + (own ? lx : 0)) + (long long)g.nx * ((y0 + (own ? ly : 0)) + (long long)g.ny * z);
+    const C beta = P / (P + C(2) * ph.mu);
+    const C alpha = C(D + 2) / C(D) - rho * in.cs2 / P - ph.eta_over_mu;
+    const C thetas = theta + alpha * theta * in.du;
+    const C Ts = Tt - FF * inv_rho * inv_rho * C(0.5) * ph.inv_cv;
+    const C e = ph.cv * Tt - ph.a * rho;
+    const C es = ph.cv * Ts - ph.a * rho;
+    const C eps_eq = e - C(0.5 * D) * theta;
+    const C eps_st = es - C(0.5 * D) * thetas;
+    AxisEq<C> eq[3], st[3];
+    Axis3<C> pf[3];
+    for (int d = 0; d < D; d++) {
+        const C us = in.u[d] + in.F[d] * inv_rho;
+        eq[d] = axis_eq(in.u[d], theta);
+        st[d] = axis_eq(us, thetas);
+        pf[d] = psi3(us, thetas + us * us + Phi[d]);
+    }
+    const C w_keep = C(1) - C(2) * beta, w_eq = C(3) * beta - C(1), w_st = C(1) - beta;
 #pragma unroll
-        for (int i = 0; i < Q; i++) {
-            fown[i] = S::load(a.fi, i * N + cell, (C)a.ref.f[i]);
-            gown[i] = S::load(a.gi, i * N + cell, (C)a.ref.g[i]);
-        }
-        if (D == 3) {
-            // plane z-1's z-neighbour fields leave the two-slot ring now
-            if (own) {
-                const int sm = zslot2(z - 1);
-                const int c1 = (ly + 1) * TL::W1 + lx + 1;
-                sZm[0][tid] = sCen[sm][CUZ][tid];
-                sZm[1][tid] = sRing[sm][RT][c1];
-                sZm[2][tid] = sRing[sm][RH][c1];
-                sZm[3][tid] = sCen[sm][CLZ][tid];
-            }
-            load_rho(z + 3);
-            __syncthreads();
-            make_lap(z + 2);
-            load_jg(z + 1);
-            __syncthreads();
-            make_fields(z + 1);
-            __syncthreads();
-        }
-
-        // -- collide the own cell of plane z ---------------------------------
-        C fpost[Q], gpost[Q];
-        if (own) {
-            const int s0 = D == 3 ? zslot2(z) : 0, s1 = D == 3 ? zslot2(z + 1) : 0;
-            const int c1 = (ly + 1) * TL::W1 + lx + 1;
-            const C rho = sCen[s0][CRHO][tid], P = sCen[s0][CP][tid], Tt = sRing[s0][RT][c1];
-            const C inv_rho = C(1) / rho;
-            const C theta = P * inv_rho;
-            C u[3] = {sRing[s0][RUX][c1], sRing[s0][RUY][c1], sCen[s0][CUZ][tid]};
-            C F[3] = {sCen[s0][CFX][tid], sCen[s0][CFY][tid], sCen[s0][CFZ][tid]};
-            C Lm[3], Lp[3], L0[3] = {sRing[s0][RLX][c1], sRing[s0][RLY][c1], sCen[s0][CLZ][tid]};
-            C dh[3], dT[3], du = 0;
-            // x, y neighbours from the R1 ring fields
-            du += C(0.5) * (sRing[s0][RUX][c1 + 1] - sRing[s0][RUX][c1 - 1]);
-            du += C(0.5) * (sRing[s0][RUY][c1 + TL::W1] - sRing[s0][RUY][c1 - TL::W1]);
-            dh[0] = C(0.5) * (sRing[s0][RH][c1 + 1] - sRing[s0][RH][c1 - 1]);
-            dh[1] = C(0.5) * (sRing[s0][RH][c1 + TL::W1] - sRing[s0][RH][c1 - TL::W1]);
-            dT[0] = C(0.5) * (sRing[s0][RT][c1 + 1] - sRing[s0][RT][c1 - 1]);
-            dT[1] = C(0.5) * (sRing[s0][RT][c1 + TL::W1] - sRing[s0][RT][c1 - TL::W1]);
-            Lm[0] = sRing[s0][RLX][c1 - 1];
-            Lp[0] = sRing[s0][RLX][c1 + 1];
-            Lm[1] = sRing[s0][RLY][c1 - TL::W1];
-            Lp[1] = sRing[s0][RLY][c1 + TL::W1];
-            if (D == 3) {
-                du += C(0.5) * (sCen[s1][CUZ][tid] - sZm[0][tid]);
-                dT[2] = C(0.5) * (sRing[s1][RT][c1] - sZm[1][tid]);
-                dh[2] = C(0.5) * (sRing[s1][RH][c1] - sZm[2][tid]);
-                Lm[2] = sZm[3][tid];
-                Lp[2] = sCen[s1][CLZ][tid];
-            }
-            C qc[3], Phi[3], FF = 0;
-            for (int d = 0; d < D; d++) {
-                FF += F[d] * F[d];
-                qc[d] = P * (dh[d] - a.ph.k_over_mu * dT[d]);
-                C dL;
-                if (u[d] > a.ph.sgn_eps) dL = L0[d] - Lm[d];
-                else if (u[d] < -a.ph.sgn_eps) dL = Lp[d] - L0[d];
-                else dL = C(0.5) * (Lp[d] - Lm[d]);
-                Phi[d] = -dL * inv_rho;
-            }
-            const C beta = P / (P + C(2) * a.ph.mu);
-            const C alpha = C(D + 2) / C(D) - rho * sCen[s0][CCS][tid] / P - a.ph.eta_over_mu;
-            const C thetas = theta + alpha * theta * du;
-            const C Ts = Tt - FF * inv_rho * inv_rho * C(0.5) * a.ph.inv_cv;
-            const C e = a.ph.cv * Tt - a.ph.a * rho;
-            const C es = a.ph.cv * Ts - a.ph.a * rho;
-            const C eps_eq = e - C(0.5 * D) * theta;
-            const C eps_st = es - C(0.5 * D) * thetas;
-            AxisEq<C> eq[3], st[3];
-            Axis3<C> pf[3];
-            for (int d = 0; d < D; d++) {
-                const C us = u[d] + F[d] * inv_rho;
-                eq[d] = axis_eq(u[d], theta);
-                st[d] = axis_eq(us, thetas);
-                pf[d] = psi3(us, thetas + us * us + Phi[d]);
-            }
-            const C w_keep = C(1) - C(2) * beta, w_eq = C(3) * beta - C(1), w_st = C(1) - beta;
-#pragma unroll
-            for (int i = 0; i < Q; i++) {
-                const int ix = cx_of(i), iy = cy_of(i), iz = D == 3 ? cz_of(i) : 0;
-                const C px = pick(eq[0].p, ix), py = pick(eq[1].p, iy);
-                const C qx = pick(eq[0].q, ix), qy = pick(eq[1].q, iy);
-                const C sx = pick(st[0].p, ix), sy = pick(st[1].p, iy);
-                const C tx = pick(st[0].q, ix), ty = pick(st[1].q, iy);
-                const C fsx = pick(pf[0], ix), fsy = pick(pf[1], iy);
-                C feq, geqs, fst, gsts, sp;
-                if (D == 2) {
-                    feq = rho * px * py;
-                    geqs = qx * py + px * qy;
-                    fst = rho * fsx * fsy;
-                    gsts = tx * sy + sx * ty;
-                    sp = sx * sy;
-                } else {
-                    const C pz = pick(eq[2].p, iz), qz = pick(eq[2].q, iz);
-                    const C sz = pick(st[2].p, iz), tz = pick(st[2].q, iz);
-                    feq = rho * px * py * pz;
-                    geqs = (qx * py + px * qy) * pz + px * py * qz;
-                    fst = rho * fsx * fsy * pick(pf[2], iz);
-                    gsts = (tx * sy + sx * ty) * sz + sx * sy * tz;
-                    sp = sx * sy * sz;
-                }
-                const C geq = feq * eps_eq + C(0.5) * rho * geqs;
-                C gst = rho * sp * eps_st + C(0.5) * rho * gsts;
-                if (csq_of<D>(i) == 1) {
-                    const C cq = ix ? (ix > 0 ? qc[0] : -qc[0]) : (iy ? (iy > 0 ? qc[1] : -qc[1]) : (iz > 0 ? qc[2] : -qc[2]));
-                    gst += C(0.5) * cq;
-                }
-                fpost[i] = w_keep * fown[i] + w_eq * feq + w_st * fst;
-                gpost[i] = w_keep * gown[i] + w_eq * geq + w_st * gst;
-            }
-            // stream: push to x + c_i of the other buffer (plane z + c_z wraps)
-            const int gx = x0 + lx, gy = y0 + ly;
-#pragma unroll
-            for (int i = 0; i < Q; i++) {
-                const int ix = cx_of(i), iy = cy_of(i), iz = D == 3 ? cz_of(i) : 0;
-                const T fe = S::enc(fpost[i], (C)a.ref.f[i]), ge = S::enc(gpost[i], (C)a.ref.g[i]);
-                int dx[2], dy[2];
-                const int nxd = push_axis(gx, ix, g.nx, g.clampx, dx);
-                const int nyd = push_axis(gy, iy, g.ny, g.clampy, dy);
-                int dz = z + iz;
-                if (D == 3) dz = dz < 0 ? dz + nz : (dz >= nz ? dz - nz : dz);
-                for (int aa = 0; aa < nxd; aa++)
-                    for (int bb = 0; bb < nyd; bb++) {
-                        const long long d = (long long)dx[aa] + (long long)g.nx * ((long long)dy[bb] + (long long)g.ny * dz);
-                        a.fo[i * N + d] = fe;
-                        a.go[i * N + d] = ge;
-                    }
-                // the stored value is what the next step reads: round the
-                // moment sums through the storage form as well
-                fpost[i] = S::load(&fe, 0, (C)a.ref.f[i]);
-                gpost[i] = S::load(&ge, 0, (C)a.ref.g[i]);
-            }
-        }
-
-        // -- moments of the pushed populations, per destination plane ------
-        for (int cz = (D == 3 ? -1 : 0); cz <= (D == 3 ? 1 : 0); cz++) {
-            C *acc = &sAcc[D == 3 ? zslot3(z + cz) : 0][0][0];
-            for (int pass = 0; pass < 2; pass++) {  // pass 0: f (rho, j); pass 1: g (G)
-                __syncthreads();
-#pragma unroll
-                for (int k = 0; k < 9; k++) {
-                    const int i = k + (D == 3 ? 9 * (cz + 1) : 0);
-                    sX[k][tid] = own ? (pass == 0 ? fpost[i] : gpost[i]) : C(0);
-                }
-                __syncthreads();
-                for (int r = tid; r < TL::R1; r += NT) {
-                    const int rx = r % TL::W1 - 1, ry = r / TL::W1 - 1;
-                    if (rx > w || ry > h) continue;
-                    const bool inx = rx >= 0 && rx < w, iny = ry >= 0 && ry < h;
-                    const bool edge_x0 = g.clampx && inx && x0 + rx == 0;
-                    const bool edge_x1 = g.clampx && inx && x0 + rx == g.nx - 1;
-                    const bool edge_y0 = g.clampy && iny && y0 + ry == 0;
-                    const bool edge_y1 = g.clampy && iny && y0 + ry == g.ny - 1;
-                    C s0 = 0, sjx = 0, sjy = 0;
-                    for (int k = 0; k < 9; k++) {
-                        const int cxk = k % 3 - 1, cyk = k / 3 - 1;
-                        // per-axis source options: normal (d - c) and, on a
-                        // zero-gradient wall with c pointing inward, d itself
-                        int xs[2], ys[2], nxs = 0, nys = 0;
-                        if (rx - cxk >= 0 && rx - cxk < w) xs[nxs++] = rx - cxk;
-                        if ((edge_x0 && cxk == 1) || (edge_x1 && cxk == -1)) xs[nxs++] = rx;
-                        if (ry - cyk >= 0 && ry - cyk < h) ys[nys++] = ry - cyk;
-                        if ((edge_y0 && cyk == 1) || (edge_y1 && cyk == -1)) ys[nys++] = ry;
-                        for (int p = 0; p < nxs; p++)
-                            for (int q = 0; q < nys; q++) {
-                                const C v = sX[k][ys[q] * TX + xs[p]];
-                                s0 += v;
-                                if (pass == 0) {
-                                    if (cxk) sjx += cxk > 0 ? v : -v;
-                                    if (cyk) sjy += cyk > 0 ? v : -v;
-                                }
-                            }
-                    }
-                    if (pass == 0) {
-                        acc[0 * TL::R1 + r] += s0;
-                        acc[1 * TL::R1 + r] += sjx;
-                        acc[2 * TL::R1 + r] += sjy;
-                        if (D == 3 && cz) acc[3 * TL::R1 + r] += cz > 0 ? s0 : -s0;
-                    } else {
-                        acc[4 * TL::R1 + r] += s0;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        if (D == 3) {
-            flush(z - 1);
+    for (int i = 0; i < Q; i++) {
+        const int ix = cx_of(i), iy = cy_of(i), iz = D == 3 ? cz_of(i) : 0;
+        const C px = pick(eq[0].p, ix), py = pick(eq[1].p, iy);
+        const C qx = pick(eq[0].q, ix), qy = pick(eq[1].q, iy);
+        const C sx = pick(st[0].p, ix), sy = pick(st[1].p, iy);
+        const C tx = pick(st[0].q, ix), ty = pick(st[1].q, iy);
+        const C fsx = pick(pf[0], ix), fsy = pick(pf[1], iy);
+        C feq, geqs, fst, gsts, sp;
+        if (D == 2) {
+            feq = rho * px * py;
+            geqs = qx * py + px * qy;
+            fst = rho * fsx * fsy;
+            gsts = tx * sy + sx * ty;
+            sp = sx * sy;
         } else {
-            flush(0);
+            const C pz = pick(eq[2].p, iz), qz = pick(eq[2].q, iz);
+            const C sz = pick(st[2].p, iz), tz = pick(st[2].q, iz);
+            feq = rho * px * py * pz;
+            geqs = (qx * py + px * qy) * pz + px * py * qz;
+            fst = rho * fsx * fsy * pick(pf[2], iz);
+            gsts = (tx * sy + sx * ty) * sz + sx * sy * tz;
+            sp = sx * sy * sz;
         }
-        __syncthreads();
-    }
-    if (D == 3) {
-        flush(nz - 1);
-        __syncthreads();
-        flush(nz);
+        const C geq = feq * eps_eq + C(0.5) * rho * geqs;
+        C gst = rho * sp * eps_st + C(0.5) * rho * gsts;
+        if (csq_of<D>(i) == 1) {
+            const C cq = ix ? (ix > 0 ? qc[0] : -qc[0]) : (iy ? (iy > 0 ? qc[1] : -qc[1]) : (iz > 0 ? qc[2] : -qc[2]));
+            gst += C(0.5) * cq;
+        }
+        f[i] = w_keep * f[i] + w_eq * feq + w_st * fst;
+        g[i] = w_keep * g[i] + w_eq * geq + w_st * gst;
     }
 }
 
-// complete moments of a state (after init or set_populations): layer of
-// plane z; the wrap layers and inbound slots are cleared separately
+// element at a 32-bit byte offset from a uniform base: the addressing form
+// global memory instructions take directly (SGPR base + VGPR offset), which
+// also keeps the compiler from holding per-lane 64-bit addresses
+template <class P> __device__ __forceinline__ P &at_bytes(P *base, unsigned off) {
+    return *(P *)((char *)base + off);
+}
+template <class P> __device__ __forceinline__ const P &at_bytes(const P *base, unsigned off) {
+    return *(const P *)((const char *)base + off);
+}
+
+// fields of one plane's cell kept in registers between marching positions
+template <class C> struct CenterF {
+    C rho, uz, F[3], P, cs2, T, h, Lz;
+};
+
+template <int D, class S, class TL, bool MLP>
+__global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, typename S::T> a) {
+    using C = typename S::C;
+    using T = typename S::T;
+    constexpr int Q = Lattice<D>::Q;
+    constexpr int TX = TL::TX, TY = TL::TY, NT = TL::NT;
+    constexpr int NRS = D == 3 ? 4 : 1;  // rho planes held in LDS
+    constexpr int NLS = D == 3 ? 4 : 1;  // Laplacian planes
+    constexpr int NFS = D == 3 ? 2 : 1;  // ring-field planes
+    constexpr int XS = NT + 1;           // exchange row: NT cells, then a zero
+    constexpr int NR3 = (TL::R3 + NT - 1) / NT;
+    constexpr int NR2 = (TL::R2 + NT - 1) / NT;
+    // ring fields on R1 (x, y neighbours of the collision): u_x, u_y, T, h,
+    // Lambda_x, Lambda_y
+    enum { RUX, RUY, RT, RH, RLX, RLY, NRF };
+    __shared__ C sRho[NRS][TL::R3];
+    __shared__ C sLap[NLS][TL::R2];
+    __shared__ C sRing[NFS][NRF][TL::R1];
+    __shared__ C sX[2][18][XS];
+    __shared__ C sRacc[D == 3 ? 3 : 1][5][TL::NR];  // moment sums of the ring destinations, by plane
+
+    const Grid &g = a.g;
+    const long long N = g.N;
+    const long long plane = (long long)g.nx * g.ny;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+
+    // -- tile and segment of this workgroup ----------------------------------
+    const int b = blockIdx.x;
+    const int L = a.chunk ? (b & 7) * a.chunk + (b >> 3) : b;
+    const int tx = L % a.ntx, ty = (L / a.ntx) % a.nty, seg = L / (a.ntx * a.nty);
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int w = min(TX, g.nx - x0), h = min(TY, g.ny - y0);
+    const int nz = g.nz;
+    const int z0 = D == 3 ? seg_lo(seg, nz, a.nseg) : 0;
+    const int z1 = D == 3 ? seg_lo(seg + 1, nz, a.nseg) : 1;
+
+    // -- z-invariant per-thread set-up ---------------------------------------
+    const int lx = tid % TX, ly = tid / TX;
+    const bool own = lx < w && ly < h;
+    const int gx = x0 + min(lx, w - 1), gy = y0 + min(ly, h - 1);
+    // per-lane offsets are unsigned 32-bit so that loads and stores take a
+    // uniform 64-bit base plus a zero-extended lane offset
+    const unsigned own_off = (unsigned)(gx + g.nx * gy);
+    const int c3o = (ly + 3) * TL::W3 + lx + 3, c2o = (ly + 2) * TL::W2 + lx + 2, c1o = (ly + 1) * TL::W1 + lx + 1;
+
+    int rx = 0, ry = 0;
+    const bool ring = ring_pos(tid, w, h, rx, ry);
+    const int nring = 2 * (w + 2) + 2 * h;
+    int rtile = 0, rslot = 0;
+    const bool ring_dst = ring && ring_slot<TL>(g, a.ntx, a.nty, tx, ty, w, h, rx, ry, rtile, rslot);
+    unsigned ring_off = own_off;
+    int c3r = c3o, c2r = c2o, c1r = c1o;
+    if (ring) {
+        const int ex = axis_eff(x0, rx, g.nx, g.clampx), ey = axis_eff(y0, ry, g.ny, g.clampy);
+        ring_off = (unsigned)(axis_global(x0, rx, g.nx, g.clampx) + g.nx * axis_global(y0, ry, g.ny, g.clampy));
+        c3r = (ey + 3) * TL::W3 + ex + 3;
+        c2r = (ey + 2) * TL::W2 + ex + 2;
+        c1r = (ry + 1) * TL::W1 + rx + 1;
+    }
+    // rho of the R3 region: plane offsets of this thread's entries
+    unsigned rho_off[NR3];
+#pragma unroll
+    for (int k = 0; k < NR3; k++) {
+        const int r = min(tid + k * NT, TL::R3 - 1);
+        rho_off[k] = (unsigned)(axis_global(x0, r % TL::W3 - 3, g.nx, g.clampx) +
+                                g.nx * axis_global(y0, r / TL::W3 - 3, g.ny, g.clampy));
+    }
+    // Laplacian on R2: R3 index of the evaluation point
+    int lap_c[NR2];
+#pragma unroll
+    for (int k = 0; k < NR2; k++) {
+        const int r = min(tid + k * NT, TL::R2 - 1);
+        const int ei = axis_eff(x0, r % TL::W2 - 2, g.nx, g.clampx);
+        const int ej = axis_eff(y0, r / TL::W2 - 2, g.ny, g.clampy);
+        lap_c[k] = (ej + 3) * TL::W3 + ei + 3;
+    }
+    // gather sources of the own and the ring destination for the 9 in-plane
+    // directions k = (c_x+1)+3(c_y+1): byte offsets into an exchange row (NT =
+    // the zero entry), two 16-bit offsets per register
+    unsigned so[5] = {0, 0, 0, 0, 0}, sr[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        const int cx = k % 3 - 1, cy = k / 3 - 1;
+        int sx = gather_src(lx, cx, x0, g.nx, g.clampx, w), sy = gather_src(ly, cy, y0, g.ny, g.clampy, h);
+        const unsigned vo = (unsigned)((own && sx >= 0 && sy >= 0) ? sy * TX + sx : NT) * sizeof(C);
+        sx = gather_src(rx, cx, x0, g.nx, g.clampx, w);
+        sy = gather_src(ry, cy, y0, g.ny, g.clampy, h);
+        const unsigned vr = (unsigned)((ring_dst && sx >= 0 && sy >= 0) ? sy * TX + sx : NT) * sizeof(C);
+        so[k / 2] |= vo << (16 * (k & 1));
+        sr[k / 2] |= vr << (16 * (k & 1));
+    }
+    static_assert((NT + 1) * sizeof(C) < 65536, "16-bit exchange offsets");
+    // push destinations of the own cell per axis (-1: none) and the
+    // zero-gradient duplicates (bit c+1 set: c also lands on the cell itself)
+    int xd[3], yd[3], xdup = 0, ydup = 0;
+#pragma unroll
+    for (int c = -1; c <= 1; c++) {
+        int p = gx + c;
+        if (!g.clampx) p = p < 0 ? p + g.nx : (p >= g.nx ? p - g.nx : p);
+        xd[c + 1] = (p >= 0 && p < g.nx) ? p : -1;
+        if (g.clampx && ((gx == 0 && c == 1) || (gx == g.nx - 1 && c == -1))) xdup |= 1 << (c + 1);
+        p = gy + c;
+        if (!g.clampy) p = p < 0 ? p + g.ny : (p >= g.ny ? p - g.ny : p);
+        yd[c + 1] = (p >= 0 && p < g.ny) ? p : -1;
+        if (g.clampy && ((gy == 0 && c == 1) || (gy == g.ny - 1 && c == -1))) ydup |= 1 << (c + 1);
+    }
+    const bool has_dup = own && (xdup | ydup);
+
+    auto zwrap = [&](int p) { return D == 3 ? (p < 0 ? p + nz * (1 + (-p - 1) / nz) : p % nz) : 0; };
+    auto s4 = [](int p) { return D == 3 ? p & 3 : 0; };
+    auto s2 = [](int p) { return D == 3 ? p & 1 : 0; };
+    auto s3 = [](int p) { return D == 3 ? ((p % 3) + 3) % 3 : 0; };
+    // moment k of plane zp at lane offset `off` (cells)
+    auto mom = [&](int k, int zp, unsigned off) -> C {
+        return at_bytes(a.Mci + (long long)k * a.nlay * plane, ((unsigned)zp * (unsigned)plane + off) * (unsigned)sizeof(C));
+    };
+
+    // zero columns of the exchange buffers, ring accumulators
+    if (tid < 36) (&sX[0][0][0])[tid * XS + NT] = C(0);
+    for (int r = tid; r < (D == 3 ? 3 : 1) * 5 * TL::NR; r += NT) (&sRacc[0][0][0])[r] = C(0);
+
+    // -- pipeline stages -----------------------------------------------------
+    auto load_rho_regs = [&](int p, C *v) {
+        const int zp = zwrap(p);
+#pragma unroll
+        for (int k = 0; k < NR3; k++) v[k] = mom(0, zp, rho_off[k]);
+    };
+    auto store_rho = [&](int p, const C *v) {
+        C *dst = sRho[s4(p)];
+#pragma unroll
+        for (int k = 0; k < NR3; k++)
+            if (tid + k * NT < TL::R3) dst[tid + k * NT] = v[k];
+    };
+    auto load_jg = [&](int p, C *jo, C *jr) {
+        const int zp = zwrap(p);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            jo[k] = mom(1 + k, zp, own_off);
+            jr[k] = mom(1 + k, zp, ring_off);
+        }
+    };
+    auto make_lap = [&](int p) {
+        const C *rc = sRho[s4(p)];
+        const C *rm = sRho[s4(p - 1)];
+        const C *rp = sRho[s4(p + 1)];
+        C *dst = sLap[s4(p)];
+#pragma unroll
+        for (int k = 0; k < NR2; k++) {
+            if (tid + k * NT >= TL::R2) continue;
+            const int c = lap_c[k];
+            const C r0 = rc[c];
+            C s = rc[c + 1] + rc[c - 1] - C(2) * r0 + rc[c + TL::W3] + rc[c - TL::W3] - C(2) * r0;
+            if (D == 3) s += rp[c] + rm[c] - C(2) * r0;
+            dst[tid + k * NT] = s;
+        }
+    };
+
+    unsigned long long n_fb = 0, n_eval = 0;  // surrogate statistics (lane 0 of each wave)
+    // surrogate: the small layers in LDS, the hidden weights (BF16) in global
+    // memory
+    __shared__ float sNet[MLP ? mlp::OFF_W2 + 2 * mlp::H + 2 : 1];
+    mlp::Net net{};
+    if constexpr (MLP) {
+        for (int r = tid; r < mlp::OFF_W2; r += NT) sNet[r] = a.mlpP[r];
+        for (int r = tid; r < 2 * mlp::H + 1; r += NT) sNet[mlp::OFF_W2 + r] = a.mlpP[mlp::OFF_B2 + r];
+        net = mlp::Net{sNet + mlp::OFF_W1, sNet + mlp::OFF_B1, a.mlpW2b, nullptr, sNet + mlp::OFF_W2,
+                       sNet + mlp::OFF_W2 + mlp::H, sNet + mlp::OFF_W2 + 2 * mlp::H};
+    }
+    // fields of logical plane p at one cell: R3 index c3, R2 index c2 of the
+    // evaluation point, j, G of the cell.  With MLP the call is collective
+    // over the wavefront.
+    auto eval_cell = [&](int p, int c3, int c2, const C *jg, bool act, C u[3], C F[3], C &rho, C &Tt, C &P,
+                         C &cs2, C &hh, C Lam[3]) {
+        const C *lc = sLap[s4(p)];
+        const C *lm = sLap[s4(p - 1)];
+        const C *lp = sLap[s4(p + 1)];
+        rho = sRho[s4(p)][c3];
+        const C inv_rho = C(1) / rho;
+        C uF = 0, u2 = 0;
+        F[0] = a.ph.kappa * rho * C(0.5) * (lc[c2 + 1] - lc[c2 - 1]);
+        F[1] = a.ph.kappa * rho * C(0.5) * (lc[c2 + TL::W2] - lc[c2 - TL::W2]);
+        F[2] = D == 3 ? a.ph.kappa * rho * C(0.5) * (lp[c2] - lm[c2]) : C(0);
+        for (int d = 0; d < 3; d++) {
+            u[d] = d < D ? (jg[d] + C(0.5) * F[d]) * inv_rho : C(0);
+            uF += u[d] * F[d];
+            u2 += u[d] * u[d];
+        }
+        const C E = (jg[3] + C(0.5) * uF) * inv_rho;
+        const C e = E - C(0.5) * u2;
+        if constexpr (MLP) {
+            // surrogate temperature, accepted when the caloric residual
+            // |e(rho, T_hat) - e| / (c_v T_hat) is within the threshold;
+            // otherwise one FP64 Newton step on e(rho, T) = e (exact for
+            // van der Waals).  P and c_s^2 from the EOS at the accepted T.
+            float x0n, x1n, yh[1];
+            mlp::normalise(a.mlpNorm, (float)rho, (float)e, x0n, x1n);
+            mlp::forward_wave<1>(x0n, x1n, net, yh);
+            float Th = yh[0] * a.mlpNorm[5] + a.mlpNorm[4];
+            const float res = fabsf((float)a.ph.cv * Th - (float)a.ph.a * (float)rho - (float)e) /
+                              ((float)a.ph.cv * fabsf(Th));
+            const bool fb = !(res <= a.mlpTol);
+            if (fb) {
+                double Td = (double)Th;
+                Td = Td - ((double)a.ph.cv * Td - (double)a.ph.a * (double)rho - (double)e) / (double)a.ph.cv;
+                Th = (float)Td;
+            }
+            Tt = (C)Th;
+            n_fb += __popcll(__ballot(fb && act));
+            n_eval += __popcll(__ballot(act));
+        } else {
+            Tt = (e + a.ph.a * rho) * a.ph.inv_cv;  // eq. lbm_temp
+        }
+        P = vdw_pressure(a.ph, rho, Tt);
+        cs2 = vdw_cs2(a.ph, rho, Tt);
+        const C theta = P * inv_rho;
+        for (int d = 0; d < 3; d++) Lam[d] = rho * u[d] * (u[d] * u[d] + C(3) * (theta - C(1.0 / 3.0)));
+        hh = e + theta;
+    };
+    // fields of plane p for the own cell (into cf) and the ring cell
+    auto make_fields = [&](int p, const C *jo, const C *jr, CenterF<C> &cf) {
+        C *rf = &sRing[s2(p)][0][0];
+        {
+            C u[3], F[3], rho, Tt, P, cs2, hh, Lam[3];
+            eval_cell(p, c3o, c2o, jo, own, u, F, rho, Tt, P, cs2, hh, Lam);
+            if (own) {
+                rf[RUX * TL::R1 + c1o] = u[0];
+                rf[RUY * TL::R1 + c1o] = u[1];
+                rf[RT * TL::R1 + c1o] = Tt;
+                rf[RH * TL::R1 + c1o] = hh;
+                rf[RLX * TL::R1 + c1o] = Lam[0];
+                rf[RLY * TL::R1 + c1o] = Lam[1];
+            }
+            cf.rho = rho;
+            cf.uz = u[2];
+            cf.F[0] = F[0];
+            cf.F[1] = F[1];
+            cf.F[2] = F[2];
+            cf.P = P;
+            cf.cs2 = cs2;
+            cf.T = Tt;
+            cf.h = hh;
+            cf.Lz = Lam[2];
+        }
+        if ((tid & ~63) < nring) {  // wavefronts holding ring cells
+            C u[3], F[3], rho, Tt, P, cs2, hh, Lam[3];
+            eval_cell(p, c3r, c2r, jr, ring, u, F, rho, Tt, P, cs2, hh, Lam);
+            if (ring) {
+                rf[RUX * TL::R1 + c1r] = u[0];
+                rf[RUY * TL::R1 + c1r] = u[1];
+                rf[RT * TL::R1 + c1r] = Tt;
+                rf[RH * TL::R1 + c1r] = hh;
+                rf[RLX * TL::R1 + c1r] = Lam[0];
+                rf[RLY * TL::R1 + c1r] = Lam[1];
+            }
+        }
+    };
+
+    // moment accumulators of the own destination in planes z-1, z, z+1
+    // (registers); the ring destination's live in sRacc, slot p mod 3 for
+    // plane p, touched only by the owning thread
+    C acc[3][5];
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+#pragma unroll
+        for (int k = 0; k < 5; k++) acc[q][k] = C(0);
+    // write plane p (own: acc[0]) to `layer`, then clear its ring slot; the
+    // reference sums enter once per cell, with the tile-own part of its plane
+    auto flush = [&](int p, int layer) {
+        if (own) {
+            const bool plane_layer = D == 2 || layer < nz;
+#pragma unroll
+            for (int k = 0; k < 5; k++) {
+                C v = acc[0][k];
+                if (plane_layer && k == 0) v = (v + a.rsf_lo) + a.rsf_hi;
+                if (plane_layer && k == 4) v = (v + a.rsg_lo) + a.rsg_hi;
+                at_bytes(a.Mco + (long long)k * a.nlay * plane,
+                         ((unsigned)layer * (unsigned)plane + own_off) * (unsigned)sizeof(C)) = v;
+            }
+        }
+        if (tid < nring) {
+            C *ra = &sRacc[s3(p)][0][0];
+#pragma unroll
+            for (int k = 0; k < 5; k++) {
+                if (ring_dst)
+                    at_bytes(a.INo + k * TL::NR,
+                             (((unsigned)rtile * (unsigned)a.nlay + (unsigned)layer) * 5u * TL::NR + (unsigned)rslot) *
+                                 (unsigned)sizeof(C)) = ra[k * TL::NR + tid];
+                ra[k * TL::NR + tid] = C(0);
+            }
+        }
+    };
+    auto shift_acc = [&]() {
+#pragma unroll
+        for (int k = 0; k < 5; k++) {
+            acc[0][k] = acc[1][k];
+            acc[1][k] = acc[2][k];
+            acc[2][k] = C(0);
+        }
+    };
+    // exchange round r: write the deviations of the pushed populations with
+    // c_z = r - 1 (D = 3)
+    auto xwrite = [&](int r, const C *fp, const C *gp) {
+        C *X = &sX[r & 1][0][0];
+        const int i0 = D == 3 ? 9 * r : 0;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            X[k * XS + tid] = fp[i0 + k];
+            X[(9 + k) * XS + tid] = gp[i0 + k];
+        }
+    };
+    auto xgather = [&](int r, int z) {
+        const char *X = (const char *)&sX[r & 1][0][0];
+        const int q = D == 3 ? r : 1;  // accumulator of plane z + c_z
+        auto xv = [&](int row, const unsigned *src, int k) -> C {
+            const unsigned off = (src[k / 2] >> (16 * (k & 1))) & 0xffffu;
+            return *(const C *)(X + (size_t)row * XS * sizeof(C) + off);
+        };
+        const C cz = D == 3 ? C(r - 1) : C(0);
+        {
+            C s0 = 0, sx = 0, sy = 0, sg = 0;
+#pragma unroll
+            for (int k = 0; k < 9; k++) {
+                const C v = xv(k, so, k);
+                s0 += v;
+                if (k % 3 == 0) sx -= v;
+                if (k % 3 == 2) sx += v;
+                if (k / 3 == 0) sy -= v;
+                if (k / 3 == 2) sy += v;
+                sg += xv(9 + k, so, k);
+            }
+            acc[q][0] += s0;
+            acc[q][1] += sx;
+            acc[q][2] += sy;
+            acc[q][3] += cz * s0;
+            acc[q][4] += sg;
+        }
+        if (tid < nring) {
+            C s0 = 0, sx = 0, sy = 0, sg = 0;
+#pragma unroll
+            for (int k = 0; k < 9; k++) {
+                const C v = xv(k, sr, k);
+                s0 += v;
+                if (k % 3 == 0) sx -= v;
+                if (k % 3 == 2) sx += v;
+                if (k / 3 == 0) sy -= v;
+                if (k / 3 == 2) sy += v;
+                sg += xv(9 + k, sr, k);
+            }
+            C *ra = &sRacc[s3(z + (D == 3 ? r - 1 : 0))][0][0];
+            ra[0 * TL::NR + tid] += s0;
+            ra[1 * TL::NR + tid] += sx;
+            ra[2 * TL::NR + tid] += sy;
+            ra[3 * TL::NR + tid] += cz * s0;
+            ra[4 * TL::NR + tid] += sg;
+        }
+    };
+
+    // -- prologue: rho(z0-3 .. z0+4), L(z0-2 .. z0+2), fields of z0-1, z0 -----
+    CenterF<C> Zc, Zm4;  // centre fields of plane z; plane z-1 (u_z, T, h, Lambda_z used)
+    C jo[4], jr[4];
+    {
+        C rv[NR3];
+        if (D == 3) {
+            // four rho slots: each plane is overwritten once its last reader
+            // has passed a barrier
+            for (int p = z0 - 3; p <= z0; p++) {
+                load_rho_regs(p, rv);
+                store_rho(p, rv);
+            }
+            __syncthreads();
+            make_lap(z0 - 2);
+            make_lap(z0 - 1);
+            __syncthreads();
+            load_rho_regs(z0 + 1, rv);
+            store_rho(z0 + 1, rv);
+            load_jg(z0 - 1, jo, jr);
+            __syncthreads();
+            make_lap(z0);
+            __syncthreads();
+            make_fields(z0 - 1, jo, jr, Zm4);
+            __syncthreads();
+            for (int p = z0 + 2; p <= z0 + 3; p++) {
+                load_rho_regs(p, rv);
+                store_rho(p, rv);
+            }
+            load_jg(z0, jo, jr);
+            __syncthreads();
+            make_lap(z0 + 1);
+            make_lap(z0 + 2);
+            __syncthreads();
+            make_fields(z0, jo, jr, Zc);
+            load_jg(z0 + 1, jo, jr);
+            load_rho_regs(z0 + 4, rv);
+            __syncthreads();
+            store_rho(z0 + 4, rv);
+        } else {
+            load_rho_regs(0, rv);
+            store_rho(0, rv);
+            load_jg(0, jo, jr);
+            __syncthreads();
+            make_lap(0);
+            __syncthreads();
+            make_fields(0, jo, jr, Zc);
+        }
+        __syncthreads();
+    }
+
+    for (int z = z0; z < z1; z++) {
+        // -- prefetch of rho(z+5) and j, G(z+2); phase A: L(z+3), fields of
+        //    plane z+1 ------------------------------------------------------------
+        C rv[NR3], jon[4], jrn[4];
+        CenterF<C> Zp;
+        if (D == 3) {
+            load_rho_regs(z + 5, rv);
+            load_jg(z + 2, jon, jrn);
+            make_lap(z + 3);
+            make_fields(z + 1, jo, jr, Zp);
+            __syncthreads();
+        }
+        // -- own populations of plane z -----------------------------------------
+        C f[Q], gq[Q];
+        {
+            const unsigned lo = ((unsigned)(D == 3 ? z : 0) * (unsigned)plane + own_off) * (unsigned)sizeof(T);
+#pragma unroll
+            for (int i = 0; i < Q; i++) {
+                f[i] = S::load(&at_bytes(a.fi + (long long)i * N, lo), 0, (C)a.ref.f[i]);
+                gq[i] = S::load(&at_bytes(a.gi + (long long)i * N, lo), 0, (C)a.ref.g[i]);
+            }
+        }
+
+        // -- phase B: collide the own cell of plane z ---------------------------
+        {
+            const C *rf = &sRing[s2(z)][0][0];
+            CollideIn<C> in;
+            in.rho = Zc.rho;
+            in.P = Zc.P;
+            in.T = Zc.T;
+            in.cs2 = Zc.cs2;
+            in.u[0] = rf[RUX * TL::R1 + c1o];
+            in.u[1] = rf[RUY * TL::R1 + c1o];
+            in.u[2] = Zc.uz;
+            in.F[0] = Zc.F[0];
+            in.F[1] = Zc.F[1];
+            in.F[2] = Zc.F[2];
+            in.du = C(0.5) * (rf[RUX * TL::R1 + c1o + 1] - rf[RUX * TL::R1 + c1o - 1]) +
+                    C(0.5) * (rf[RUY * TL::R1 + c1o + TL::W1] - rf[RUY * TL::R1 + c1o - TL::W1]);
+            in.dh[0] = C(0.5) * (rf[RH * TL::R1 + c1o + 1] - rf[RH * TL::R1 + c1o - 1]);
+            in.dh[1] = C(0.5) * (rf[RH * TL::R1 + c1o + TL::W1] - rf[RH * TL::R1 + c1o - TL::W1]);
+            in.dT[0] = C(0.5) * (rf[RT * TL::R1 + c1o + 1] - rf[RT * TL::R1 + c1o - 1]);
+            in.dT[1] = C(0.5) * (rf[RT * TL::R1 + c1o + TL::W1] - rf[RT * TL::R1 + c1o - TL::W1]);
+            in.L0[0] = rf[RLX * TL::R1 + c1o];
+            in.Lm[0] = rf[RLX * TL::R1 + c1o - 1];
+            in.Lp[0] = rf[RLX * TL::R1 + c1o + 1];
+            in.L0[1] = rf[RLY * TL::R1 + c1o];
+            in.Lm[1] = rf[RLY * TL::R1 + c1o - TL::W1];
+            in.Lp[1] = rf[RLY * TL::R1 + c1o + TL::W1];
+            if (D == 3) {
+                in.du += C(0.5) * (Zp.uz - Zm4.uz);
+                in.dT[2] = C(0.5) * (Zp.T - Zm4.T);
+                in.dh[2] = C(0.5) * (Zp.h - Zm4.h);
+                in.L0[2] = Zc.Lz;
+                in.Lm[2] = Zm4.Lz;
+                in.Lp[2] = Zp.Lz;
+            } else {
+                in.dT[2] = in.dh[2] = in.L0[2] = in.Lm[2] = in.Lp[2] = C(0);
+            }
+            collide_cell<D>(a.ph, in, f, gq);
+        }
+        if (D == 3) {
+            store_rho(z + 5, rv);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                jo[k] = jon[k];
+                jr[k] = jrn[k];
+            }
+        }
+        // -- stream: push to x + c_i of the other buffer; the moment sums of
+        //    the next step use the stored values (as deviations) -------------
+        {
+#pragma unroll
+            for (int i = 0; i < Q; i++) {
+                const int ix = cx_of(i), iy = cy_of(i), iz = D == 3 ? cz_of(i) : 0;
+                const T fe = S::enc(f[i], (C)a.ref.f[i]), ge = S::enc(gq[i], (C)a.ref.g[i]);
+                f[i] = S::dev(&fe, 0, (C)a.ref.f[i]);
+                gq[i] = S::dev(&ge, 0, (C)a.ref.g[i]);
+                // uniform base of population i, lane byte offset within it
+                // (the population arrays are below 4 GiB each)
+                char *fb = (char *)(a.fo + (long long)i * N), *gb = (char *)(a.go + (long long)i * N);
+                const unsigned zo = (unsigned)(D == 3 ? zwrap(z + iz) : 0) * (unsigned)plane;
+                const int dxv = xd[ix + 1], dyv = yd[iy + 1];
+                if (own && dxv >= 0 && dyv >= 0) {
+                    const unsigned off = (zo + (unsigned)(dxv + g.nx * dyv)) * (unsigned)sizeof(T);
+                    *(T *)(fb + off) = fe;
+                    *(T *)(gb + off) = ge;
+                }
+                if (has_dup) {
+                    const int xs[2] = {dxv, (xdup >> (ix + 1)) & 1 ? gx : -1};
+                    const int ys[2] = {dyv, (ydup >> (iy + 1)) & 1 ? gy : -1};
+                    for (int p = 0; p < 2; p++)
+                        for (int q = 0; q < 2; q++) {
+                            if ((p | q) == 0 || xs[p] < 0 || ys[q] < 0) continue;
+                            const unsigned off = (zo + (unsigned)(xs[p] + g.nx * ys[q])) * (unsigned)sizeof(T);
+                            *(T *)(fb + off) = fe;
+                            *(T *)(gb + off) = ge;
+                        }
+                }
+            }
+        }
+
+        // -- exchange and gather by c_z --------------------------------------
+        if (D == 3) {
+            xwrite(0, f, gq);
+            __syncthreads();
+            xgather(0, z);
+            flush(z - 1, z == z0 ? nz + 2 * seg : z - 1);  // plane z-1 is complete
+            xwrite(1, f, gq);
+            __syncthreads();
+            xgather(1, z);
+            xwrite(2, f, gq);
+            __syncthreads();
+            xgather(2, z);
+            shift_acc();
+            Zm4 = Zc;
+            Zc = Zp;
+        } else {
+            xwrite(0, f, gq);
+            __syncthreads();
+            xgather(0, 0);
+            // accumulator 1 holds plane 0
+#pragma unroll
+            for (int k = 0; k < 5; k++) acc[0][k] = acc[1][k];
+            flush(0, 0);
+        }
+    }
+    if (D == 3) {
+        flush(z1 - 1, z1 - 1);
+        shift_acc();
+        flush(z1, nz + 2 * seg + 1);
+    }
+    if constexpr (MLP) {
+        if (lane == 0 && n_eval) {
+            atomicAdd(&a.mlpCount[0], n_fb);
+            atomicAdd(&a.mlpCount[1], n_eval);
+        }
+    }
+}
+
+// Completes the moments of the output state: adds the inbound slots of tile
+// edge cells and the spill layers of the segment end planes into Mc (own
+// layers).  mode 0: perimeter cells of tiles in planes that are not segment
+// ends, grid (ceil(tiles * PMAX / BX), nz); mode 1 (D = 3): every cell of the
+// first and last plane of each segment, grid (ceil(nx ny / BX), 2 nseg).
+template <int D, class TL, class C>
+__global__ void __launch_bounds__(BX) k_fused_fixup(Grid g, int ntx, int nty, int nseg, int nlay, int mode, C *Mc,
+                                                    const C *IN) {
+    const int nz = g.nz;
+    int z, gxv, gyv;
+    int s = 0;
+    if (mode == 0) {
+        z = blockIdx.y;
+        if (D == 3) {
+            s = seg_of(z, nz, nseg);
+            if (z == seg_lo(s, nz, nseg) || z == seg_lo(s + 1, nz, nseg) - 1) return;
+        }
+        const long long idx = (long long)blockIdx.x * BX + threadIdx.x;
+        const long long tile = idx / TL::PMAX;
+        int q = (int)(idx - tile * TL::PMAX);
+        if (tile >= (long long)ntx * nty) return;
+        const int tx = (int)(tile % ntx), ty = (int)(tile / ntx);
+        const int w = min(TL::TX, g.nx - tx * TL::TX), h = min(TL::TY, g.ny - ty * TL::TY);
+        int lx, ly;
+        if (w == 1 || h == 1) {
+            if (q >= w * h) return;
+            lx = q % w;
+            ly = q / w;
+        } else {
+            if (q >= 2 * w + 2 * h - 4) return;
+            if (q < w) { lx = q; ly = 0; }
+            else if (q < 2 * w) { lx = q - w; ly = h - 1; }
+            else if (q < 2 * w + h - 2) { lx = 0; ly = 1 + q - 2 * w; }
+            else { lx = w - 1; ly = 1 + q - (2 * w + h - 2); }
+        }
+        gxv = tx * TL::TX + lx;
+        gyv = ty * TL::TY + ly;
+    } else {
+        s = blockIdx.y >> 1;
+        const int zlo = seg_lo(s, nz, nseg), zhi = seg_lo(s + 1, nz, nseg) - 1;
+        if ((blockIdx.y & 1) && zhi == zlo) return;
+        z = (blockIdx.y & 1) ? zhi : zlo;
+        const long long c = (long long)blockIdx.x * BX + threadIdx.x;
+        if (c >= (long long)g.nx * g.ny) return;
+        gxv = (int)(c % g.nx);
+        gyv = (int)(c / g.nx);
+    }
+    const int tx = gxv / TL::TX, ty = gyv / TL::TY;
+    const int lx = gxv - tx * TL::TX, ly = gyv - ty * TL::TY;
+    const int w = min(TL::TX, g.nx - tx * TL::TX), h = min(TL::TY, g.ny - ty * TL::TY);
+    const long long tile = (long long)ty * ntx + tx;
+    const long long plane = (long long)g.nx * g.ny;
+    const long long cell = gxv + (long long)g.nx * gyv;
+    const int zlo = seg_lo(s, nz, nseg), zhi = seg_lo(s + 1, nz, nseg) - 1;
+    const int lay_hi = nz + 2 * ((s + nseg - 1) % nseg) + 1;  // plane z0 of segment s, from segment s-1
+    const int lay_lo = nz + 2 * ((s + 1) % nseg);             // plane z1-1 of segment s, from segment s+1
+    for (int k = 0; k < 5; k++) {
+        const long long mi = ((long long)k * nlay + z) * plane + cell;
+        C v = Mc[mi] + inbound_sum<TL>(IN + ((tile * nlay + z) * 5 + k) * TL::NR, lx, ly, w, h);
+        if (D == 3 && mode == 1) {
+            if (z == zlo)
+                v += Mc[((long long)k * nlay + lay_hi) * plane + cell] +
+                     inbound_sum<TL>(IN + ((tile * nlay + lay_hi) * 5 + k) * TL::NR, lx, ly, w, h);
+            if (z == zhi)
+                v += Mc[((long long)k * nlay + lay_lo) * plane + cell] +
+                     inbound_sum<TL>(IN + ((tile * nlay + lay_lo) * 5 + k) * TL::NR, lx, ly, w, h);
+        }
+        Mc[mi] = v;
+    }
+}
+
+// Complete moments of a stored state (after init or set_populations) in the
+// plane layers of Mc, summed in exactly the order, grouping and rounding of
+// the fused step's gather and fix-up: deviation sums per source tile and
+// segment, accumulated round by round (c_z = +1, 0, -1), the reference sums
+// added to the tile-own part, then the inbound and spill parts in fix-up
+// order.  A state restored from its populations therefore continues bitwise
+// like the run that produced it.  One thread per cell.
 template <int D, class S, class TL>
-__global__ void __launch_bounds__(BX) k_fused_moments(Grid g, RefPops ref, int nlayer, const typename S::T *fi,
+__global__ void __launch_bounds__(BX) k_fused_moments(Grid g, RefPops ref, typename S::C rsf_hi,
+                                                      typename S::C rsf_lo, typename S::C rsg_hi, typename S::C rsg_lo,
+                                                      int ntx, int nty, int nseg, int nlay, const typename S::T *fi,
                                                       const typename S::T *gi, typename S::C *Mc) {
     using C = typename S::C;
-    constexpr int Q = Lattice<D>::Q;
-    int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
     if (x >= g.nx) return;
-    const long long c = cell_index<D>(g, x, y, z);
-    C rho = 0, J[3] = {0, 0, 0}, G = 0;
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-        const C f = S::load(fi, i * g.N + c, (C)ref.f[i]);
-        rho += f;
-        if (cx_of(i)) J[0] += cx_of(i) > 0 ? f : -f;
-        if (cy_of(i)) J[1] += cy_of(i) > 0 ? f : -f;
-        if (D == 3 && cz_of(i)) J[2] += cz_of(i) > 0 ? f : -f;
-        G += S::load(gi, i * g.N + c, (C)ref.g[i]);
+    const int nz = g.nz;
+    const int tx = x / TL::TX, ty = y / TL::TY;
+    const int lx = x - tx * TL::TX, ly = y - ty * TL::TY;
+    const int x0 = tx * TL::TX, y0 = ty * TL::TY;
+    const int w = min(TL::TX, g.nx - x0), h = min(TL::TY, g.ny - y0);
+    int z0 = 0, z1 = 1;
+    if (D == 3) {
+        const int s = seg_of(z, nz, nseg);
+        z0 = seg_lo(s, nz, nseg);
+        z1 = seg_lo(s + 1, nz, nseg);
     }
+    const long long cell = cell_index<D>(g, x, y, z);
+    // acc[class][group][moment]: class 0 sources in the own segment, 1 in
+    // plane z0-1 (segment below), 2 in plane z1 (segment above); group =
+    // source tile relative to the cell's tile, (oy + 1) * 3 + (ox + 1)
+    C acc[3][9][5];
+    for (int c = 0; c < 3; c++)
+        for (int q = 0; q < 9; q++)
+            for (int k = 0; k < 5; k++) acc[c][q][k] = C(0);
+    for (int r = 0; r < (D == 3 ? 3 : 1); r++) {
+        const int cz = D == 3 ? 1 - r : 0;  // the march meets sources at z-1 first
+        int cls = 0;
+        if (D == 3) cls = z - cz < z0 ? 1 : (z - cz >= z1 ? 2 : 0);
+        C s0[9], sx[9], sy[9], sg[9];
+        for (int q = 0; q < 9; q++) s0[q] = sx[q] = sy[q] = sg[q] = C(0);
+        for (int k = 0; k < 9; k++) {
+            const int cx = k % 3 - 1, cy = k / 3 - 1;
+            const int i = k + (D == 3 ? 9 * (cz + 1) : 0);
+            // source along each axis in tile-local coordinates (d - c, or d
+            // itself on a zero-gradient wall when c points inward)
+            const int sxl = (g.clampx && ((x == 0 && cx == 1) || (x == g.nx - 1 && cx == -1))) ? lx : lx - cx;
+            const int syl = (g.clampy && ((y == 0 && cy == 1) || (y == g.ny - 1 && cy == -1))) ? ly : ly - cy;
+            const int src = ((syl < 0 ? -1 : (syl >= h ? 1 : 0)) + 1) * 3 + (sxl < 0 ? -1 : (sxl >= w ? 1 : 0)) + 1;
+            const C v = S::dev(fi, i * g.N + cell, (C)ref.f[i]);
+            const C vg = S::dev(gi, i * g.N + cell, (C)ref.g[i]);
+            for (int q = 0; q < 9; q++) {
+                const C vq = q == src ? v : C(0);
+                s0[q] += vq;
+                if (k % 3 == 0) sx[q] -= vq;
+                if (k % 3 == 2) sx[q] += vq;
+                if (k / 3 == 0) sy[q] -= vq;
+                if (k / 3 == 2) sy[q] += vq;
+                sg[q] += q == src ? vg : C(0);
+            }
+        }
+        for (int q = 0; q < 9; q++) {
+            acc[cls][q][0] += s0[q];
+            acc[cls][q][1] += sx[q];
+            acc[cls][q][2] += sy[q];
+            acc[cls][q][3] += C(cz) * s0[q];
+            acc[cls][q][4] += sg[q];
+        }
+    }
+    // inbound part of one class in the order of the fix-up pass
+    auto inbound = [&](int c, int k) -> C {
+        C v = 0;
+        if (lx == 0) v += acc[c][3][k];
+        if (lx == w - 1) v += acc[c][5][k];
+        if (ly == 0) v += acc[c][1][k];
+        if (ly == h - 1) v += acc[c][7][k];
+        if (lx == 0 && ly == 0) v += acc[c][0][k];
+        if (lx == w - 1 && ly == 0) v += acc[c][2][k];
+        if (lx == 0 && ly == h - 1) v += acc[c][6][k];
+        if (lx == w - 1 && ly == h - 1) v += acc[c][8][k];
+        return v;
+    };
+    const bool seg_end = D == 3 && (z == z0 || z == z1 - 1);
+    const bool edge = lx == 0 || lx == w - 1 || ly == 0 || ly == h - 1;
     const long long plane = (long long)g.nx * g.ny;
     const long long pc = (long long)x + (long long)g.nx * y;
-    const int layer = layer_of<D>(z);
-    C v[5] = {rho, J[0], J[1], J[2], G};
-    for (int k = 0; k < 5; k++) Mc[((long long)k * nlayer + layer) * plane + pc] = v[k];
+    for (int k = 0; k < 5; k++) {
+        C v = acc[0][4][k];
+        if (k == 0) v = (v + rsf_lo) + rsf_hi;
+        if (k == 4) v = (v + rsg_lo) + rsg_hi;
+        if (seg_end || edge) v = v + inbound(0, k);
+        if (seg_end) {
+            if (z == z0) v += acc[1][4][k] + inbound(1, k);
+            if (z == z1 - 1) v += acc[2][4][k] + inbound(2, k);
+        }
+        Mc[((long long)k * nlay + (D == 3 ? z : 0)) * plane + pc] = v;
+    }
 }
 
 }  // namespace lbm

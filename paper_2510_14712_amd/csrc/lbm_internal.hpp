@@ -28,10 +28,10 @@ struct lbm_ctx {
     uint16_t mlp_w2b_host[64 * 64];
     // single-pass fused step: moment side channel of the current state
     bool fused = false;
-    void *Mc[2] = {nullptr, nullptr};  // [5][nlayer][ny][nx]
-    void *IN[2] = {nullptr, nullptr};  // [tiles][nlayer][5][slots]
+    void *Mc[2] = {nullptr, nullptr};  // [5][nlay][ny][nx]
+    void *IN[2] = {nullptr, nullptr};  // [tiles][nlay][5][slots]
     size_t mc_bytes = 0, in_bytes = 0;
-    int ntx = 0, nty = 0, nlayer = 0;
+    int ntx = 0, nty = 0, nseg = 1, nlay = 0, chunk = 0;
 };
 
 // carve the field arrays out of the work buffer

@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(64) k_forward(const float *P, const float *nor
     const int bc = b < B ? b : B - 1;
     float x0, x1, o[3];
     normalise(norm, x[2 * bc], x[2 * bc + 1], x0, x1);
-    if constexpr (MFMA) forward_wave<3>(x0, x1, P, nullptr, o);
+    if constexpr (MFMA) forward_wave<3>(x0, x1, net_of(P, nullptr), o);
     else forward_wave_lds<false>(x0, x1, P, lds, o);
     if (b < B)
         for (int k = 0; k < 3; k++) y[3 * b + k] = o[k] * norm[5 + 2 * k] + norm[4 + 2 * k];
@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(MLP_BLOCK) k_fields_mlp(Grid g, Phys<float> ph
     float e = E - 0.5f * u2;
     float x0, x1, yh[1];
     normalise(norm, rho, e, x0, x1);
-    forward_wave<1>(x0, x1, P, W2b, yh);
+    forward_wave<1>(x0, x1, net_of(P, W2b), yh);
     // The residual check validates the temperature only, so the pressure and
     // c_s^2 of the step come from the equation of state at the accepted T
     // (explicit once T is known); the network's P and c_s^2 outputs are

@@ -37,78 +37,82 @@ __device__ __forceinline__ void normalise(const float *norm, float rho, float e,
     x1 = 2.0f * (e - norm[2]) / (norm[3] - norm[2]) - 1.0f;
 }
 
-// P: FP32 parameters; W2b: BF16 copy of W2 (row-major, [out][in]) or null,
-// in which case the FP32 W2 of P is rounded on the fly.
+// Parameter pointers of one forward pass: the small layers may live in LDS,
+// the 64 x 64 hidden weights are read as BF16 (w2b) or rounded on the fly
+// from FP32 (w2b null: w2).
+struct Net {
+    const float *w1, *b1;  // [64][2], [64]
+    const uint16_t *w2b;   // [64][64] BF16, row-major [out][in], or null
+    const float *w2;       // [64][64] FP32 (when w2b is null)
+    const float *b2, *w3, *b3;  // [64], [NOUT][64], [NOUT]
+};
+__device__ __forceinline__ Net net_of(const float *P, const uint16_t *W2b) {
+    return Net{P + OFF_W1, P + OFF_B1, W2b, P + OFF_W2, P + OFF_B2, P + OFF_W3, P + OFF_B3};
+}
+
 // Returns the normalised outputs 0..NOUT-1 of this lane's sample.  Every lane
-// of the wavefront must call with uniform control flow.
+// of the wavefront must call with uniform control flow.  The two 32-sample
+// halves of the wavefront go through the hidden layer one after the other and
+// each k-step's B operand is formed just before its MFMA, which keeps the
+// live registers low.
 template <int NOUT>
-__device__ __forceinline__ void forward_wave(float x0, float x1, const float *__restrict__ P,
-                                             const uint16_t *__restrict__ W2b, float y[NOUT]) {
+__device__ __forceinline__ void forward_wave(float x0, float x1, const Net &p, float y[NOUT]) {
     const int lane = threadIdx.x & 63;
     const int hh = lane >> 5, c = lane & 31;
-    // inputs of the two samples this lane serves in the B operand
-    float xs0[2], xs1[2];
-    xs0[0] = __shfl(x0, c, 64);
-    xs1[0] = __shfl(x1, c, 64);
-    xs0[1] = __shfl(x0, 32 + c, 64);
-    xs1[1] = __shfl(x1, 32 + c, 64);
-    bf16x8 b[2][4];
 #pragma unroll
-    for (int ks = 0; ks < 4; ks++)
+    for (int nt = 0; nt < 2; nt++) {
+        // inputs of the sample this lane serves in the B operand
+        const float xs0 = __shfl(x0, 32 * nt + c, 64), xs1 = __shfl(x1, 32 * nt + c, 64);
+        f32x16 acc[2];
 #pragma unroll
-        for (int j = 0; j < 8; j++) {
-            const int k = 16 * ks + 8 * hh + j;
-            const float w0 = P[OFF_W1 + 2 * k], w1 = P[OFF_W1 + 2 * k + 1], bk = P[OFF_B1 + k];
+        for (int mt = 0; mt < 2; mt++)
 #pragma unroll
-            for (int nt = 0; nt < 2; nt++) b[nt][ks][j] = to_bf16(fast_tanh(fmaf(w0, xs0[nt], fmaf(w1, xs1[nt], bk))));
+            for (int v = 0; v < 16; v++) acc[mt][v] = 0.0f;
+#pragma unroll
+        for (int ks = 0; ks < 4; ks++) {
+            bf16x8 b;
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const int k = 16 * ks + 8 * hh + j;
+                b[j] = to_bf16(fast_tanh(fmaf(p.w1[2 * k], xs0, fmaf(p.w1[2 * k + 1], xs1, p.b1[k]))));
+            }
+#pragma unroll
+            for (int mt = 0; mt < 2; mt++) {
+                bf16x8 a;
+                if (p.w2b) {
+                    const uint4 raw = *(const uint4 *)(p.w2b + (32 * mt + c) * H + 16 * ks + 8 * hh);
+                    a = __builtin_bit_cast(bf16x8, raw);
+                } else {
+                    const float *row = p.w2 + (32 * mt + c) * H + 16 * ks + 8 * hh;
+#pragma unroll
+                    for (int j = 0; j < 8; j++) a[j] = to_bf16(row[j]);
+                }
+                acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[mt], 0, 0, 0);
+            }
+            // keep the next k-step's parameter loads from being hoisted here:
+            // bounds the live registers of the first layer to one k-step
+            __builtin_amdgcn_sched_barrier(0);
         }
-    f32x16 acc[2][2];
+        float ys[NOUT];
 #pragma unroll
-    for (int mt = 0; mt < 2; mt++)
-#pragma unroll
-        for (int nt = 0; nt < 2; nt++)
-#pragma unroll
-            for (int v = 0; v < 16; v++) acc[mt][nt][v] = 0.0f;
-#pragma unroll
-    for (int ks = 0; ks < 4; ks++) {
+        for (int k = 0; k < NOUT; k++) ys[k] = 0.0f;
 #pragma unroll
         for (int mt = 0; mt < 2; mt++) {
-            bf16x8 a;
-            if (W2b) {
-                const uint4 raw = *(const uint4 *)(W2b + (32 * mt + c) * H + 16 * ks + 8 * hh);
-                a = __builtin_bit_cast(bf16x8, raw);
-            } else {
-                const float *row = P + OFF_W2 + (32 * mt + c) * H + 16 * ks + 8 * hh;
 #pragma unroll
-                for (int j = 0; j < 8; j++) a[j] = to_bf16(row[j]);
+            for (int v = 0; v < 16; v++) {
+                const int o = 32 * mt + 8 * (v >> 2) + 4 * hh + (v & 3);
+                const float h2 = fast_tanh(acc[mt][v] + p.b2[o]);
+#pragma unroll
+                for (int k = 0; k < NOUT; k++) ys[k] = fmaf(p.w3[k * H + o], h2, ys[k]);
             }
-#pragma unroll
-            for (int nt = 0; nt < 2; nt++)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[nt][ks], acc[mt][nt], 0, 0, 0);
-        }
-    }
-    float ys[NOUT][2];
-#pragma unroll
-    for (int k = 0; k < NOUT; k++) ys[k][0] = ys[k][1] = 0.0f;
-#pragma unroll
-    for (int mt = 0; mt < 2; mt++)
-#pragma unroll
-        for (int v = 0; v < 16; v++) {
-            const int o = 32 * mt + 8 * (v >> 2) + 4 * hh + (v & 3);
-            const float bo = P[OFF_B2 + o];
-#pragma unroll
-            for (int nt = 0; nt < 2; nt++) {
-                const float h2 = fast_tanh(acc[mt][nt][v] + bo);
-#pragma unroll
-                for (int k = 0; k < NOUT; k++) ys[k][nt] = fmaf(P[OFF_W3 + k * H + o], h2, ys[k][nt]);
-            }
+            __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
-    for (int k = 0; k < NOUT; k++) {
-#pragma unroll
-        for (int nt = 0; nt < 2; nt++) ys[k][nt] += __shfl_xor(ys[k][nt], 32, 64);
-        // lane l's own sample is 32 nt + c with nt = l / 32
-        y[k] = (hh == 0 ? ys[k][0] : ys[k][1]) + P[OFF_B3 + k];
+        for (int k = 0; k < NOUT; k++) {
+            ys[k] += __shfl_xor(ys[k], 32, 64);
+            // lane l's own sample is 32 nt + c with nt = l / 32
+            if (hh == nt) y[k] = ys[k] + p.b3[k];
+        }
     }
 }
 

@@ -39,7 +39,7 @@ class _Params(ctypes.Structure):
                 ("kappa", ctypes.c_double),
                 ("storage", ctypes.c_int), ("eos", ctypes.c_int), ("mlp_tol", ctypes.c_double),
                 ("ref_rho", ctypes.c_double), ("ref_T", ctypes.c_double), ("stream", ctypes.c_void_p),
-                ("upwind_eps", ctypes.c_double)]
+                ("upwind_eps", ctypes.c_double), ("zsegments", ctypes.c_int)]
 
 
 _lib = None
@@ -134,7 +134,7 @@ class Lattice:
 
     def __init__(self, lattice, shape, bc=(0, 0, 0), a=3.0 / 49.0, b=2.0 / 21.0, R=1.0, cv=2.5, mu=0.05,
                  eta=0.05, k=None, kappa=0.01, storage="f32", eos="vdw", mlp_tol=1e-6, ref_rho=0.0, ref_T=0.0,
-                 stream=None, upwind_eps=UPWIND_EPS):
+                 stream=None, upwind_eps=UPWIND_EPS, zsegments=0):
         L = load()
         self.D = int(lattice)
         nx, ny = int(shape[0]), int(shape[1])
@@ -155,6 +155,7 @@ class Lattice:
         p.mlp_tol = mlp_tol
         p.ref_rho, p.ref_T = ref_rho, ref_T
         p.upwind_eps = upwind_eps
+        p.zsegments = int(zsegments)
         self._stream = stream
         p.stream = _stream_ptr(stream).value if _torch().cuda.is_available() else None
         self.params = p

@@ -49,7 +49,7 @@ def _params(**over):
 @pytest.mark.parametrize("over", [
     dict(lattice=4), dict(nx=0), dict(lattice=2, nz=2), dict(bc=(2, 0, 0)), dict(storage=7),
     dict(eos=3), dict(cv=0.0), dict(mu=-1.0), dict(storage=2, ref_rho=0.0, ref_T=0.2),
-    dict(storage=0, eos=1), dict(ny=70000), dict(upwind_eps=-1.0),
+    dict(storage=0, eos=1), dict(ny=70000), dict(upwind_eps=-1.0), dict(zsegments=-1), dict(zsegments=9),
 ])
 def test_invalid_parameters_rejected(over):
     from paper_2510_14712_amd import lbm
