@@ -163,7 +163,7 @@ __device__ __forceinline__ int gather_src(int d, int c, int t0, int n, int clamp
 // Inputs of one cell's collision (eqs. sh_vel_1, sh_temp_1, sh_T_1, qc_1,
 // correction) gathered from the field pipeline.
 template <class C> struct CollideIn {
-    C rho, P, T, cs2;
+    C rho, P, e, cs2;     // e: specific internal energy of the moments (eq. def_E)
     C u[3], F[3];
     C du;                 // divergence of u, central differences
     C dh[3], dT[3];       // central differences of h and T
@@ -175,7 +175,7 @@ template <class C> struct CollideIn {
 template <int D, class C>
 __device__ __forceinline__ void collide_cell(const Phys<C> &ph, const CollideIn<C> &in, C *f, C *g) {
     constexpr int Q = Lattice<D>::Q;
-    const C rho = in.rho, P = in.P, Tt = in.T;
+    const C rho = in.rho, P = in.P;
     const C inv_rho = C(1) / rho;
     const C theta = P * inv_rho;
     C qc[3], Phi[3], FF = 0;
@@ -191,9 +191,12 @@ __device__ __forceinline__ void collide_cell(const Phys<C> &ph, const CollideIn<
     const C beta = P / (P + C(2) * ph.mu);
     const C alpha = C(D + 2) / C(D) - rho * in.cs2 / P - ph.eta_over_mu;
     const C thetas = theta + alpha * theta * in.du;
-    const C Ts = Tt - FF * inv_rho * inv_rho * C(0.5) * ph.inv_cv;
-    const C e = ph.cv * Tt - ph.a * rho;
-    const C es = ph.cv * Ts - ph.a * rho;
+    // e(rho, T*) with T* = T - |F|^2 / (2 rho^2 c_v) (eq. sh_T_1): for van der
+    // Waals e is linear in T, so e(rho, T*) = e - |F|^2 / (2 rho^2), taken
+    // from the moments' own e (no round trip through T, which keeps the
+    // attractor's energy consistent with the populations')
+    const C e = in.e;
+    const C es = e - FF * inv_rho * inv_rho * C(0.5);
     const C eps_eq = e - C(0.5 * D) * theta;
     const C eps_st = es - C(0.5 * D) * thetas;
     AxisEq<C> eq[3], st[3];
@@ -252,7 +255,7 @@ template <class P> __device__ __forceinline__ const P &at_bytes(const P *base, u
 
 // fields of one plane's cell kept in registers between marching positions
 template <class C> struct CenterF {
-    C rho, uz, F[3], P, cs2, T, h, Lz;
+    C rho, uz, F[3], P, cs2, T, e, h, Lz;
 };
 
 template <int D, class S, class TL, bool MLP>
@@ -427,7 +430,7 @@ __global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, ty
     // fields of logical plane p at one cell: R3 index c3, R2 index c2 of the
     // evaluation point, j, G of the cell.  With MLP the call is collective
     // over the wavefront.
-    auto eval_cell = [&](int p, int c3, int c2, const C *jg, bool act, C u[3], C F[3], C &rho, C &Tt, C &P,
+    auto eval_cell = [&](int p, int c3, int c2, const C *jg, bool act, C u[3], C F[3], C &rho, C &Tt, C &ee, C &P,
                          C &cs2, C &hh, C Lam[3]) {
         const C *lc = sLap[s4(p)];
         const C *lm = sLap[s4(p - 1)];
@@ -473,13 +476,14 @@ __global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, ty
         const C theta = P * inv_rho;
         for (int d = 0; d < 3; d++) Lam[d] = rho * u[d] * (u[d] * u[d] + C(3) * (theta - C(1.0 / 3.0)));
         hh = e + theta;
+        ee = e;
     };
     // fields of plane p for the own cell (into cf) and the ring cell
     auto make_fields = [&](int p, const C *jo, const C *jr, CenterF<C> &cf) {
         C *rf = &sRing[s2(p)][0][0];
         {
-            C u[3], F[3], rho, Tt, P, cs2, hh, Lam[3];
-            eval_cell(p, c3o, c2o, jo, own, u, F, rho, Tt, P, cs2, hh, Lam);
+            C u[3], F[3], rho, Tt, ee, P, cs2, hh, Lam[3];
+            eval_cell(p, c3o, c2o, jo, own, u, F, rho, Tt, ee, P, cs2, hh, Lam);
             if (own) {
                 rf[RUX * TL::R1 + c1o] = u[0];
                 rf[RUY * TL::R1 + c1o] = u[1];
@@ -496,12 +500,13 @@ __global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, ty
             cf.P = P;
             cf.cs2 = cs2;
             cf.T = Tt;
+            cf.e = ee;
             cf.h = hh;
             cf.Lz = Lam[2];
         }
         if ((tid & ~63) < nring) {  // wavefronts holding ring cells
-            C u[3], F[3], rho, Tt, P, cs2, hh, Lam[3];
-            eval_cell(p, c3r, c2r, jr, ring, u, F, rho, Tt, P, cs2, hh, Lam);
+            C u[3], F[3], rho, Tt, ee, P, cs2, hh, Lam[3];
+            eval_cell(p, c3r, c2r, jr, ring, u, F, rho, Tt, ee, P, cs2, hh, Lam);
             if (ring) {
                 rf[RUX * TL::R1 + c1r] = u[0];
                 rf[RUY * TL::R1 + c1r] = u[1];
@@ -692,7 +697,7 @@ __global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, ty
             CollideIn<C> in;
             in.rho = Zc.rho;
             in.P = Zc.P;
-            in.T = Zc.T;
+            in.e = Zc.e;
             in.cs2 = Zc.cs2;
             in.u[0] = rf[RUX * TL::R1 + c1o];
             in.u[1] = rf[RUY * TL::R1 + c1o];

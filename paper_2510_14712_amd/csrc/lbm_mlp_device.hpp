@@ -59,6 +59,9 @@ template <int NOUT>
 __device__ __forceinline__ void forward_wave(float x0, float x1, const Net &p, float y[NOUT]) {
     const int lane = threadIdx.x & 63;
     const int hh = lane >> 5, c = lane & 31;
+    // byte offset of this lane's A-operand row segment in the BF16 weights
+    // (uniform base + 32-bit lane offset + constant per (mt, ks))
+    const unsigned a_off = (unsigned)(c * H + 8 * hh) * 2u;
 #pragma unroll
     for (int nt = 0; nt < 2; nt++) {
         // inputs of the sample this lane serves in the B operand
@@ -80,7 +83,7 @@ __device__ __forceinline__ void forward_wave(float x0, float x1, const Net &p, f
             for (int mt = 0; mt < 2; mt++) {
                 bf16x8 a;
                 if (p.w2b) {
-                    const uint4 raw = *(const uint4 *)(p.w2b + (32 * mt + c) * H + 16 * ks + 8 * hh);
+                    const uint4 raw = *(const uint4 *)((const char *)p.w2b + a_off + (unsigned)((32 * mt * H + 16 * ks) * 2));
                     a = __builtin_bit_cast(bf16x8, raw);
                 } else {
                     const float *row = p.w2 + (32 * mt + c) * H + 16 * ks + 8 * hh;
