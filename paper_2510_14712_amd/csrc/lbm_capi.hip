@@ -78,9 +78,10 @@ __global__ void __launch_bounds__(BX) k_get_pops(Grid g, RefPops ref, const type
     int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
     if (x >= g.nx) return;
     long long c = cell_index<D>(g, x, y, z);
+    const long long xy = x + (long long)g.nx * y;
     for (int i = 0; i < Q; i++) {
-        fo[i * g.N + c] = (double)S::load(fi, i * g.N + c, (C)ref.f[i]);
-        go[i * g.N + c] = (double)S::load(gi, i * g.N + c, (C)ref.g[i]);
+        fo[i * g.N + c] = (double)S::load(fi, pop_index<Q>(g, i, z, xy), (C)ref.f[i]);
+        go[i * g.N + c] = (double)S::load(gi, pop_index<Q>(g, i, z, xy), (C)ref.g[i]);
     }
 }
 template <int D, class S>
@@ -91,9 +92,10 @@ __global__ void __launch_bounds__(BX) k_set_pops(Grid g, RefPops ref, const doub
     int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
     if (x >= g.nx) return;
     long long c = cell_index<D>(g, x, y, z);
+    const long long xy = x + (long long)g.nx * y;
     for (int i = 0; i < Q; i++) {
-        fo[i * g.N + c] = S::enc((C)fi[i * g.N + c], (C)ref.f[i]);
-        go[i * g.N + c] = S::enc((C)gi[i * g.N + c], (C)ref.g[i]);
+        fo[pop_index<Q>(g, i, z, xy)] = S::enc((C)fi[i * g.N + c], (C)ref.f[i]);
+        go[pop_index<Q>(g, i, z, xy)] = S::enc((C)gi[i * g.N + c], (C)ref.g[i]);
     }
 }
 template <int D, class C>
@@ -260,13 +262,19 @@ template <int D, class S> struct Impl {
         a.mlpTol = (float)c->p.mlp_tol;
         a.mlpCount = c->mlp_counters;
         const dim3 grid((unsigned)(c->ntx * c->nty * c->nseg));
+        // full tiles and periodic x, y: the specialisation without wall and
+        // partial-tile handling
+        const bool fast = c->p.nx % TL::TX == 0 && c->p.ny % TL::TY == 0 && c->p.bc[0] == LBM_BC_PERIODIC &&
+                          c->p.bc[1] == LBM_BC_PERIODIC;
         if constexpr (std::is_same<C, float>::value) {
             if (c->p.eos == LBM_EOS_MLP) {
-                hipLaunchKernelGGL((k_fused<D, S, TL, true>), grid, dim3(TL::NT), 0, c->stream, a);
+                if (fast) hipLaunchKernelGGL((k_fused<D, S, TL, true, true>), grid, dim3(TL::NT), 0, c->stream, a);
+                else hipLaunchKernelGGL((k_fused<D, S, TL, true, false>), grid, dim3(TL::NT), 0, c->stream, a);
                 return;
             }
         }
-        hipLaunchKernelGGL((k_fused<D, S, TL, false>), grid, dim3(TL::NT), 0, c->stream, a);
+        if (fast) hipLaunchKernelGGL((k_fused<D, S, TL, false, true>), grid, dim3(TL::NT), 0, c->stream, a);
+        else hipLaunchKernelGGL((k_fused<D, S, TL, false, false>), grid, dim3(TL::NT), 0, c->stream, a);
     }
     // completes the output moments (kind 1 of step_timed) and flips the state
     static void fused_fixup(lbm_ctx *c) {

@@ -59,6 +59,14 @@ struct Grid {
     long long N;
 };
 
+// Internal population layout, plane-major: pops[(z Q + i) nx ny + y nx + x].
+// The Q populations of one plane lie within Q nx ny values, so a kernel
+// addresses a plane with one 64-bit base and 32-bit offsets.  (The public
+// layout of lbm_get/set_populations stays pops[i N + cell].)
+template <int Q> __host__ __device__ __forceinline__ long long pop_index(const Grid &g, int i, long long z, long long xy) {
+    return (z * Q + i) * ((long long)g.nx * g.ny) + xy;
+}
+
 // ---------------------------------------------------------------------------
 // Population storage forms.  load() returns the population in the compute
 // type; enc() encodes it; dev() returns its deviation from the per-direction

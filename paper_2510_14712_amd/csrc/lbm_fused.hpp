@@ -19,14 +19,18 @@
 // inbound slots and spill layers into Mc (fixed order, one thread per cell),
 // so the next step reads complete moments with one load per value.
 //
-// Per marching position z (rho(z+1..z+4) and L(z..z+2) already in LDS):
+// Per marching position z (rho(z+1..z+4) and L(z..z+2) in LDS, the
+// populations of plane z in registers):
 //   phase A  Laplacian L(z+3); fields u, T, P, h, Lambda, F, c_s^2 of plane
-//            z+1 for the tile and its ring
+//            z+1 for the tile and its ring                         | barrier
 //   phase B  collide plane z, store rho(z+5) (loaded at the top of the
-//            iteration) over rho(z+1), push to the other buffer
-//   rounds   exchange the pushed populations by c_z through LDS (three
-//            double-buffered rounds), gather the moment sums; plane z-1 is
-//            complete after the first round and is written out.
+//            iteration) over rho(z+1), push to the other buffer, write the
+//            pushed deviations to the exchange buffer, load the populations
+//            of plane z+1                                          | barrier
+//   gather   moment sums of planes z-1, z, z+1 for the tile and its ring;
+//            plane z-1 is complete and is written out.
+// One workgroup per compute unit: the registers hold the prefetched plane and
+// the LDS the whole exchange, with two barriers per plane.
 // Ghost cells of zero-gradient axes take the field of the clamped cell.
 #pragma once
 
@@ -258,8 +262,11 @@ template <class C> struct CenterF {
     C rho, uz, F[3], P, cs2, T, e, h, Lz;
 };
 
-template <int D, class S, class TL, bool MLP>
-__global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, typename S::T> a) {
+// FAST: every tile is full and the x, y axes are periodic (no zero-gradient
+// wall in the tile plane); the per-lane wall and partial-tile cases then fold
+// away at compile time.
+template <int D, class S, class TL, bool MLP, bool FAST>
+__global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, typename S::T> a) {
     using C = typename S::C;
     using T = typename S::T;
     constexpr int Q = Lattice<D>::Q;
@@ -276,10 +283,14 @@ __global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, ty
     __shared__ C sRho[NRS][TL::R3];
     __shared__ C sLap[NLS][TL::R2];
     __shared__ C sRing[NFS][NRF][TL::R1];
-    __shared__ C sX[2][18][XS];
+    __shared__ C sX[2 * Q][XS];  // exchange: deviations of the pushed f (rows 0..Q-1) and g
     __shared__ C sRacc[D == 3 ? 3 : 1][5][TL::NR];  // moment sums of the ring destinations, by plane
 
-    const Grid &g = a.g;
+    Grid g = a.g;
+    if constexpr (FAST) {
+        g.clampx = 0;
+        g.clampy = 0;
+    }
     const long long N = g.N;
     const long long plane = (long long)g.nx * g.ny;
     const int tid = threadIdx.x;
@@ -290,14 +301,14 @@ __global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, ty
     const int L = a.chunk ? (b & 7) * a.chunk + (b >> 3) : b;
     const int tx = L % a.ntx, ty = (L / a.ntx) % a.nty, seg = L / (a.ntx * a.nty);
     const int x0 = tx * TX, y0 = ty * TY;
-    const int w = min(TX, g.nx - x0), h = min(TY, g.ny - y0);
+    const int w = FAST ? TX : min(TX, g.nx - x0), h = FAST ? TY : min(TY, g.ny - y0);
     const int nz = g.nz;
     const int z0 = D == 3 ? seg_lo(seg, nz, a.nseg) : 0;
     const int z1 = D == 3 ? seg_lo(seg + 1, nz, a.nseg) : 1;
 
     // -- z-invariant per-thread set-up ---------------------------------------
     const int lx = tid % TX, ly = tid / TX;
-    const bool own = lx < w && ly < h;
+    const bool own = FAST || (lx < w && ly < h);
     const int gx = x0 + min(lx, w - 1), gy = y0 + min(ly, h - 1);
     // per-lane offsets are unsigned 32-bit so that loads and stores take a
     // uniform 64-bit base plus a zero-extended lane offset
@@ -365,7 +376,7 @@ __global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, ty
         yd[c + 1] = (p >= 0 && p < g.ny) ? p : -1;
         if (g.clampy && ((gy == 0 && c == 1) || (gy == g.ny - 1 && c == -1))) ydup |= 1 << (c + 1);
     }
-    const bool has_dup = own && (xdup | ydup);
+    const bool has_dup = !FAST && own && (xdup | ydup);
 
     auto zwrap = [&](int p) { return D == 3 ? (p < 0 ? p + nz * (1 + (-p - 1) / nz) : p % nz) : 0; };
     auto s4 = [](int p) { return D == 3 ? p & 3 : 0; };
@@ -377,7 +388,7 @@ __global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, ty
     };
 
     // zero columns of the exchange buffers, ring accumulators
-    if (tid < 36) (&sX[0][0][0])[tid * XS + NT] = C(0);
+    if (tid < 2 * Q) sX[tid][NT] = C(0);
     for (int r = tid; r < (D == 3 ? 3 : 1) * 5 * TL::NR; r += NT) (&sRacc[0][0][0])[r] = C(0);
 
     // -- pipeline stages -----------------------------------------------------
@@ -560,19 +571,19 @@ __global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, ty
             acc[2][k] = C(0);
         }
     };
-    // exchange round r: write the deviations of the pushed populations with
-    // c_z = r - 1 (D = 3)
-    auto xwrite = [&](int r, const C *fp, const C *gp) {
-        C *X = &sX[r & 1][0][0];
-        const int i0 = D == 3 ? 9 * r : 0;
+    // exchange: the deviations of all pushed populations of the own cell
+    auto xwrite = [&](const C *fp, const C *gp) {
 #pragma unroll
-        for (int k = 0; k < 9; k++) {
-            X[k * XS + tid] = fp[i0 + k];
-            X[(9 + k) * XS + tid] = gp[i0 + k];
+        for (int i = 0; i < Q; i++) {
+            sX[i][tid] = fp[i];
+            sX[Q + i][tid] = gp[i];
         }
     };
+    // gather of the directions with c_z = r - 1 (D = 3): rows i0 + k of f and
+    // Q + i0 + k of g
     auto xgather = [&](int r, int z) {
-        const char *X = (const char *)&sX[r & 1][0][0];
+        const int i0 = D == 3 ? 9 * r : 0;
+        const char *X = (const char *)&sX[0][0];
         const int q = D == 3 ? r : 1;  // accumulator of plane z + c_z
         auto xv = [&](int row, const unsigned *src, int k) -> C {
             const unsigned off = (src[k / 2] >> (16 * (k & 1))) & 0xffffu;
@@ -583,13 +594,13 @@ __global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, ty
             C s0 = 0, sx = 0, sy = 0, sg = 0;
 #pragma unroll
             for (int k = 0; k < 9; k++) {
-                const C v = xv(k, so, k);
+                const C v = xv(i0 + k, so, k);
                 s0 += v;
                 if (k % 3 == 0) sx -= v;
                 if (k % 3 == 2) sx += v;
                 if (k / 3 == 0) sy -= v;
                 if (k / 3 == 2) sy += v;
-                sg += xv(9 + k, so, k);
+                sg += xv(Q + i0 + k, so, k);
             }
             acc[q][0] += s0;
             acc[q][1] += sx;
@@ -601,13 +612,13 @@ __global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, ty
             C s0 = 0, sx = 0, sy = 0, sg = 0;
 #pragma unroll
             for (int k = 0; k < 9; k++) {
-                const C v = xv(k, sr, k);
+                const C v = xv(i0 + k, sr, k);
                 s0 += v;
                 if (k % 3 == 0) sx -= v;
                 if (k % 3 == 2) sx += v;
                 if (k / 3 == 0) sy -= v;
                 if (k / 3 == 2) sy += v;
-                sg += xv(9 + k, sr, k);
+                sg += xv(Q + i0 + k, sr, k);
             }
             C *ra = &sRacc[s3(z + (D == 3 ? r - 1 : 0))][0][0];
             ra[0 * TL::NR + tid] += s0;
@@ -668,6 +679,22 @@ __global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, ty
         __syncthreads();
     }
 
+    // own populations of plane p into f, g (loaded one position ahead, so that
+    // their latency overlaps the exchange and the field pipeline)
+    C f[Q], gq[Q];
+    auto load_pops = [&](int p) {
+        // plane base (uniform) + (i nx ny + cell) elements (32-bit)
+        const long long pb = (long long)(D == 3 ? p : 0) * Q * plane;
+        const T *fp = a.fi + pb, *gp = a.gi + pb;
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            const unsigned lo = ((unsigned)i * (unsigned)plane + own_off) * (unsigned)sizeof(T);
+            f[i] = S::load(&at_bytes(fp, lo), 0, (C)a.ref.f[i]);
+            gq[i] = S::load(&at_bytes(gp, lo), 0, (C)a.ref.g[i]);
+        }
+    };
+    load_pops(z0);
+
     for (int z = z0; z < z1; z++) {
         // -- prefetch of rho(z+5) and j, G(z+2); phase A: L(z+3), fields of
         //    plane z+1 ------------------------------------------------------------
@@ -679,16 +706,6 @@ __global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, ty
             make_lap(z + 3);
             make_fields(z + 1, jo, jr, Zp);
             __syncthreads();
-        }
-        // -- own populations of plane z -----------------------------------------
-        C f[Q], gq[Q];
-        {
-            const unsigned lo = ((unsigned)(D == 3 ? z : 0) * (unsigned)plane + own_off) * (unsigned)sizeof(T);
-#pragma unroll
-            for (int i = 0; i < Q; i++) {
-                f[i] = S::load(&at_bytes(a.fi + (long long)i * N, lo), 0, (C)a.ref.f[i]);
-                gq[i] = S::load(&at_bytes(a.gi + (long long)i * N, lo), 0, (C)a.ref.g[i]);
-            }
         }
 
         // -- phase B: collide the own cell of plane z ---------------------------
@@ -746,12 +763,13 @@ __global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, ty
                 const T fe = S::enc(f[i], (C)a.ref.f[i]), ge = S::enc(gq[i], (C)a.ref.g[i]);
                 f[i] = S::dev(&fe, 0, (C)a.ref.f[i]);
                 gq[i] = S::dev(&ge, 0, (C)a.ref.g[i]);
-                // uniform base of population i, lane byte offset within it
-                // (the population arrays are below 4 GiB each)
-                char *fb = (char *)(a.fo + (long long)i * N), *gb = (char *)(a.go + (long long)i * N);
-                const unsigned zo = (unsigned)(D == 3 ? zwrap(z + iz) : 0) * (unsigned)plane;
+                // uniform base of the destination plane, lane byte offset of
+                // (i nx ny + cell) within it
+                const long long pb = (long long)(D == 3 ? zwrap(z + iz) : 0) * Q * plane;
+                char *fb = (char *)(a.fo + pb), *gb = (char *)(a.go + pb);
+                const unsigned zo = (unsigned)i * (unsigned)plane;
                 const int dxv = xd[ix + 1], dyv = yd[iy + 1];
-                if (own && dxv >= 0 && dyv >= 0) {
+                if (FAST || (own && dxv >= 0 && dyv >= 0)) {
                     const unsigned off = (zo + (unsigned)(dxv + g.nx * dyv)) * (unsigned)sizeof(T);
                     *(T *)(fb + off) = fe;
                     *(T *)(gb + off) = ge;
@@ -770,24 +788,20 @@ __global__ void __launch_bounds__(TL::NT, 2) k_fused(FusedArgs<typename S::C, ty
             }
         }
 
-        // -- exchange and gather by c_z --------------------------------------
+        // -- exchange, then the next position's populations, then the gather
+        //    by c_z --------------------------------------------------------------
+        xwrite(f, gq);
+        if (D == 3 && z + 1 < z1) load_pops(z + 1);
+        __syncthreads();
         if (D == 3) {
-            xwrite(0, f, gq);
-            __syncthreads();
             xgather(0, z);
             flush(z - 1, z == z0 ? nz + 2 * seg : z - 1);  // plane z-1 is complete
-            xwrite(1, f, gq);
-            __syncthreads();
             xgather(1, z);
-            xwrite(2, f, gq);
-            __syncthreads();
             xgather(2, z);
             shift_acc();
             Zm4 = Zc;
             Zc = Zp;
         } else {
-            xwrite(0, f, gq);
-            __syncthreads();
             xgather(0, 0);
             // accumulator 1 holds plane 0
 #pragma unroll
@@ -927,8 +941,9 @@ __global__ void __launch_bounds__(BX) k_fused_moments(Grid g, RefPops ref, typen
             const int sxl = (g.clampx && ((x == 0 && cx == 1) || (x == g.nx - 1 && cx == -1))) ? lx : lx - cx;
             const int syl = (g.clampy && ((y == 0 && cy == 1) || (y == g.ny - 1 && cy == -1))) ? ly : ly - cy;
             const int src = ((syl < 0 ? -1 : (syl >= h ? 1 : 0)) + 1) * 3 + (sxl < 0 ? -1 : (sxl >= w ? 1 : 0)) + 1;
-            const C v = S::dev(fi, i * g.N + cell, (C)ref.f[i]);
-            const C vg = S::dev(gi, i * g.N + cell, (C)ref.g[i]);
+            const long long pi = pop_index<Lattice<D>::Q>(g, i, D == 3 ? z : 0, x + (long long)g.nx * y);
+            const C v = S::dev(fi, pi, (C)ref.f[i]);
+            const C vg = S::dev(gi, pi, (C)ref.g[i]);
             for (int q = 0; q < 9; q++) {
                 const C vq = q == src ? v : C(0);
                 s0[q] += vq;

@@ -111,8 +111,9 @@ __global__ void __launch_bounds__(BX) k_init(Grid g, Phys<double> ph, RefPops re
             gsum = (qx * py + px * qy) * pz + px * py * qz;
         }
         double geq = feq * eps + 0.5 * r * gsum;
-        fo[i * g.N + c] = S::enc((C)feq, (C)ref.f[i]);
-        go[i * g.N + c] = S::enc((C)geq, (C)ref.g[i]);
+        const long long pi = pop_index<Q>(g, i, z, x + (long long)g.nx * y);
+        fo[pi] = S::enc((C)feq, (C)ref.f[i]);
+        go[pi] = S::enc((C)geq, (C)ref.g[i]);
     }
 }
 
@@ -128,12 +129,13 @@ __global__ void __launch_bounds__(BX) k_moments(Grid g, RefPops ref, const typen
     C rho = 0, J[3] = {0, 0, 0}, G = 0;
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-        C f = S::load(fi, i * g.N + c, (C)ref.f[i]);
+        const long long pi = pop_index<Q>(g, i, z, x + (long long)g.nx * y);
+        C f = S::load(fi, pi, (C)ref.f[i]);
         rho += f;
         if (cx_of(i)) J[0] += cx_of(i) > 0 ? f : -f;
         if (cy_of(i)) J[1] += cy_of(i) > 0 ? f : -f;
         if (D == 3 && cz_of(i)) J[2] += cz_of(i) > 0 ? f : -f;
-        G += S::load(gi, i * g.N + c, (C)ref.g[i]);
+        G += S::load(gi, pi, (C)ref.g[i]);
     }
     fl.rho[c] = rho;
     for (int a = 0; a < D; a++) fl.J[a * g.N + c] = J[a];
@@ -265,8 +267,9 @@ __global__ void __launch_bounds__(BX) k_collide(Grid g, Phys<typename S::C> ph, 
             C cq = ix ? (ix > 0 ? qc[0] : -qc[0]) : (iy ? (iy > 0 ? qc[1] : -qc[1]) : (iz > 0 ? qc[2] : -qc[2]));
             gst += C(0.5) * cq;
         }
-        C f = S::load(fi, i * N + c, (C)ref.f[i]);
-        C gg = S::load(gi, i * N + c, (C)ref.g[i]);
+        const long long pi = pop_index<Q>(g, i, z, x + (long long)g.nx * y);
+        C f = S::load(fi, pi, (C)ref.f[i]);
+        C gg = S::load(gi, pi, (C)ref.g[i]);
         // eqs. fLBGK, gLBGK: f + 2 beta (f^eq - f) + (1 - beta)(f* - f^eq)
         C fn = w_keep * f + w_eq * feq + w_st * fst;
         C gn = w_keep * gg + w_eq * geq + w_st * gst;
@@ -278,9 +281,9 @@ __global__ void __launch_bounds__(BX) k_collide(Grid g, Phys<typename S::C> ph, 
         for (int a = 0; a < nxd; a++)
             for (int b = 0; b < nyd; b++)
                 for (int cc = 0; cc < nzd; cc++) {
-                    long long d = cell_index<D>(g, dx[a], dy[b], dz[cc]);
-                    fo[i * N + d] = fe;
-                    go[i * N + d] = ge;
+                    const long long d = pop_index<Q>(g, i, dz[cc], dx[a] + (long long)g.nx * dy[b]);
+                    fo[d] = fe;
+                    go[d] = ge;
                 }
     }
 }
