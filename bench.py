@@ -27,6 +27,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# sources of the fused step; the measured HBM traffic in profiles/ is reported
+# only while these are unchanged since the counters were taken
+KERNEL_SOURCES = ("lbm_fused.hpp", "lbm_kernels.hpp", "lbm_device.hpp", "lbm_mlp_device.hpp", "lbm_capi.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_tgv512_hbm_traffic.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_14712_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(form):
+    """HBM bytes per launch of the fused kernel of `form` from the committed
+    FETCH_SIZE / WRITE_SIZE summary (scaled by the plain-copy calibration), or
+    None when the summary is missing or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_SUMMARY) as fh:
+            for line in fh:
+                if line.startswith("traffic-json:"):
+                    rec = json.loads(line[len("traffic-json:"):])
+                    if rec.get("source_hash") == kernel_source_hash() and form in rec.get("forms", {}):
+                        return rec["forms"][form]
+    except OSError:
+        pass
+    return None
 
 
 def _p(msg):
@@ -77,13 +106,15 @@ def time_form(lbm, torch, shape, bc, fields, ref, kw, storage, eos, steps, warmu
         lat.synchronize()
         if eos == "mlp":
             lat.mlp_stats()  # reset the fallback counters
+        # the timed region: K steps with HIP events around every launch on the
+        # library's stream (per-kernel average durations of these same steps)
+        lat.synchronize()
         t0 = time.perf_counter()
-        lat.step(steps)
+        kt = lat.step_timed(steps)
         lat.synchronize()
         dt = time.perf_counter() - t0
         sums = lat.conservation(raise_on_nan=False)
         fb = lat.mlp_stats() if eos == "mlp" else None
-        kt = lat.step_timed(3)
         bpc = lat.bytes_per_cell
     finally:
         lat.close()
@@ -168,15 +199,19 @@ def main():
         print(json.dumps({"forms": {"surrogate_bf16": surr}}), flush=True)
         return
 
-    def roof(form):
+    def roof(form, name):
         kms = form["kernel_ms"]
         dom = max(kms, key=kms.get)
         bytes_launch = form["bytes_per_cell"] * N
         achieved = bytes_launch / (kms[dom] * 1e-3) / 1e9
+        tr = measured_traffic(name)
         return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if tr is None else tr["bytes_per_launch"],
+                     "traffic_bytes_per_cell": None if tr is None else round(tr["bytes_per_launch"] / N, 1),
+                     "algorithmic_bytes_per_cell": form["bytes_per_cell"]}
 
-    dom, rl = roof(surr)
+    dom, rl = roof(surr, "surrogate_bf16")
     line = {
         "metric": "MLUPS & % HBM peak, D3Q27 fused step: plain FP32 vs surrogate-EOS/BF16 form",
         "value": round(surr["mlups"], 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
@@ -190,7 +225,7 @@ def main():
                            "step_hbm_frac": round(plain["bytes_per_cell"] * plain["mlups"] * 1e6 / 1e9
                                                   / HBM_PEAK_GBS, 4),
                            "kernel_ms": plain["kernel_ms"], "finite": plain["finite"],
-                           "roofline": roof(plain)[1]},
+                           "roofline": roof(plain, "plain_fp32")[1]},
             "surrogate_bf16": {"mlups": round(surr["mlups"], 1), "ms_per_step": round(surr["ms_per_step"], 4),
                                "step_hbm_frac": round(surr["bytes_per_cell"] * surr["mlups"] * 1e6 / 1e9
                                                       / HBM_PEAK_GBS, 4),

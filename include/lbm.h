@@ -149,10 +149,11 @@ int lbm_step_timed(lbm_ctx *ctx, int n, double *host_ms, int nslots);
 const char *lbm_kernel_name(const lbm_ctx *ctx, int kernel);
 
 /* 1 when lbm_step runs the single-pass fused kernel (one read and one write
- * of every population per step; periodic z or D = 2) followed by the small
- * pass completing its moment side channel (kernel kinds "k_fused",
- * "k_fused_fixup"), 0 when it runs the four-kernel path (moments, Laplacian,
- * fields, collide). */
+ * of every population per step; periodic z or D = 2, and one plane of
+ * populations, one moment layer and the inbound slots each below 2^31 bytes)
+ * followed by the small pass completing its moment side channel (kernel kinds
+ * "k_fused", "k_fused_fixup"), 0 when it runs the four-kernel path (moments,
+ * Laplacian, fields, collide). */
 int lbm_is_fused(const lbm_ctx *ctx);
 
 /* Algorithmic HBM bytes moved per cell update by lbm_step (2 Q populations

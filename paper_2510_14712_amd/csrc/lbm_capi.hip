@@ -72,16 +72,16 @@ __global__ void __launch_bounds__(64) k_reduce_final(int nblocks, const double *
 // population decode / encode between the storage form and FP64
 template <int D, class S>
 __global__ void __launch_bounds__(BX) k_get_pops(Grid g, RefPops ref, const typename S::T *fi, const typename S::T *gi,
-                                                 double *fo, double *go) {
+                                                 double *fo, double *go, int pull) {
     using C = typename S::C;
     constexpr int Q = Lattice<D>::Q;
     int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
     if (x >= g.nx) return;
     long long c = cell_index<D>(g, x, y, z);
-    const long long xy = x + (long long)g.nx * y;
     for (int i = 0; i < Q; i++) {
-        fo[i * g.N + c] = (double)S::load(fi, pop_index<Q>(g, i, z, xy), (C)ref.f[i]);
-        go[i * g.N + c] = (double)S::load(gi, pop_index<Q>(g, i, z, xy), (C)ref.g[i]);
+        const long long pi = arrived_index<D>(g, i, x, y, z, pull);
+        fo[i * g.N + c] = (double)S::load(fi, pi, (C)ref.f[i]);
+        go[i * g.N + c] = (double)S::load(gi, pi, (C)ref.g[i]);
     }
 }
 template <int D, class S>
@@ -213,7 +213,7 @@ template <int D, class S> struct Impl {
         hipLaunchKernelGGL((k_fused_moments<D, S, TL>), cell_grid(c), dim3(BX), 0, c->stream, c->grid, c->ref, rs[0],
                            rs[1], rs[2], rs[3],
                            c->ntx, c->nty, c->nseg, c->nlay, (const T *)c->f[c->cur], (const T *)c->g[c->cur],
-                           (C *)c->Mc[c->cur]);
+                           (C *)c->Mc[c->cur], c->pulled);
         return last_launch();
     }
     // sums of the reference populations in the compute type as hi + lo
@@ -240,6 +240,7 @@ template <int D, class S> struct Impl {
         a.nseg = c->nseg;
         a.nlay = c->nlay;
         a.chunk = c->chunk;
+        a.pull = c->pulled;
         {
             C rs[4];
             ref_sums(c, rs);
@@ -290,6 +291,7 @@ template <int D, class S> struct Impl {
                                (C *)c->Mc[nxt], (const C *)c->IN[nxt]);
         }
         c->cur = nxt;
+        c->pulled = 1;
     }
     static void fused_launch(lbm_ctx *c) {
         fused_main(c);
@@ -299,6 +301,7 @@ template <int D, class S> struct Impl {
     static int init(lbm_ctx *c, const double *rho, const double *u, const double *Tf) {
         hipLaunchKernelGGL((k_init<D, S>), cell_grid(c), dim3(BX), 0, c->stream, c->grid, make_phys<double>(c->p), c->ref,
                            rho, u, Tf, (T *)c->f[c->cur], (T *)c->g[c->cur]);
+        c->pulled = 0;
         int rc = last_launch();
         return rc ? rc : fused_prepare(c);
     }
@@ -306,7 +309,7 @@ template <int D, class S> struct Impl {
         Fields<C> fl = get_fields<C>(c);
         dim3 gr = cell_grid(c);
         hipLaunchKernelGGL((k_moments<D, S>), gr, dim3(BX), 0, c->stream, c->grid, c->ref, (const T *)c->f[c->cur],
-                           (const T *)c->g[c->cur], fl);
+                           (const T *)c->g[c->cur], fl, c->pulled);
         hipLaunchKernelGGL((k_lap<D, C>), gr, dim3(BX), 0, c->stream, c->grid, fl);
         if (c->p.eos == LBM_EOS_MLP) {
             int rc = launch_fields_mlp<D, C>(c, fl);
@@ -374,7 +377,7 @@ template <int D, class S> struct Impl {
         for (int s = 0; s < n && rc == LBM_OK; s++) {
             (void)hipEventRecord(ev[0], c->stream);
             hipLaunchKernelGGL((k_moments<D, S>), gr, dim3(BX), 0, c->stream, c->grid, c->ref,
-                               (const T *)c->f[c->cur], (const T *)c->g[c->cur], fl);
+                               (const T *)c->f[c->cur], (const T *)c->g[c->cur], fl, 0);
             (void)hipEventRecord(ev[1], c->stream);
             hipLaunchKernelGGL((k_lap<D, C>), gr, dim3(BX), 0, c->stream, c->grid, fl);
             (void)hipEventRecord(ev[2], c->stream);
@@ -407,12 +410,13 @@ template <int D, class S> struct Impl {
     }
     static int get_pops(lbm_ctx *c, double *f, double *g) {
         hipLaunchKernelGGL((k_get_pops<D, S>), cell_grid(c), dim3(BX), 0, c->stream, c->grid, c->ref,
-                           (const T *)c->f[c->cur], (const T *)c->g[c->cur], f, g);
+                           (const T *)c->f[c->cur], (const T *)c->g[c->cur], f, g, c->pulled);
         return last_launch();
     }
     static int set_pops(lbm_ctx *c, const double *f, const double *g) {
         hipLaunchKernelGGL((k_set_pops<D, S>), cell_grid(c), dim3(BX), 0, c->stream, c->grid, c->ref, f, g,
                            (T *)c->f[c->cur], (T *)c->g[c->cur]);
+        c->pulled = 0;
         int rc = last_launch();
         return rc ? rc : fused_prepare(c);
     }
@@ -570,6 +574,14 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
     if (c->fused) {
         auto tiles = [&]() { DISPATCH_VOID(c, tiles(c)); };
         tiles();
+        // its buffer resources (one plane of populations, one side-channel
+        // layer, the inbound slots) must stay below 2^31 bytes; larger
+        // lattices take the multi-kernel path
+        const long long plane = (long long)params->nx * params->ny, lim = 1LL << 31;
+        if ((long long)c->Q * plane * sb >= lim || 5 * plane * cb >= lim || (long long)c->in_bytes >= lim)
+            c->fused = false;
+    }
+    if (c->fused) {
         ok = hipMalloc(&c->Mc[0], c->mc_bytes) == hipSuccess && hipMalloc(&c->Mc[1], c->mc_bytes) == hipSuccess &&
              hipMalloc(&c->IN[0], c->in_bytes) == hipSuccess && hipMalloc(&c->IN[1], c->in_bytes) == hipSuccess;
         if (!ok) {

@@ -67,6 +67,30 @@ template <int Q> __host__ __device__ __forceinline__ long long pop_index(const G
     return (z * Q + i) * ((long long)g.nx * g.ny) + xy;
 }
 
+// Stored population sets come in two forms.  After initialisation (and after
+// lbm_set_populations) the set holds the arrived populations f_i(x) that the
+// next collision uses in place.  The fused step stores the post-collision set
+// instead and streams on the way in: the population arriving at x with
+// velocity c_i is read from x - c_i (wrapped on a periodic axis, clamped to
+// the edge cell on a zero-gradient axis, which is the streaming rule of
+// Sec. 3.2 with the boundary reading of the oracle).  `pull` selects the
+// form: 0 reads x itself, 1 reads x - c.
+__host__ __device__ __forceinline__ int pull_coord(int x, int c, int n, int clamp, int pull) {
+    const int p = x - pull * c;
+    if (clamp) return p < 0 ? 0 : (p >= n ? n - 1 : p);
+    return p < 0 ? p + n : (p >= n ? p - n : p);
+}
+// index of arrived population i of cell (x, y, z) in a stored set of either
+// form
+template <int D>
+__host__ __device__ __forceinline__ long long arrived_index(const Grid &g, int i, int x, int y, int z, int pull) {
+    constexpr int Q = D == 2 ? 9 : 27;
+    const int sx = pull_coord(x, cx_of(i), g.nx, g.clampx, pull);
+    const int sy = pull_coord(y, cy_of(i), g.ny, g.clampy, pull);
+    const int sz = D == 3 ? pull_coord(z, cz_of(i), g.nz, g.clampz, pull) : 0;
+    return pop_index<Q>(g, i, sz, sx + (long long)g.nx * sy);
+}
+
 // ---------------------------------------------------------------------------
 // Population storage forms.  load() returns the population in the compute
 // type; enc() encodes it; dev() returns its deviation from the per-direction
@@ -75,12 +99,17 @@ template <int Q> __host__ __device__ __forceinline__ long long pop_index(const G
 // within a factor two of the reference).  Moment sums over deviations keep
 // the large, nearly constant part out of the rounding.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float v) {
-    uint32_t u = __float_as_uint(v);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN -> quiet NaN
-    uint32_t lsb = (u >> 16) & 1u;
-    return (uint16_t)((u + 0x7fffu + lsb) >> 16);
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+// round to nearest, ties to even, by the hardware convert (v_cvt_pk_bf16_f32);
+// a NaN gives a quiet NaN whose payload is not specified
+__device__ __forceinline__ uint16_t bf16_hw(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
+// two values in one convert: a in the low half, b in the high half
+__device__ __forceinline__ uint32_t bf16x2_hw(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){a, b}, bf16x2_t));
 }
+// the codec's definition: as bf16_hw, every NaN to the quiet NaN 0x7fc0
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float v) { return v != v ? (uint16_t)0x7fc0 : bf16_hw(v); }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 __device__ __forceinline__ uint16_t f32_to_f16_rne(float v) {
     _Float16 h = (_Float16)v;  // hardware conversion, round to nearest even
@@ -94,6 +123,10 @@ struct StoreF64 {
     static constexpr int bytes = 8;
     __device__ static __forceinline__ C load(const T *p, long long j, C) { return p[j]; }
     __device__ static __forceinline__ T enc(C v, C) { return v; }
+    __device__ static __forceinline__ void enc2(C a, C ra, C b, C rb, T &ea, T &eb) {
+        ea = enc(a, ra);
+        eb = enc(b, rb);
+    }
     __device__ static __forceinline__ C dev(const T *p, long long j, C ref) { return p[j] - ref; }
 };
 struct StoreF32 {
@@ -102,6 +135,10 @@ struct StoreF32 {
     static constexpr int bytes = 4;
     __device__ static __forceinline__ C load(const T *p, long long j, C) { return p[j]; }
     __device__ static __forceinline__ T enc(C v, C) { return v; }
+    __device__ static __forceinline__ void enc2(C a, C ra, C b, C rb, T &ea, T &eb) {
+        ea = enc(a, ra);
+        eb = enc(b, rb);
+    }
     __device__ static __forceinline__ C dev(const T *p, long long j, C ref) { return p[j] - ref; }
 };
 struct StoreBF16 {
@@ -109,8 +146,14 @@ struct StoreBF16 {
     using C = float;
     static constexpr int bytes = 2;
     __device__ static __forceinline__ C load(const T *p, long long j, C ref) { return ref + bf16_to_f32(p[j]); }
-    __device__ static __forceinline__ T enc(C v, C ref) { return f32_to_bf16_rne(v - ref); }
+    __device__ static __forceinline__ T enc(C v, C ref) { return bf16_hw(v - ref); }
     __device__ static __forceinline__ C dev(const T *p, long long j, C) { return bf16_to_f32(p[j]); }
+    // two populations in one convert
+    __device__ static __forceinline__ void enc2(C a, C ra, C b, C rb, T &ea, T &eb) {
+        const uint32_t h = bf16x2_hw(a - ra, b - rb);
+        ea = (T)h;
+        eb = (T)(h >> 16);
+    }
 };
 struct StoreF16 {
     using T = uint16_t;
@@ -118,6 +161,10 @@ struct StoreF16 {
     static constexpr int bytes = 2;
     __device__ static __forceinline__ C load(const T *p, long long j, C ref) { return ref + f16_to_f32(p[j]); }
     __device__ static __forceinline__ T enc(C v, C ref) { return f32_to_f16_rne(v - ref); }
+    __device__ static __forceinline__ void enc2(C a, C ra, C b, C rb, T &ea, T &eb) {
+        ea = enc(a, ra);
+        eb = enc(b, rb);
+    }
     __device__ static __forceinline__ C dev(const T *p, long long j, C) { return f16_to_f32(p[j]); }
 };
 

@@ -2,16 +2,21 @@
 // step (Section 3.2 and its flowchart: moments -> Korteweg force -> u, E, T,
 // P, Phi, q^c -> attractors -> collide and stream).
 //
+// Streaming is done on the way in: the stored set is the post-collision one,
+// a cell reads its arrived population i from x - c_i and writes its collided
+// populations back to its own addresses, so every store is a full, aligned
+// row and only the loads are shifted (one element along x at most).
+//
 // Decomposition.  A workgroup owns a TX x TY tile of (x, y) columns and one
 // segment [z0, z1) of planes, which it marches through.  The non-local inputs
 // of the collision are the moments of the post-streaming state: rho on the L1
 // ball of radius 3 (Laplacian, then the Korteweg force at the face
 // neighbours), j and G at the cell and its face neighbours.  Those moments are
 // produced by the previous step: after colliding plane z the workgroup
-// gathers the pushed populations into per-thread moment accumulators of the
-// destination cells in planes z-1, z, z+1: the thread's own cell and, for the
-// first threads, one cell of the one-cell ring around the tile.  A completed
-// plane is written out as
+// gathers the collided populations into per-thread moment accumulators of the
+// cells they arrive at in the next step, in planes z-1, z, z+1: the thread's
+// own cell and, for the low lanes of every wavefront, one cell of the one-cell
+// ring around the tile.  A completed plane is written out as
 //   Mc  tile cells: the tile's own part of the sum,
 //   IN  ring cells: inbound slots of the neighbouring tile that owns the cell,
 // and the planes z0-1 and z1 of a segment, which the neighbouring segments
@@ -24,9 +29,9 @@
 //   phase A  Laplacian L(z+3); fields u, T, P, h, Lambda, F, c_s^2 of plane
 //            z+1 for the tile and its ring                         | barrier
 //   phase B  collide plane z, store rho(z+5) (loaded at the top of the
-//            iteration) over rho(z+1), push to the other buffer, write the
-//            pushed deviations to the exchange buffer, load the populations
-//            of plane z+1                                          | barrier
+//            iteration) over rho(z+1), store the collided set to the other
+//            buffer, write its deviations to the exchange buffer, load the
+//            arrived populations of plane z+1 (from planes z..z+2)  | barrier
 //   gather   moment sums of planes z-1, z, z+1 for the tile and its ring;
 //            plane z-1 is complete and is written out.
 // One workgroup per compute unit: the registers hold the prefetched plane and
@@ -72,6 +77,7 @@ template <class C, class T> struct FusedArgs {
     int ntx, nty, nseg;  // tiles along x, y; z segments
     int nlay;            // layers of Mc / IN: nz planes + 2 spill layers per segment (D = 3), 1 (D = 2)
     int chunk;           // tiles per XCD in the remapped order, 0: identity order
+    int pull;            // form of the input set: 0 arrived, 1 post-collision (read from x - c_i)
     // sums of the reference populations as hi + lo pairs (moment sums run
     // over deviations; the pair keeps the constant's rounding from biasing
     // every cell's mass the same way)
@@ -247,14 +253,36 @@ __device__ __forceinline__ void collide_cell(const Phys<C> &ph, const CollideIn<
     }
 }
 
-// element at a 32-bit byte offset from a uniform base: the addressing form
-// global memory instructions take directly (SGPR base + VGPR offset), which
-// also keeps the compiler from holding per-lane 64-bit addresses
-template <class P> __device__ __forceinline__ P &at_bytes(P *base, unsigned off) {
-    return *(P *)((char *)base + off);
+// -- buffer access ------------------------------------------------------------
+// The step addresses HBM through buffer resources (base address and byte size;
+// word 3 = 0x00020000, the raw 32-bit data format of gfx9) with a 32-bit
+// per-lane offset and a 32-bit uniform offset.  No per-lane 64-bit pointer is
+// formed, so the compiler cannot hoist one per population into registers
+// across the march, and the uniform part stays in scalar registers.  Accesses
+// at or past the resource's size read zero and write nothing; the host keeps
+// every resource below 2^31 bytes.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ Rsrc make_rsrc(const void *base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
-template <class P> __device__ __forceinline__ const P &at_bytes(const P *base, unsigned off) {
-    return *(const P *)((const char *)base + off);
+__device__ __forceinline__ void buf_ld(Rsrc r, unsigned vo, unsigned so, float &v) {
+    v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+__device__ __forceinline__ void buf_ld(Rsrc r, unsigned vo, unsigned so, double &v) {
+    v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+__device__ __forceinline__ void buf_ld(Rsrc r, unsigned vo, unsigned so, uint16_t &v) {
+    v = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
+}
+__device__ __forceinline__ void buf_st(Rsrc r, unsigned vo, unsigned so, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+}
+__device__ __forceinline__ void buf_st(Rsrc r, unsigned vo, unsigned so, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, 0);
+}
+__device__ __forceinline__ void buf_st(Rsrc r, unsigned vo, unsigned so, uint16_t v) {
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, vo, so, 0);
 }
 
 // fields of one plane's cell kept in registers between marching positions
@@ -277,13 +305,16 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
     constexpr int XS = NT + 1;           // exchange row: NT cells, then a zero
     constexpr int NR3 = (TL::R3 + NT - 1) / NT;
     constexpr int NR2 = (TL::R2 + NT - 1) / NT;
+    constexpr int NW = (NT + 63) / 64;  // wavefronts per workgroup
+    // 32-sample halves of the surrogate needed for a wave's ring cells
+    constexpr int RING_HALVES = (TL::NR + NW - 1) / NW <= 32 ? 1 : 2;
     // ring fields on R1 (x, y neighbours of the collision): u_x, u_y, T, h,
     // Lambda_x, Lambda_y
     enum { RUX, RUY, RT, RH, RLX, RLY, NRF };
     __shared__ C sRho[NRS][TL::R3];
     __shared__ C sLap[NLS][TL::R2];
     __shared__ C sRing[NFS][NRF][TL::R1];
-    __shared__ C sX[2 * Q][XS];  // exchange: deviations of the pushed f (rows 0..Q-1) and g
+    __shared__ C sX[2 * Q][XS];  // exchange: deviations of the collided f (rows 0..Q-1) and g
     __shared__ C sRacc[D == 3 ? 3 : 1][5][TL::NR];  // moment sums of the ring destinations, by plane
 
     Grid g = a.g;
@@ -315,8 +346,13 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
     const unsigned own_off = (unsigned)(gx + g.nx * gy);
     const int c3o = (ly + 3) * TL::W3 + lx + 3, c2o = (ly + 2) * TL::W2 + lx + 2, c1o = (ly + 1) * TL::W1 + lx + 1;
 
+    // ring cell rid of this thread: ring cells are dealt round-robin over
+    // the wavefronts (cell r to wave r mod NW, lane r / NW), so that every
+    // wave carries the same share of ring work and the ring cells of a wave
+    // sit in its low lanes
+    const int rid = lane * NW + (tid >> 6);
     int rx = 0, ry = 0;
-    const bool ring = ring_pos(tid, w, h, rx, ry);
+    const bool ring = ring_pos(rid, w, h, rx, ry);
     const int nring = 2 * (w + 2) + 2 * h;
     int rtile = 0, rslot = 0;
     const bool ring_dst = ring && ring_slot<TL>(g, a.ntx, a.nty, tx, ty, w, h, rx, ry, rtile, rslot);
@@ -362,40 +398,52 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
         sr[k / 2] |= vr << (16 * (k & 1));
     }
     static_assert((NT + 1) * sizeof(C) < 65536, "16-bit exchange offsets");
-    // push destinations of the own cell per axis (-1: none) and the
-    // zero-gradient duplicates (bit c+1 set: c also lands on the cell itself)
-    int xd[3], yd[3], xdup = 0, ydup = 0;
+    // streaming on the way in: the arrived population with velocity c comes
+    // from x - c of the stored post-collision set (per axis: x and nx y
+    // parts of the cell offset); the first step after an initialisation reads
+    // the arrived set in place
+    unsigned xs[3], ys[3];
 #pragma unroll
     for (int c = -1; c <= 1; c++) {
-        int p = gx + c;
-        if (!g.clampx) p = p < 0 ? p + g.nx : (p >= g.nx ? p - g.nx : p);
-        xd[c + 1] = (p >= 0 && p < g.nx) ? p : -1;
-        if (g.clampx && ((gx == 0 && c == 1) || (gx == g.nx - 1 && c == -1))) xdup |= 1 << (c + 1);
-        p = gy + c;
-        if (!g.clampy) p = p < 0 ? p + g.ny : (p >= g.ny ? p - g.ny : p);
-        yd[c + 1] = (p >= 0 && p < g.ny) ? p : -1;
-        if (g.clampy && ((gy == 0 && c == 1) || (gy == g.ny - 1 && c == -1))) ydup |= 1 << (c + 1);
+        xs[c + 1] = (unsigned)pull_coord(gx, c, g.nx, g.clampx, a.pull);
+        ys[c + 1] = (unsigned)(g.nx * pull_coord(gy, c, g.ny, g.clampy, a.pull));
     }
-    const bool has_dup = !FAST && own && (xdup | ydup);
 
-    auto zwrap = [&](int p) { return D == 3 ? (p < 0 ? p + nz * (1 + (-p - 1) / nz) : p % nz) : 0; };
+    // periodic plane index; the march only asks for planes within a few of
+    // [0, nz), so conditional adds replace a division (one pass for nz >= 6)
+    auto zwrap = [&](int p) {
+        if (D != 3) return 0;
+        while (p < 0) p += nz;
+        while (p >= nz) p -= nz;
+        return p;
+    };
     auto s4 = [](int p) { return D == 3 ? p & 3 : 0; };
     auto s2 = [](int p) { return D == 3 ? p & 1 : 0; };
-    auto s3 = [](int p) { return D == 3 ? ((p % 3) + 3) % 3 : 0; };
-    // moment k of plane zp at lane offset `off` (cells)
-    auto mom = [&](int k, int zp, unsigned off) -> C {
-        return at_bytes(a.Mci + (long long)k * a.nlay * plane, ((unsigned)zp * (unsigned)plane + off) * (unsigned)sizeof(C));
+    auto s3 = [](int p) { return D == 3 ? (int)((unsigned)(p + 3 * 4096) % 3u) : 0; };  // p > -3 * 4096
+    // side channel, layer-major Mc[layer][k][y][x]: one resource per layer
+    // over its 5 moments, the moment selected by the uniform offset
+    const unsigned mc_bytes = (unsigned)(5 * plane * (long long)sizeof(C));
+    auto mc_layer = [&](const C *M, int layer) { return make_rsrc(M + (long long)layer * 5 * plane, mc_bytes); };
+    // moment k at lane offset `off` (cells) of a layer's resource
+    auto mom = [&](Rsrc r, int k, unsigned off) -> C {
+        C v;
+        buf_ld(r, off * (unsigned)sizeof(C), (unsigned)k * (unsigned)plane * (unsigned)sizeof(C), v);
+        return v;
     };
 
+    // reference populations in LDS (read where used, uniform), so that they
+    // do not hold 2Q scalar registers through the march
+    __shared__ C sRef[2 * Q];
+    for (int r = tid; r < 2 * Q; r += NT) sRef[r] = (C)(r < Q ? a.ref.f[r] : a.ref.g[r - Q]);
     // zero columns of the exchange buffers, ring accumulators
-    if (tid < 2 * Q) sX[tid][NT] = C(0);
+    for (int r = tid; r < 2 * Q; r += NT) sX[r][NT] = C(0);
     for (int r = tid; r < (D == 3 ? 3 : 1) * 5 * TL::NR; r += NT) (&sRacc[0][0][0])[r] = C(0);
 
     // -- pipeline stages -----------------------------------------------------
     auto load_rho_regs = [&](int p, C *v) {
-        const int zp = zwrap(p);
+        const Rsrc r = mc_layer(a.Mci, zwrap(p));
 #pragma unroll
-        for (int k = 0; k < NR3; k++) v[k] = mom(0, zp, rho_off[k]);
+        for (int k = 0; k < NR3; k++) v[k] = mom(r, 0, rho_off[k]);
     };
     auto store_rho = [&](int p, const C *v) {
         C *dst = sRho[s4(p)];
@@ -404,11 +452,11 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
             if (tid + k * NT < TL::R3) dst[tid + k * NT] = v[k];
     };
     auto load_jg = [&](int p, C *jo, C *jr) {
-        const int zp = zwrap(p);
+        const Rsrc r = mc_layer(a.Mci, zwrap(p));
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            jo[k] = mom(1 + k, zp, own_off);
-            jr[k] = mom(1 + k, zp, ring_off);
+            jo[k] = mom(r, 1 + k, own_off);
+            jr[k] = mom(r, 1 + k, ring_off);
         }
     };
     auto make_lap = [&](int p) {
@@ -428,21 +476,28 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
     };
 
     unsigned long long n_fb = 0, n_eval = 0;  // surrogate statistics (lane 0 of each wave)
-    // surrogate: the small layers in LDS, the hidden weights (BF16) in global
-    // memory
+    // surrogate: all parameters in LDS; the BF16 hidden weights in rows padded
+    // to 72 elements (144 B), so that the 16-byte A-operand reads of eight
+    // consecutive rows fall on disjoint banks
+    constexpr int W2LD = 72;
     __shared__ float sNet[MLP ? mlp::OFF_W2 + 2 * mlp::H + 2 : 1];
+    __shared__ __attribute__((aligned(16))) uint16_t sW2[MLP ? mlp::H * W2LD : 1];
     mlp::Net net{};
     if constexpr (MLP) {
         for (int r = tid; r < mlp::OFF_W2; r += NT) sNet[r] = a.mlpP[r];
-        for (int r = tid; r < 2 * mlp::H + 1; r += NT) sNet[mlp::OFF_W2 + r] = a.mlpP[mlp::OFF_B2 + r];
-        net = mlp::Net{sNet + mlp::OFF_W1, sNet + mlp::OFF_B1, a.mlpW2b, nullptr, sNet + mlp::OFF_W2,
-                       sNet + mlp::OFF_W2 + mlp::H, sNet + mlp::OFF_W2 + 2 * mlp::H};
+        // b2 and the temperature row of w3 are contiguous; b3[0] follows all
+        // output rows of w3
+        for (int r = tid; r < 2 * mlp::H; r += NT) sNet[mlp::OFF_W2 + r] = a.mlpP[mlp::OFF_B2 + r];
+        if (tid == 0) sNet[mlp::OFF_W2 + 2 * mlp::H] = a.mlpP[mlp::OFF_B3];
+        for (int r = tid; r < mlp::H * mlp::H; r += NT) sW2[(r / mlp::H) * W2LD + r % mlp::H] = a.mlpW2b[r];
+        net = mlp::Net{sNet + mlp::OFF_W1, sNet + mlp::OFF_B1, sW2, nullptr, sNet + mlp::OFF_W2,
+                       sNet + mlp::OFF_W2 + mlp::H, sNet + mlp::OFF_W2 + 2 * mlp::H, W2LD};
     }
     // fields of logical plane p at one cell: R3 index c3, R2 index c2 of the
     // evaluation point, j, G of the cell.  With MLP the call is collective
     // over the wavefront.
-    auto eval_cell = [&](int p, int c3, int c2, const C *jg, bool act, C u[3], C F[3], C &rho, C &Tt, C &ee, C &P,
-                         C &cs2, C &hh, C Lam[3]) {
+    auto eval_cell = [&](int p, int c3, int c2, const C *jg, bool act, bool ring_call, C u[3], C F[3], C &rho,
+                         C &Tt, C &ee, C &P, C &cs2, C &hh, C Lam[3]) {
         const C *lc = sLap[s4(p)];
         const C *lm = sLap[s4(p - 1)];
         const C *lp = sLap[s4(p + 1)];
@@ -466,7 +521,8 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
             // van der Waals).  P and c_s^2 from the EOS at the accepted T.
             float x0n, x1n, yh[1];
             mlp::normalise(a.mlpNorm, (float)rho, (float)e, x0n, x1n);
-            mlp::forward_wave<1>(x0n, x1n, net, yh);
+            if (ring_call && RING_HALVES == 1) mlp::forward_wave<1, 1>(x0n, x1n, net, yh);
+            else mlp::forward_wave<1, 2>(x0n, x1n, net, yh);
             float Th = yh[0] * a.mlpNorm[5] + a.mlpNorm[4];
             const float res = fabsf((float)a.ph.cv * Th - (float)a.ph.a * (float)rho - (float)e) /
                               ((float)a.ph.cv * fabsf(Th));
@@ -494,7 +550,7 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
         C *rf = &sRing[s2(p)][0][0];
         {
             C u[3], F[3], rho, Tt, ee, P, cs2, hh, Lam[3];
-            eval_cell(p, c3o, c2o, jo, own, u, F, rho, Tt, ee, P, cs2, hh, Lam);
+            eval_cell(p, c3o, c2o, jo, own, false, u, F, rho, Tt, ee, P, cs2, hh, Lam);
             if (own) {
                 rf[RUX * TL::R1 + c1o] = u[0];
                 rf[RUY * TL::R1 + c1o] = u[1];
@@ -515,9 +571,9 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
             cf.h = hh;
             cf.Lz = Lam[2];
         }
-        if ((tid & ~63) < nring) {  // wavefronts holding ring cells
+        if ((tid >> 6) < nring) {  // wavefronts holding ring cells (lane 0 holds ring cell `wave`)
             C u[3], F[3], rho, Tt, ee, P, cs2, hh, Lam[3];
-            eval_cell(p, c3r, c2r, jr, ring, u, F, rho, Tt, ee, P, cs2, hh, Lam);
+            eval_cell(p, c3r, c2r, jr, ring, true, u, F, rho, Tt, ee, P, cs2, hh, Lam);
             if (ring) {
                 rf[RUX * TL::R1 + c1r] = u[0];
                 rf[RUY * TL::R1 + c1r] = u[1];
@@ -537,29 +593,31 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
     for (int q = 0; q < 3; q++)
 #pragma unroll
         for (int k = 0; k < 5; k++) acc[q][k] = C(0);
+    const Rsrc rIN = make_rsrc(a.INo, (unsigned)((long long)a.ntx * a.nty * a.nlay * 5 * TL::NR * sizeof(C)));
     // write plane p (own: acc[0]) to `layer`, then clear its ring slot; the
     // reference sums enter once per cell, with the tile-own part of its plane
     auto flush = [&](int p, int layer) {
         if (own) {
+            const Rsrc mo = mc_layer(a.Mco, layer);
             const bool plane_layer = D == 2 || layer < nz;
 #pragma unroll
             for (int k = 0; k < 5; k++) {
                 C v = acc[0][k];
                 if (plane_layer && k == 0) v = (v + a.rsf_lo) + a.rsf_hi;
                 if (plane_layer && k == 4) v = (v + a.rsg_lo) + a.rsg_hi;
-                at_bytes(a.Mco + (long long)k * a.nlay * plane,
-                         ((unsigned)layer * (unsigned)plane + own_off) * (unsigned)sizeof(C)) = v;
+                buf_st(mo, own_off * (unsigned)sizeof(C), (unsigned)k * (unsigned)plane * (unsigned)sizeof(C), v);
             }
         }
-        if (tid < nring) {
+        if (ring) {
             C *ra = &sRacc[s3(p)][0][0];
 #pragma unroll
             for (int k = 0; k < 5; k++) {
                 if (ring_dst)
-                    at_bytes(a.INo + k * TL::NR,
-                             (((unsigned)rtile * (unsigned)a.nlay + (unsigned)layer) * 5u * TL::NR + (unsigned)rslot) *
-                                 (unsigned)sizeof(C)) = ra[k * TL::NR + tid];
-                ra[k * TL::NR + tid] = C(0);
+                    buf_st(rIN,
+                           (((unsigned)rtile * (unsigned)a.nlay + (unsigned)layer) * 5u * TL::NR + (unsigned)rslot) *
+                               (unsigned)sizeof(C),
+                           (unsigned)(k * TL::NR * sizeof(C)), ra[k * TL::NR + rid]);
+                ra[k * TL::NR + rid] = C(0);
             }
         }
     };
@@ -571,7 +629,7 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
             acc[2][k] = C(0);
         }
     };
-    // exchange: the deviations of all pushed populations of the own cell
+    // exchange: the deviations of all collided populations of the own cell
     auto xwrite = [&](const C *fp, const C *gp) {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
@@ -608,7 +666,7 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
             acc[q][3] += cz * s0;
             acc[q][4] += sg;
         }
-        if (tid < nring) {
+        if (ring) {
             C s0 = 0, sx = 0, sy = 0, sg = 0;
 #pragma unroll
             for (int k = 0; k < 9; k++) {
@@ -621,11 +679,11 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
                 sg += xv(Q + i0 + k, sr, k);
             }
             C *ra = &sRacc[s3(z + (D == 3 ? r - 1 : 0))][0][0];
-            ra[0 * TL::NR + tid] += s0;
-            ra[1 * TL::NR + tid] += sx;
-            ra[2 * TL::NR + tid] += sy;
-            ra[3 * TL::NR + tid] += cz * s0;
-            ra[4 * TL::NR + tid] += sg;
+            ra[0 * TL::NR + rid] += s0;
+            ra[1 * TL::NR + rid] += sx;
+            ra[2 * TL::NR + rid] += sy;
+            ra[3 * TL::NR + rid] += cz * s0;
+            ra[4 * TL::NR + rid] += sg;
         }
     };
 
@@ -679,18 +737,32 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
         __syncthreads();
     }
 
-    // own populations of plane p into f, g (loaded one position ahead, so that
-    // their latency overlaps the exchange and the field pipeline)
+    // arrived populations of the own cell of plane p into f, g (loaded one
+    // position ahead, so that their latency overlaps the exchange and the
+    // field pipeline)
     C f[Q], gq[Q];
     auto load_pops = [&](int p) {
-        // plane base (uniform) + (i nx ny + cell) elements (32-bit)
-        const long long pb = (long long)(D == 3 ? p : 0) * Q * plane;
-        const T *fp = a.fi + pb, *gp = a.gi + pb;
+        // one resource per source plane (c_z = -1, 0, +1 read planes p + 1,
+        // p, p - 1 of the pulled set) over its Q nx ny values; uniform offset
+        // i nx ny, lane offset of the source cell
+        const unsigned pbytes = (unsigned)((long long)Q * plane * sizeof(T));
+        Rsrc rf[3], rg[3];
+#pragma unroll
+        for (int c = 0; c < (D == 3 ? 3 : 1); c++) {
+            const int ps = D == 3 ? zwrap(p - a.pull * (c - 1)) : 0;
+            rf[c] = make_rsrc(a.fi + (long long)ps * Q * plane, pbytes);
+            rg[c] = make_rsrc(a.gi + (long long)ps * Q * plane, pbytes);
+        }
 #pragma unroll
         for (int i = 0; i < Q; i++) {
-            const unsigned lo = ((unsigned)i * (unsigned)plane + own_off) * (unsigned)sizeof(T);
-            f[i] = S::load(&at_bytes(fp, lo), 0, (C)a.ref.f[i]);
-            gq[i] = S::load(&at_bytes(gp, lo), 0, (C)a.ref.g[i]);
+            const int c = D == 3 ? cz_of(i) + 1 : 0;
+            const unsigned so = (unsigned)i * (unsigned)plane * (unsigned)sizeof(T);
+            const unsigned vo = (xs[cx_of(i) + 1] + ys[cy_of(i) + 1]) * (unsigned)sizeof(T);
+            T rawf, rawg;
+            buf_ld(rf[c], vo, so, rawf);
+            buf_ld(rg[c], vo, so, rawg);
+            f[i] = S::load(&rawf, 0, sRef[i]);
+            gq[i] = S::load(&rawg, 0, sRef[Q + i]);
         }
     };
     load_pops(z0);
@@ -754,36 +826,24 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
                 jr[k] = jrn[k];
             }
         }
-        // -- stream: push to x + c_i of the other buffer; the moment sums of
-        //    the next step use the stored values (as deviations) -------------
+        // -- store the post-collision set at the cell itself (the next step
+        //    streams it on the way in); the moment sums of the next step use
+        //    the stored values (as deviations) --------------------------------
         {
+            const long long pb = (long long)(D == 3 ? z : 0) * Q * plane;
+            const unsigned pbytes = (unsigned)((long long)Q * plane * sizeof(T));
+            const Rsrc rf = make_rsrc(a.fo + pb, pbytes), rg = make_rsrc(a.go + pb, pbytes);
 #pragma unroll
             for (int i = 0; i < Q; i++) {
-                const int ix = cx_of(i), iy = cy_of(i), iz = D == 3 ? cz_of(i) : 0;
-                const T fe = S::enc(f[i], (C)a.ref.f[i]), ge = S::enc(gq[i], (C)a.ref.g[i]);
-                f[i] = S::dev(&fe, 0, (C)a.ref.f[i]);
-                gq[i] = S::dev(&ge, 0, (C)a.ref.g[i]);
-                // uniform base of the destination plane, lane byte offset of
-                // (i nx ny + cell) within it
-                const long long pb = (long long)(D == 3 ? zwrap(z + iz) : 0) * Q * plane;
-                char *fb = (char *)(a.fo + pb), *gb = (char *)(a.go + pb);
-                const unsigned zo = (unsigned)i * (unsigned)plane;
-                const int dxv = xd[ix + 1], dyv = yd[iy + 1];
-                if (FAST || (own && dxv >= 0 && dyv >= 0)) {
-                    const unsigned off = (zo + (unsigned)(dxv + g.nx * dyv)) * (unsigned)sizeof(T);
-                    *(T *)(fb + off) = fe;
-                    *(T *)(gb + off) = ge;
-                }
-                if (has_dup) {
-                    const int xs[2] = {dxv, (xdup >> (ix + 1)) & 1 ? gx : -1};
-                    const int ys[2] = {dyv, (ydup >> (iy + 1)) & 1 ? gy : -1};
-                    for (int p = 0; p < 2; p++)
-                        for (int q = 0; q < 2; q++) {
-                            if ((p | q) == 0 || xs[p] < 0 || ys[q] < 0) continue;
-                            const unsigned off = (zo + (unsigned)(xs[p] + g.nx * ys[q])) * (unsigned)sizeof(T);
-                            *(T *)(fb + off) = fe;
-                            *(T *)(gb + off) = ge;
-                        }
+                const C rf_i = sRef[i], rg_i = sRef[Q + i];
+                T fe, ge;
+                S::enc2(f[i], rf_i, gq[i], rg_i, fe, ge);
+                f[i] = S::dev(&fe, 0, rf_i);
+                gq[i] = S::dev(&ge, 0, rg_i);
+                if (own) {
+                    const unsigned so = (unsigned)i * (unsigned)plane * (unsigned)sizeof(T);
+                    buf_st(rf, own_off * (unsigned)sizeof(T), so, fe);
+                    buf_st(rg, own_off * (unsigned)sizeof(T), so, ge);
                 }
             }
         }
@@ -879,14 +939,14 @@ __global__ void __launch_bounds__(BX) k_fused_fixup(Grid g, int ntx, int nty, in
     const int lay_hi = nz + 2 * ((s + nseg - 1) % nseg) + 1;  // plane z0 of segment s, from segment s-1
     const int lay_lo = nz + 2 * ((s + 1) % nseg);             // plane z1-1 of segment s, from segment s+1
     for (int k = 0; k < 5; k++) {
-        const long long mi = ((long long)k * nlay + z) * plane + cell;
+        const long long mi = ((long long)z * 5 + k) * plane + cell;
         C v = Mc[mi] + inbound_sum<TL>(IN + ((tile * nlay + z) * 5 + k) * TL::NR, lx, ly, w, h);
         if (D == 3 && mode == 1) {
             if (z == zlo)
-                v += Mc[((long long)k * nlay + lay_hi) * plane + cell] +
+                v += Mc[((long long)lay_hi * 5 + k) * plane + cell] +
                      inbound_sum<TL>(IN + ((tile * nlay + lay_hi) * 5 + k) * TL::NR, lx, ly, w, h);
             if (z == zhi)
-                v += Mc[((long long)k * nlay + lay_lo) * plane + cell] +
+                v += Mc[((long long)lay_lo * 5 + k) * plane + cell] +
                      inbound_sum<TL>(IN + ((tile * nlay + lay_lo) * 5 + k) * TL::NR, lx, ly, w, h);
         }
         Mc[mi] = v;
@@ -899,12 +959,13 @@ __global__ void __launch_bounds__(BX) k_fused_fixup(Grid g, int ntx, int nty, in
 // segment, accumulated round by round (c_z = +1, 0, -1), the reference sums
 // added to the tile-own part, then the inbound and spill parts in fix-up
 // order.  A state restored from its populations therefore continues bitwise
-// like the run that produced it.  One thread per cell.
+// like the run that produced it.  The stored set may be in either form
+// (`pull`, see arrived_index).  One thread per cell.
 template <int D, class S, class TL>
 __global__ void __launch_bounds__(BX) k_fused_moments(Grid g, RefPops ref, typename S::C rsf_hi,
                                                       typename S::C rsf_lo, typename S::C rsg_hi, typename S::C rsg_lo,
                                                       int ntx, int nty, int nseg, int nlay, const typename S::T *fi,
-                                                      const typename S::T *gi, typename S::C *Mc) {
+                                                      const typename S::T *gi, typename S::C *Mc, int pull) {
     using C = typename S::C;
     const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
     if (x >= g.nx) return;
@@ -941,7 +1002,7 @@ __global__ void __launch_bounds__(BX) k_fused_moments(Grid g, RefPops ref, typen
             const int sxl = (g.clampx && ((x == 0 && cx == 1) || (x == g.nx - 1 && cx == -1))) ? lx : lx - cx;
             const int syl = (g.clampy && ((y == 0 && cy == 1) || (y == g.ny - 1 && cy == -1))) ? ly : ly - cy;
             const int src = ((syl < 0 ? -1 : (syl >= h ? 1 : 0)) + 1) * 3 + (sxl < 0 ? -1 : (sxl >= w ? 1 : 0)) + 1;
-            const long long pi = pop_index<Lattice<D>::Q>(g, i, D == 3 ? z : 0, x + (long long)g.nx * y);
+            const long long pi = arrived_index<D>(g, i, x, y, D == 3 ? z : 0, pull);
             const C v = S::dev(fi, pi, (C)ref.f[i]);
             const C vg = S::dev(gi, pi, (C)ref.g[i]);
             for (int q = 0; q < 9; q++) {
@@ -988,7 +1049,7 @@ __global__ void __launch_bounds__(BX) k_fused_moments(Grid g, RefPops ref, typen
             if (z == z0) v += acc[1][4][k] + inbound(1, k);
             if (z == z1 - 1) v += acc[2][4][k] + inbound(2, k);
         }
-        Mc[((long long)k * nlay + (D == 3 ? z : 0)) * plane + pc] = v;
+        Mc[((long long)(D == 3 ? z : 0) * 5 + k) * plane + pc] = v;
     }
 }
 

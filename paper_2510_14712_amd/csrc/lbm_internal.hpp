@@ -13,6 +13,7 @@ struct lbm_ctx {
     void *f[2] = {nullptr, nullptr};  // population state buffers (ping-pong)
     void *g[2] = {nullptr, nullptr};
     int cur = 0;                      // index of the buffer holding the state
+    int pulled = 0;                   // 1: the state is the post-collision set (read from x - c_i)
     void *work = nullptr;             // per-cell field arrays
     lbm::RefPops ref;
     hipStream_t stream = nullptr;
@@ -28,7 +29,7 @@ struct lbm_ctx {
     uint16_t mlp_w2b_host[64 * 64];
     // single-pass fused step: moment side channel of the current state
     bool fused = false;
-    void *Mc[2] = {nullptr, nullptr};  // [5][nlay][ny][nx]
+    void *Mc[2] = {nullptr, nullptr};  // [nlay][5][ny][nx]
     void *IN[2] = {nullptr, nullptr};  // [tiles][nlay][5][slots]
     size_t mc_bytes = 0, in_bytes = 0;
     int ntx = 0, nty = 0, nseg = 1, nlay = 0, chunk = 0;

@@ -120,7 +120,8 @@ __global__ void __launch_bounds__(BX) k_init(Grid g, Phys<double> ph, RefPops re
 // ---------------------------------------------------------------------------
 template <int D, class S>
 __global__ void __launch_bounds__(BX) k_moments(Grid g, RefPops ref, const typename S::T *__restrict__ fi,
-                                                const typename S::T *__restrict__ gi, Fields<typename S::C> fl) {
+                                                const typename S::T *__restrict__ gi, Fields<typename S::C> fl,
+                                                int pull) {
     using C = typename S::C;
     constexpr int Q = Lattice<D>::Q;
     int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
@@ -129,7 +130,7 @@ __global__ void __launch_bounds__(BX) k_moments(Grid g, RefPops ref, const typen
     C rho = 0, J[3] = {0, 0, 0}, G = 0;
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-        const long long pi = pop_index<Q>(g, i, z, x + (long long)g.nx * y);
+        const long long pi = arrived_index<D>(g, i, x, y, z, pull);
         C f = S::load(fi, pi, (C)ref.f[i]);
         rho += f;
         if (cx_of(i)) J[0] += cx_of(i) > 0 ? f : -f;

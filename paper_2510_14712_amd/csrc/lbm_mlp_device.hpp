@@ -23,14 +23,15 @@ constexpr int OFF_W1 = 0, OFF_B1 = 128, OFF_W2 = 192, OFF_B2 = 4288, OFF_W3 = 43
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+// tanh x = 1 - 2 / (1 + e^{2x}): one exp2, one reciprocal and an FMA; both
+// saturations come out exactly (e^{2x} = inf gives 1, e^{2x} = 0 gives -1);
+// absolute error about 2e-7
 __device__ __forceinline__ float fast_tanh(float x) {
-    const float ax = fminf(fabsf(x), 15.0f);
-    const float e = __expf(-2.0f * ax);
-    const float t = __fdividef(1.0f - e, 1.0f + e);
-    return copysignf(t, x);
+    const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // 2 log2(e)
+    return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
 }
 
-__device__ __forceinline__ __bf16 to_bf16(float v) { return __builtin_bit_cast(__bf16, f32_to_bf16_rne(v)); }
+__device__ __forceinline__ __bf16 to_bf16(float v) { return __builtin_bit_cast(__bf16, bf16_hw(v)); }
 
 __device__ __forceinline__ void normalise(const float *norm, float rho, float e, float &x0, float &x1) {
     x0 = 2.0f * (rho - norm[0]) / (norm[1] - norm[0]) - 1.0f;
@@ -38,32 +39,35 @@ __device__ __forceinline__ void normalise(const float *norm, float rho, float e,
 }
 
 // Parameter pointers of one forward pass: the small layers may live in LDS,
-// the 64 x 64 hidden weights are read as BF16 (w2b) or rounded on the fly
-// from FP32 (w2b null: w2).
+// the 64 x 64 hidden weights are read as BF16 (w2b, rows of w2_ld elements,
+// global memory or LDS) or rounded on the fly from FP32 (w2b null: w2).
 struct Net {
     const float *w1, *b1;  // [64][2], [64]
-    const uint16_t *w2b;   // [64][64] BF16, row-major [out][in], or null
+    const uint16_t *w2b;   // [64][w2_ld] BF16, row-major [out][in], or null
     const float *w2;       // [64][64] FP32 (when w2b is null)
     const float *b2, *w3, *b3;  // [64], [NOUT][64], [NOUT]
+    int w2_ld;
 };
 __device__ __forceinline__ Net net_of(const float *P, const uint16_t *W2b) {
-    return Net{P + OFF_W1, P + OFF_B1, W2b, P + OFF_W2, P + OFF_B2, P + OFF_W3, P + OFF_B3};
+    return Net{P + OFF_W1, P + OFF_B1, W2b, P + OFF_W2, P + OFF_B2, P + OFF_W3, P + OFF_B3, H};
 }
 
 // Returns the normalised outputs 0..NOUT-1 of this lane's sample.  Every lane
-// of the wavefront must call with uniform control flow.  The two 32-sample
-// halves of the wavefront go through the hidden layer one after the other and
-// each k-step's B operand is formed just before its MFMA, which keeps the
-// live registers low.
-template <int NOUT>
+// of the wavefront must call with uniform control flow.  The 32-sample halves
+// of the wavefront go through the hidden layer one after the other and each
+// k-step's B operand is formed just before its MFMA, which keeps the live
+// registers low.  HALVES = 1 evaluates only the samples of lanes 0..31 (the
+// outputs of lanes 32..63 are left unset).
+template <int NOUT, int HALVES = 2>
 __device__ __forceinline__ void forward_wave(float x0, float x1, const Net &p, float y[NOUT]) {
+    static_assert(HALVES == 1 || HALVES == 2, "one or two 32-sample halves");
     const int lane = threadIdx.x & 63;
     const int hh = lane >> 5, c = lane & 31;
     // byte offset of this lane's A-operand row segment in the BF16 weights
     // (uniform base + 32-bit lane offset + constant per (mt, ks))
-    const unsigned a_off = (unsigned)(c * H + 8 * hh) * 2u;
+    const unsigned a_off = (unsigned)(c * p.w2_ld + 8 * hh) * 2u;
 #pragma unroll
-    for (int nt = 0; nt < 2; nt++) {
+    for (int nt = 0; nt < HALVES; nt++) {
         // inputs of the sample this lane serves in the B operand
         const float xs0 = __shfl(x0, 32 * nt + c, 64), xs1 = __shfl(x1, 32 * nt + c, 64);
         f32x16 acc[2];
@@ -73,17 +77,25 @@ __device__ __forceinline__ void forward_wave(float x0, float x1, const Net &p, f
             for (int v = 0; v < 16; v++) acc[mt][v] = 0.0f;
 #pragma unroll
         for (int ks = 0; ks < 4; ks++) {
-            bf16x8 b;
+            float hv[8];
 #pragma unroll
             for (int j = 0; j < 8; j++) {
                 const int k = 16 * ks + 8 * hh + j;
-                b[j] = to_bf16(fast_tanh(fmaf(p.w1[2 * k], xs0, fmaf(p.w1[2 * k + 1], xs1, p.b1[k]))));
+                hv[j] = fast_tanh(fmaf(p.w1[2 * k], xs0, fmaf(p.w1[2 * k + 1], xs1, p.b1[k])));
             }
+            // two activations per convert
+            uint4 bp;
+            bp.x = bf16x2_hw(hv[0], hv[1]);
+            bp.y = bf16x2_hw(hv[2], hv[3]);
+            bp.z = bf16x2_hw(hv[4], hv[5]);
+            bp.w = bf16x2_hw(hv[6], hv[7]);
+            const bf16x8 b = __builtin_bit_cast(bf16x8, bp);
 #pragma unroll
             for (int mt = 0; mt < 2; mt++) {
                 bf16x8 a;
                 if (p.w2b) {
-                    const uint4 raw = *(const uint4 *)((const char *)p.w2b + a_off + (unsigned)((32 * mt * H + 16 * ks) * 2));
+                    const uint4 raw =
+                        *(const uint4 *)((const char *)p.w2b + a_off + (unsigned)((32 * mt * p.w2_ld + 16 * ks) * 2));
                     a = __builtin_bit_cast(bf16x8, raw);
                 } else {
                     const float *row = p.w2 + (32 * mt + c) * H + 16 * ks + 8 * hh;

@@ -141,6 +141,37 @@ def test_step_with_surrogate_and_fallback():
         assert e <= 1e-5
 
 
+def test_step_surrogate_accepted_where_residual_allows():
+    """Thresholds the BF16 network can meet: at 1e-2 (relative, in c_v T) the
+    trained surrogate is accepted on most cells and an untrained one almost
+    nowhere; tightening to 1e-3 sends more cells to the exact fallback and
+    holds the density within 1e-3 of the FP64 oracle."""
+    lbm = _lbm()
+    params, norm, _ = _train()
+    c = ST["tgv_3d_256"]
+    shape = (40, 32, 24)
+    rho, u, T = inputs.taylor_green(shape, c["seed"], c["rho0"], c["T0"], c["U0"], c["noise"])
+    p = oracle.Params(3, shape, **KW)
+    fr, gr = oracle.run(p, *oracle.init(p, rho, u, T), 50)
+    ref = oracle.fields(p, fr, gr)
+    fracs, errs = {}, {}
+    cases = (("trained", params, 1e-2), ("trained", params, 1e-3),
+             ("untrained", inputs.mlp_params(4).astype(np.float32), 1e-2))
+    for name, w, tol in cases:
+        _say(f"case step eos=mlp tol={tol} {name}")
+        with lbm.Lattice(3, shape, storage="f32", eos="mlp", mlp_tol=tol, **KW) as lat:
+            lat.mlp_set(w, norm)
+            lat.init(rho, u, T).step(50)
+            mom = {k: v.cpu().numpy() for k, v in lat.moments().items()}
+            fracs[name, tol] = lat.mlp_stats()
+        errs[name, tol] = {k: rel_l2(mom[k], ref[k]) for k in ("rho", "u", "T")}
+        _say(f"  fallback fraction {fracs[name, tol]:.4f}, per-field rel-L2 {errs[name, tol]}")
+    assert fracs["trained", 1e-2] < 0.1
+    assert fracs["untrained", 1e-2] > 0.5
+    assert fracs["trained", 1e-3] >= fracs["trained", 1e-2]
+    assert errs["trained", 1e-3]["rho"] <= 1e-3
+
+
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
 def test_deviation_storage_error_per_field(storage):
     lbm = _lbm()
