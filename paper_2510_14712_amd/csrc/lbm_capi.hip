@@ -190,18 +190,25 @@ static void make_ref(const lbm_params &p, int D, RefPops &ref) {
 // ---------------------------------------------------------------------------
 // dispatch over (lattice, storage)
 // ---------------------------------------------------------------------------
-// tile of the fused step: FP64 uses a smaller tile to fit the LDS budget
-template <class S> using TileOf = typename std::conditional<std::is_same<S, StoreF64>::value, Tile<16, 8>, Tile<32, 8>>::type;
+// tile of the fused step.  FP64 uses a smaller tile to fit the LDS budget;
+// the other forms take a wide 64 x 4 tile (fewer x-shifted row fragments per
+// plane), except with the surrogate, whose 32 x 8 tile has 84 ring cells: 21
+// per wavefront, one 32-sample half of the network.
+template <class S, bool MLP>
+using TileOf = typename std::conditional<std::is_same<S, StoreF64>::value, Tile<16, 8>,
+                                         typename std::conditional<MLP, Tile<32, 8>, Tile<64, 4>>::type>::type;
 
 template <int D, class S> struct Impl {
     using C = typename S::C;
     using T = typename S::T;
-    using TL = TileOf<S>;
+    static bool mlp(const lbm_ctx *c) { return std::is_same<C, float>::value && c->p.eos == LBM_EOS_MLP; }
 
     // complete moments of the current state into the side channel; inbound
     // slots of both buffers start at zero (slots behind a zero-gradient wall
     // are never written afterwards, the fix-up pass adds them as zeros)
-    static int fused_prepare(lbm_ctx *c) {
+    static int fused_prepare(lbm_ctx *c) { return mlp(c) ? fused_prepare_t<true>(c) : fused_prepare_t<false>(c); }
+    template <bool M> static int fused_prepare_t(lbm_ctx *c) {
+        using TL = TileOf<S, M>;
         if (!c->fused) return LBM_OK;
         for (int s = 0; s < 2; s++) {
             if (hipMemsetAsync(c->Mc[s], 0, c->mc_bytes, c->stream) != hipSuccess ||
@@ -230,7 +237,9 @@ template <int D, class S> struct Impl {
         rs[3] = (C)(sg - (double)rs[2]);
     }
     // the fused step proper (kind 0 of step_timed)
-    static void fused_main(lbm_ctx *c) {
+    static void fused_main(lbm_ctx *c) { mlp(c) ? fused_main_t<true>(c) : fused_main_t<false>(c); }
+    template <bool M> static void fused_main_t(lbm_ctx *c) {
+        using TL = TileOf<S, M>;
         FusedArgs<C, T> a;
         a.g = c->grid;
         a.ph = make_phys<C>(c->p);
@@ -251,9 +260,7 @@ template <int D, class S> struct Impl {
         }
         const int nxt = 1 - c->cur;
         a.fi = (const T *)c->f[c->cur];
-        a.gi = (const T *)c->g[c->cur];
         a.fo = (T *)c->f[nxt];
-        a.go = (T *)c->g[nxt];
         a.Mci = (const C *)c->Mc[c->cur];
         a.Mco = (C *)c->Mc[nxt];
         a.INo = (C *)c->IN[nxt];
@@ -267,18 +274,18 @@ template <int D, class S> struct Impl {
         // partial-tile handling
         const bool fast = c->p.nx % TL::TX == 0 && c->p.ny % TL::TY == 0 && c->p.bc[0] == LBM_BC_PERIODIC &&
                           c->p.bc[1] == LBM_BC_PERIODIC;
-        if constexpr (std::is_same<C, float>::value) {
-            if (c->p.eos == LBM_EOS_MLP) {
-                if (fast) hipLaunchKernelGGL((k_fused<D, S, TL, true, true>), grid, dim3(TL::NT), 0, c->stream, a);
-                else hipLaunchKernelGGL((k_fused<D, S, TL, true, false>), grid, dim3(TL::NT), 0, c->stream, a);
-                return;
-            }
+        if constexpr (M && std::is_same<C, float>::value) {
+            if (fast) hipLaunchKernelGGL((k_fused<D, S, TL, true, true>), grid, dim3(TL::NT), 0, c->stream, a);
+            else hipLaunchKernelGGL((k_fused<D, S, TL, true, false>), grid, dim3(TL::NT), 0, c->stream, a);
+        } else {
+            if (fast) hipLaunchKernelGGL((k_fused<D, S, TL, false, true>), grid, dim3(TL::NT), 0, c->stream, a);
+            else hipLaunchKernelGGL((k_fused<D, S, TL, false, false>), grid, dim3(TL::NT), 0, c->stream, a);
         }
-        if (fast) hipLaunchKernelGGL((k_fused<D, S, TL, false, true>), grid, dim3(TL::NT), 0, c->stream, a);
-        else hipLaunchKernelGGL((k_fused<D, S, TL, false, false>), grid, dim3(TL::NT), 0, c->stream, a);
     }
     // completes the output moments (kind 1 of step_timed) and flips the state
-    static void fused_fixup(lbm_ctx *c) {
+    static void fused_fixup(lbm_ctx *c) { mlp(c) ? fused_fixup_t<true>(c) : fused_fixup_t<false>(c); }
+    template <bool M> static void fused_fixup_t(lbm_ctx *c) {
+        using TL = TileOf<S, M>;
         const int nxt = 1 - c->cur;
         const long long per = (long long)c->ntx * c->nty * TL::PMAX;
         hipLaunchKernelGGL((k_fused_fixup<D, TL, C>), dim3((unsigned)((per + BX - 1) / BX), c->p.nz), dim3(BX), 0,
@@ -420,7 +427,9 @@ template <int D, class S> struct Impl {
         int rc = last_launch();
         return rc ? rc : fused_prepare(c);
     }
-    static void tiles(lbm_ctx *c) {
+    static void tiles(lbm_ctx *c) { mlp(c) ? tiles_t<true>(c) : tiles_t<false>(c); }
+    template <bool M> static void tiles_t(lbm_ctx *c) {
+        using TL = TileOf<S, M>;
         c->ntx = (c->p.nx + TL::TX - 1) / TL::TX;
         c->nty = (c->p.ny + TL::TY - 1) / TL::TY;
         const long long ntiles = (long long)c->ntx * c->nty;
@@ -555,8 +564,9 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
     size_t nfield = (size_t)(8 + 4 * c->D);
     size_t field_bytes = nfield * N * cb;
     c->red_blocks = 1024;
-    bool ok = hipMalloc(&c->f[0], pop_bytes) == hipSuccess && hipMalloc(&c->f[1], pop_bytes) == hipSuccess &&
-              hipMalloc(&c->g[0], pop_bytes) == hipSuccess && hipMalloc(&c->g[1], pop_bytes) == hipSuccess &&
+    // one buffer per ping-pong slot holds both sets, f_i and g_i side by side
+    // (the g pointer is the f buffer offset by one element)
+    bool ok = hipMalloc(&c->f[0], 2 * pop_bytes) == hipSuccess && hipMalloc(&c->f[1], 2 * pop_bytes) == hipSuccess &&
               hipMalloc(&c->work, field_bytes) == hipSuccess &&
               hipMalloc((void **)&c->red_partials, sizeof(double) * RED_VALS * c->red_blocks) == hipSuccess &&
               hipMalloc((void **)&c->red_out, sizeof(double) * RED_VALS) == hipSuccess &&
@@ -564,6 +574,8 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
               hipMalloc((void **)&c->mlp_params, sizeof(float) * (LBM_MLP_NPARAMS + 64)) == hipSuccess &&
               hipMalloc((void **)&c->mlp_norm, sizeof(float) * 16) == hipSuccess &&
               hipMalloc((void **)&c->mlp_w2b, sizeof(uint16_t) * 64 * 64) == hipSuccess;
+    if (ok)
+        for (int k = 0; k < 2; k++) c->g[k] = (char *)c->f[k] + sb;
     if (!ok) {
         lbm_note(hipGetLastError());
         lbm_destroy(c);
@@ -578,7 +590,7 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
         // layer, the inbound slots) must stay below 2^31 bytes; larger
         // lattices take the multi-kernel path
         const long long plane = (long long)params->nx * params->ny, lim = 1LL << 31;
-        if ((long long)c->Q * plane * sb >= lim || 5 * plane * cb >= lim || (long long)c->in_bytes >= lim)
+        if (2LL * c->Q * plane * sb >= lim || 5 * plane * cb >= lim || (long long)c->in_bytes >= lim)
             c->fused = false;
     }
     if (c->fused) {
@@ -602,7 +614,7 @@ void lbm_destroy(lbm_ctx *c) {
     if (!c) return;
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
-    void *ptrs[] = {c->f[0], c->f[1], c->g[0], c->g[1], c->work, c->red_partials, c->red_out,
+    void *ptrs[] = {c->f[0], c->f[1], c->work, c->red_partials, c->red_out,
                     c->mlp_counters, c->mlp_params, c->mlp_norm, c->mlp_w2b, c->Mc[0], c->Mc[1], c->IN[0], c->IN[1]};
     for (void *p : ptrs)
         if (p) hipFree(p);

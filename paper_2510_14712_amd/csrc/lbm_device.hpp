@@ -59,12 +59,16 @@ struct Grid {
     long long N;
 };
 
-// Internal population layout, plane-major: pops[(z Q + i) nx ny + y nx + x].
-// The Q populations of one plane lie within Q nx ny values, so a kernel
-// addresses a plane with one 64-bit base and 32-bit offsets.  (The public
-// layout of lbm_get/set_populations stays pops[i N + cell].)
+// Internal population layout: plane-major, with f_i and g_i of a cell side by
+// side, pops[((z Q + i) nx ny + y nx + x) 2 + {0: f, 1: g}].  The Q population
+// pairs of one plane lie within 2 Q nx ny values, so a kernel addresses a
+// plane with one 64-bit base and 32-bit offsets, and one load or store moves
+// both populations of a direction.  pop_index gives the element index of f;
+// the g array is the same buffer offset by one element, so f[j] and g[j]
+// address the pair.  (The public layout of lbm_get/set_populations stays
+// pops[i N + cell].)
 template <int Q> __host__ __device__ __forceinline__ long long pop_index(const Grid &g, int i, long long z, long long xy) {
-    return (z * Q + i) * ((long long)g.nx * g.ny) + xy;
+    return 2 * ((z * Q + i) * ((long long)g.nx * g.ny) + xy);
 }
 
 // Stored population sets come in two forms.  After initialisation (and after

@@ -82,8 +82,8 @@ template <class C, class T> struct FusedArgs {
     // over deviations; the pair keeps the constant's rounding from biasing
     // every cell's mass the same way)
     C rsf_hi, rsf_lo, rsg_hi, rsg_lo;
-    const T *fi, *gi;
-    T *fo, *go;
+    const T *fi;  // input pair buffer (f_i, g_i side by side)
+    T *fo;        // output pair buffer
     const C *Mci;  // complete moments of the input state, [5][nlay][ny][nx]
     C *Mco, *INo;  // output: tile-own partial sums, inbound slots [tiles][nlay][5][NR]
     // surrogate equation of state (kernels built with MLP)
@@ -283,6 +283,37 @@ __device__ __forceinline__ void buf_st(Rsrc r, unsigned vo, unsigned so, double 
 }
 __device__ __forceinline__ void buf_st(Rsrc r, unsigned vo, unsigned so, uint16_t v) {
     __builtin_amdgcn_raw_buffer_store_b16(v, r, vo, so, 0);
+}
+// the (f_i, g_i) pair of one cell in one access
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// (vector elements are copied to scalars before __builtin_bit_cast: this
+// compiler's bit_cast of an element expression such as v.y reads element 0)
+__device__ __forceinline__ void pair_ld(Rsrc r, unsigned vo, unsigned so, float &f, float &g) {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+    const unsigned lo = v.x, hi = v.y;
+    f = __builtin_bit_cast(float, lo);
+    g = __builtin_bit_cast(float, hi);
+}
+__device__ __forceinline__ void pair_ld(Rsrc r, unsigned vo, unsigned so, double &f, double &g) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+    f = __builtin_bit_cast(double, (u32x2){v.x, v.y});
+    g = __builtin_bit_cast(double, (u32x2){v.z, v.w});
+}
+__device__ __forceinline__ void pair_ld(Rsrc r, unsigned vo, unsigned so, uint16_t &f, uint16_t &g) {
+    const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0);
+    f = (uint16_t)v;
+    g = (uint16_t)(v >> 16);
+}
+__device__ __forceinline__ void pair_st(Rsrc r, unsigned vo, unsigned so, float f, float g) {
+    __builtin_amdgcn_raw_buffer_store_b64((u32x2){__builtin_bit_cast(unsigned, f), __builtin_bit_cast(unsigned, g)}, r,
+                                          vo, so, 0);
+}
+__device__ __forceinline__ void pair_st(Rsrc r, unsigned vo, unsigned so, double f, double g) {
+    const u32x2 a = __builtin_bit_cast(u32x2, f), b = __builtin_bit_cast(u32x2, g);
+    __builtin_amdgcn_raw_buffer_store_b128((u32x4){a.x, a.y, b.x, b.y}, r, vo, so, 0);
+}
+__device__ __forceinline__ void pair_st(Rsrc r, unsigned vo, unsigned so, uint16_t f, uint16_t g) {
+    __builtin_amdgcn_raw_buffer_store_b32((unsigned)f | ((unsigned)g << 16), r, vo, so, 0);
 }
 
 // fields of one plane's cell kept in registers between marching positions
@@ -743,24 +774,23 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
     C f[Q], gq[Q];
     auto load_pops = [&](int p) {
         // one resource per source plane (c_z = -1, 0, +1 read planes p + 1,
-        // p, p - 1 of the pulled set) over its Q nx ny values; uniform offset
-        // i nx ny, lane offset of the source cell
-        const unsigned pbytes = (unsigned)((long long)Q * plane * sizeof(T));
-        Rsrc rf[3], rg[3];
+        // p, p - 1 of the pulled set) over its Q nx ny pairs; uniform offset
+        // of direction i, lane offset of the source cell
+        constexpr unsigned PB = 2 * sizeof(T);  // bytes of an (f, g) pair
+        const unsigned pbytes = (unsigned)((long long)Q * plane * PB);
+        Rsrc rp[3];
 #pragma unroll
         for (int c = 0; c < (D == 3 ? 3 : 1); c++) {
             const int ps = D == 3 ? zwrap(p - a.pull * (c - 1)) : 0;
-            rf[c] = make_rsrc(a.fi + (long long)ps * Q * plane, pbytes);
-            rg[c] = make_rsrc(a.gi + (long long)ps * Q * plane, pbytes);
+            rp[c] = make_rsrc(a.fi + 2 * (long long)ps * Q * plane, pbytes);
         }
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             const int c = D == 3 ? cz_of(i) + 1 : 0;
-            const unsigned so = (unsigned)i * (unsigned)plane * (unsigned)sizeof(T);
-            const unsigned vo = (xs[cx_of(i) + 1] + ys[cy_of(i) + 1]) * (unsigned)sizeof(T);
+            const unsigned so = (unsigned)i * (unsigned)plane * PB;
+            const unsigned vo = (xs[cx_of(i) + 1] + ys[cy_of(i) + 1]) * PB;
             T rawf, rawg;
-            buf_ld(rf[c], vo, so, rawf);
-            buf_ld(rg[c], vo, so, rawg);
+            pair_ld(rp[c], vo, so, rawf, rawg);
             f[i] = S::load(&rawf, 0, sRef[i]);
             gq[i] = S::load(&rawg, 0, sRef[Q + i]);
         }
@@ -830,9 +860,9 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
         //    streams it on the way in); the moment sums of the next step use
         //    the stored values (as deviations) --------------------------------
         {
-            const long long pb = (long long)(D == 3 ? z : 0) * Q * plane;
-            const unsigned pbytes = (unsigned)((long long)Q * plane * sizeof(T));
-            const Rsrc rf = make_rsrc(a.fo + pb, pbytes), rg = make_rsrc(a.go + pb, pbytes);
+            constexpr unsigned PB = 2 * sizeof(T);  // bytes of an (f, g) pair
+            const long long pb = 2 * (long long)(D == 3 ? z : 0) * Q * plane;
+            const Rsrc ro = make_rsrc(a.fo + pb, (unsigned)((long long)Q * plane * PB));
 #pragma unroll
             for (int i = 0; i < Q; i++) {
                 const C rf_i = sRef[i], rg_i = sRef[Q + i];
@@ -840,11 +870,7 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
                 S::enc2(f[i], rf_i, gq[i], rg_i, fe, ge);
                 f[i] = S::dev(&fe, 0, rf_i);
                 gq[i] = S::dev(&ge, 0, rg_i);
-                if (own) {
-                    const unsigned so = (unsigned)i * (unsigned)plane * (unsigned)sizeof(T);
-                    buf_st(rf, own_off * (unsigned)sizeof(T), so, fe);
-                    buf_st(rg, own_off * (unsigned)sizeof(T), so, ge);
-                }
+                if (own) pair_st(ro, own_off * PB, (unsigned)i * (unsigned)plane * PB, fe, ge);
             }
         }
 

@@ -10,8 +10,8 @@ struct lbm_ctx {
     lbm_params p;
     lbm::Grid grid;
     int D, Q, store_bytes;
-    void *f[2] = {nullptr, nullptr};  // population state buffers (ping-pong)
-    void *g[2] = {nullptr, nullptr};
+    void *f[2] = {nullptr, nullptr};  // population state buffers (ping-pong), f_i and g_i side by side
+    void *g[2] = {nullptr, nullptr};  // f[k] + one element (not separately allocated)
     int cur = 0;                      // index of the buffer holding the state
     int pulled = 0;                   // 1: the state is the post-collision set (read from x - c_i)
     void *work = nullptr;             // per-cell field arrays
