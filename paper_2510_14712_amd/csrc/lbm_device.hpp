@@ -124,7 +124,10 @@ __device__ __forceinline__ float f16_to_f32(uint16_t h) { return (float)__builti
 struct StoreF64 {
     using T = double;
     using C = double;
+    using X = double;  // exchange type (deviation as computed)
     static constexpr int bytes = 8;
+    __device__ static __forceinline__ X xenc(C d) { return d; }
+    __device__ static __forceinline__ C xdec(X x) { return x; }
     __device__ static __forceinline__ C load(const T *p, long long j, C) { return p[j]; }
     __device__ static __forceinline__ T enc(C v, C) { return v; }
     __device__ static __forceinline__ void enc2(C a, C ra, C b, C rb, T &ea, T &eb) {
@@ -136,7 +139,10 @@ struct StoreF64 {
 struct StoreF32 {
     using T = float;
     using C = float;
+    using X = float;
     static constexpr int bytes = 4;
+    __device__ static __forceinline__ X xenc(C d) { return d; }
+    __device__ static __forceinline__ C xdec(X x) { return x; }
     __device__ static __forceinline__ C load(const T *p, long long j, C) { return p[j]; }
     __device__ static __forceinline__ T enc(C v, C) { return v; }
     __device__ static __forceinline__ void enc2(C a, C ra, C b, C rb, T &ea, T &eb) {
@@ -148,7 +154,10 @@ struct StoreF32 {
 struct StoreBF16 {
     using T = uint16_t;
     using C = float;
+    using X = uint16_t;  // a stored deviation is a BF16 value: its code, exactly
     static constexpr int bytes = 2;
+    __device__ static __forceinline__ X xenc(C d) { return (X)(__float_as_uint(d) >> 16); }
+    __device__ static __forceinline__ C xdec(X x) { return bf16_to_f32(x); }
     __device__ static __forceinline__ C load(const T *p, long long j, C ref) { return ref + bf16_to_f32(p[j]); }
     __device__ static __forceinline__ T enc(C v, C ref) { return bf16_hw(v - ref); }
     __device__ static __forceinline__ C dev(const T *p, long long j, C) { return bf16_to_f32(p[j]); }
@@ -162,7 +171,10 @@ struct StoreBF16 {
 struct StoreF16 {
     using T = uint16_t;
     using C = float;
+    using X = uint16_t;  // an FP16 value: its code, exactly
     static constexpr int bytes = 2;
+    __device__ static __forceinline__ X xenc(C d) { return f32_to_f16_rne(d); }
+    __device__ static __forceinline__ C xdec(X x) { return f16_to_f32(x); }
     __device__ static __forceinline__ C load(const T *p, long long j, C ref) { return ref + f16_to_f32(p[j]); }
     __device__ static __forceinline__ T enc(C v, C ref) { return f32_to_f16_rne(v - ref); }
     __device__ static __forceinline__ void enc2(C a, C ra, C b, C rb, T &ea, T &eb) {

@@ -324,8 +324,15 @@ template <class C> struct CenterF {
 // FAST: every tile is full and the x, y axes are periodic (no zero-gradient
 // wall in the tile plane); the per-lane wall and partial-tile cases then fold
 // away at compile time.
+// Waves per SIMD asked of the compiler: two for the 16-bit forms without the
+// surrogate (their LDS, with a 16-bit exchange, fits two workgroups per CU;
+// measured 1.4x faster than one), one otherwise (the registers then hold the
+// prefetched plane; for FP32, exchanging f and g in turn to fit two
+// workgroups was slower).
+template <class S, bool MLP> constexpr int fused_occupancy() { return sizeof(typename S::T) == 2 ? 2 : 1; }
+
 template <int D, class S, class TL, bool MLP, bool FAST>
-__global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, typename S::T> a) {
+__global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(FusedArgs<typename S::C, typename S::T> a) {
     using C = typename S::C;
     using T = typename S::T;
     constexpr int Q = Lattice<D>::Q;
@@ -345,7 +352,9 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
     __shared__ C sRho[NRS][TL::R3];
     __shared__ C sLap[NLS][TL::R2];
     __shared__ C sRing[NFS][NRF][TL::R1];
-    __shared__ C sX[2 * Q][XS];  // exchange: deviations of the collided f (rows 0..Q-1) and g
+    using XT = typename S::X;
+    constexpr int GROW = Q;          // first exchange row of g
+    __shared__ XT sX[2 * Q][XS];  // exchange: deviations of the collided f (rows 0..Q-1) and g
     __shared__ C sRacc[D == 3 ? 3 : 1][5][TL::NR];  // moment sums of the ring destinations, by plane
 
     Grid g = a.g;
@@ -421,14 +430,14 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
     for (int k = 0; k < 9; k++) {
         const int cx = k % 3 - 1, cy = k / 3 - 1;
         int sx = gather_src(lx, cx, x0, g.nx, g.clampx, w), sy = gather_src(ly, cy, y0, g.ny, g.clampy, h);
-        const unsigned vo = (unsigned)((own && sx >= 0 && sy >= 0) ? sy * TX + sx : NT) * sizeof(C);
+        const unsigned vo = (unsigned)((own && sx >= 0 && sy >= 0) ? sy * TX + sx : NT) * sizeof(XT);
         sx = gather_src(rx, cx, x0, g.nx, g.clampx, w);
         sy = gather_src(ry, cy, y0, g.ny, g.clampy, h);
-        const unsigned vr = (unsigned)((ring_dst && sx >= 0 && sy >= 0) ? sy * TX + sx : NT) * sizeof(C);
+        const unsigned vr = (unsigned)((ring_dst && sx >= 0 && sy >= 0) ? sy * TX + sx : NT) * sizeof(XT);
         so[k / 2] |= vo << (16 * (k & 1));
         sr[k / 2] |= vr << (16 * (k & 1));
     }
-    static_assert((NT + 1) * sizeof(C) < 65536, "16-bit exchange offsets");
+    static_assert((NT + 1) * sizeof(XT) < 65536, "16-bit exchange offsets");
     // streaming on the way in: the arrived population with velocity c comes
     // from x - c of the stored post-collision set (per axis: x and nx y
     // parts of the cell offset); the first step after an initialisation reads
@@ -467,7 +476,7 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
     __shared__ C sRef[2 * Q];
     for (int r = tid; r < 2 * Q; r += NT) sRef[r] = (C)(r < Q ? a.ref.f[r] : a.ref.g[r - Q]);
     // zero columns of the exchange buffers, ring accumulators
-    for (int r = tid; r < 2 * Q; r += NT) sX[r][NT] = C(0);
+    for (int r = tid; r < 2 * Q; r += NT) sX[r][NT] = S::xenc(C(0));
     for (int r = tid; r < (D == 3 ? 3 : 1) * 5 * TL::NR; r += NT) (&sRacc[0][0][0])[r] = C(0);
 
     // -- pipeline stages -----------------------------------------------------
@@ -660,63 +669,63 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
             acc[2][k] = C(0);
         }
     };
-    // exchange: the deviations of all collided populations of the own cell
-    auto xwrite = [&](const C *fp, const C *gp) {
+    // exchange: the deviations of the collided populations of the own cell
+    auto xwrite = [&](const C *pp, int row0) {
 #pragma unroll
-        for (int i = 0; i < Q; i++) {
-            sX[i][tid] = fp[i];
-            sX[Q + i][tid] = gp[i];
-        }
+        for (int i = 0; i < Q; i++) sX[row0 + i][tid] = S::xenc(pp[i]);
     };
-    // gather of the directions with c_z = r - 1 (D = 3): rows i0 + k of f and
-    // Q + i0 + k of g
-    auto xgather = [&](int r, int z) {
+    // gather of the directions with c_z = r - 1 (D = 3) of the set(s) in W
+    // (1: f from rows i0 + k, 2: g from rows GROW + i0 + k)
+    auto xgather = [&](auto W, int r, int z) {
+        constexpr int w = decltype(W)::value;
         const int i0 = D == 3 ? 9 * r : 0;
         const char *X = (const char *)&sX[0][0];
         const int q = D == 3 ? r : 1;  // accumulator of plane z + c_z
         auto xv = [&](int row, const unsigned *src, int k) -> C {
             const unsigned off = (src[k / 2] >> (16 * (k & 1))) & 0xffffu;
-            return *(const C *)(X + (size_t)row * XS * sizeof(C) + off);
+            return S::xdec(*(const XT *)(X + (size_t)row * XS * sizeof(XT) + off));
         };
         const C cz = D == 3 ? C(r - 1) : C(0);
-        {
-            C s0 = 0, sx = 0, sy = 0, sg = 0;
+        auto sums = [&](const unsigned *src, C &s0, C &sx, C &sy, C &sg) {
+            s0 = sx = sy = sg = 0;
 #pragma unroll
             for (int k = 0; k < 9; k++) {
-                const C v = xv(i0 + k, so, k);
-                s0 += v;
-                if (k % 3 == 0) sx -= v;
-                if (k % 3 == 2) sx += v;
-                if (k / 3 == 0) sy -= v;
-                if (k / 3 == 2) sy += v;
-                sg += xv(Q + i0 + k, so, k);
+                if (w & 1) {
+                    const C v = xv(i0 + k, src, k);
+                    s0 += v;
+                    if (k % 3 == 0) sx -= v;
+                    if (k % 3 == 2) sx += v;
+                    if (k / 3 == 0) sy -= v;
+                    if (k / 3 == 2) sy += v;
+                }
+                if (w & 2) sg += xv(GROW + i0 + k, src, k);
             }
-            acc[q][0] += s0;
-            acc[q][1] += sx;
-            acc[q][2] += sy;
-            acc[q][3] += cz * s0;
-            acc[q][4] += sg;
+        };
+        {
+            C s0, sx, sy, sg;
+            sums(so, s0, sx, sy, sg);
+            if (w & 1) {
+                acc[q][0] += s0;
+                acc[q][1] += sx;
+                acc[q][2] += sy;
+                acc[q][3] += cz * s0;
+            }
+            if (w & 2) acc[q][4] += sg;
         }
         if (ring) {
-            C s0 = 0, sx = 0, sy = 0, sg = 0;
-#pragma unroll
-            for (int k = 0; k < 9; k++) {
-                const C v = xv(i0 + k, sr, k);
-                s0 += v;
-                if (k % 3 == 0) sx -= v;
-                if (k % 3 == 2) sx += v;
-                if (k / 3 == 0) sy -= v;
-                if (k / 3 == 2) sy += v;
-                sg += xv(Q + i0 + k, sr, k);
-            }
+            C s0, sx, sy, sg;
+            sums(sr, s0, sx, sy, sg);
             C *ra = &sRacc[s3(z + (D == 3 ? r - 1 : 0))][0][0];
-            ra[0 * TL::NR + rid] += s0;
-            ra[1 * TL::NR + rid] += sx;
-            ra[2 * TL::NR + rid] += sy;
-            ra[3 * TL::NR + rid] += cz * s0;
-            ra[4 * TL::NR + rid] += sg;
+            if (w & 1) {
+                ra[0 * TL::NR + rid] += s0;
+                ra[1 * TL::NR + rid] += sx;
+                ra[2 * TL::NR + rid] += sy;
+                ra[3 * TL::NR + rid] += cz * s0;
+            }
+            if (w & 2) ra[4 * TL::NR + rid] += sg;
         }
     };
+    using WFG = std::integral_constant<int, 3>;
 
     // -- prologue: rho(z0-3 .. z0+4), L(z0-2 .. z0+2), fields of z0-1, z0 -----
     CenterF<C> Zc, Zm4;  // centre fields of plane z; plane z-1 (u_z, T, h, Lambda_z used)
@@ -876,19 +885,26 @@ __global__ void __launch_bounds__(TL::NT, 1) k_fused(FusedArgs<typename S::C, ty
 
         // -- exchange, then the next position's populations, then the gather
         //    by c_z --------------------------------------------------------------
-        xwrite(f, gq);
+        auto rounds = [&](auto W) {
+            if (D == 3) {
+                xgather(W, 0, z);
+                xgather(W, 1, z);
+                xgather(W, 2, z);
+            } else {
+                xgather(W, 0, 0);
+            }
+        };
+        xwrite(f, 0);
+        xwrite(gq, GROW);
         if (D == 3 && z + 1 < z1) load_pops(z + 1);
         __syncthreads();
+        rounds(WFG{});
         if (D == 3) {
-            xgather(0, z);
             flush(z - 1, z == z0 ? nz + 2 * seg : z - 1);  // plane z-1 is complete
-            xgather(1, z);
-            xgather(2, z);
             shift_acc();
             Zm4 = Zc;
             Zc = Zp;
         } else {
-            xgather(0, 0);
             // accumulator 1 holds plane 0
 #pragma unroll
             for (int k = 0; k < 5; k++) acc[0][k] = acc[1][k];
