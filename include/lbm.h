@@ -152,8 +152,9 @@ const char *lbm_kernel_name(const lbm_ctx *ctx, int kernel);
  * of every population per step; periodic z or D = 2, and one plane of
  * populations, one moment layer and the inbound slots each below 2^31 bytes)
  * followed by the small pass completing its moment side channel (kernel kinds
- * "k_fused", "k_fused_fixup"), 0 when it runs the four-kernel path (moments,
- * Laplacian, fields, collide). */
+ * "k_fused", "k_fused_fixup"; with the surrogate EOS the network runs in a
+ * pass ahead of them, kind "k_eos_surrogate", writing T of every cell), 0 when
+ * it runs the four-kernel path (moments, Laplacian, fields, collide). */
 int lbm_is_fused(const lbm_ctx *ctx);
 
 /* Algorithmic HBM bytes moved per cell update by lbm_step (2 Q populations
@@ -168,7 +169,7 @@ const char *lbm_strerror(int status);
 const char *lbm_last_error(void);
 
 /* ---- learned equation-of-state surrogate ------------------------------- */
-/* Network 2 -> 64 -> 64 -> 3 with tanh hidden layers.  Parameter vector
+/* Network 2 -> 64 -> 64 -> 3 with ReLU hidden layers.  Parameter vector
  * (4547 FP32 values, LBM_MLP_NPARAMS):
  *   W1[64][2], b1[64], W2[64][64], b2[64], W3[3][64], b3[3]
  * Normalisation vector (10 FP32 values, LBM_MLP_NNORM):

@@ -5,8 +5,8 @@ TEST INFRASTRUCTURE ONLY (part of the oracle; see ``oracle/__init__.py``).
 
 The surrogate maps (rho, e) to (T, P, c_s^2) of the van der Waals fluid; it
 stands in for the caloric inversion (eq. lbm_temp; an iterative solve for a
-general equation of state).  Network: 2 -> 64 -> 64 -> 3, tanh hidden
-activations, linear output.  Parameter vector layout (4547 values):
+general equation of state).  Network: 2 -> 64 -> 64 -> 3, ReLU hidden
+activations (max(z, 0)), linear output.  Parameter vector layout (4547 values):
   W1[64][2], b1[64], W2[64][64], b2[64], W3[3][64], b3[3]
 (row j of W holds the weights into output unit j).
 Inputs are min-max scaled to [-1, 1]; outputs are z-scored:
@@ -52,8 +52,8 @@ def normalize_inputs(x, lo, hi):
 def forward(params, xn):
     """xn: (B, 2) normalised inputs; returns yhat (B, 3) and the activations."""
     W1, b1, W2, b2, W3, b3 = unpack(params)
-    h1 = np.tanh(xn @ W1.T + b1)
-    h2 = np.tanh(h1 @ W2.T + b2)
+    h1 = np.maximum(xn @ W1.T + b1, 0.0)
+    h2 = np.maximum(h1 @ W2.T + b2, 0.0)
     y = h2 @ W3.T + b3
     return y, (xn, h1, h2)
 
@@ -68,10 +68,10 @@ def loss_grad(params, xn, tn):
     dy = 2.0 * r / (3.0 * B)                 # dL/dyhat
     dW3 = dy.T @ h2
     db3 = dy.sum(0)
-    dz2 = (dy @ W3) * (1.0 - h2 * h2)        # tanh' = 1 - tanh^2
+    dz2 = (dy @ W3) * (h2 > 0.0)             # ReLU' = 1 where the unit is active
     dW2 = dz2.T @ h1
     db2 = dz2.sum(0)
-    dz1 = (dz2 @ W2) * (1.0 - h1 * h1)
+    dz1 = (dz2 @ W2) * (h1 > 0.0)
     dW1 = dz1.T @ x
     db1 = dz1.sum(0)
     return L, pack(dW1, db1, dW2, db2, dW3, db3)

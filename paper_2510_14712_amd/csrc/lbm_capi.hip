@@ -195,8 +195,7 @@ static void make_ref(const lbm_params &p, int D, RefPops &ref) {
 // plane), except with the surrogate, whose 32 x 8 tile has 84 ring cells: 21
 // per wavefront, one 32-sample half of the network.
 template <class S, bool MLP>
-using TileOf = typename std::conditional<std::is_same<S, StoreF64>::value, Tile<16, 8>,
-                                         typename std::conditional<MLP, Tile<32, 8>, Tile<64, 4>>::type>::type;
+using TileOf = typename std::conditional<std::is_same<S, StoreF64>::value, Tile<16, 8>, Tile<64, 4>>::type;
 
 template <int D, class S> struct Impl {
     using C = typename S::C;
@@ -264,11 +263,7 @@ template <int D, class S> struct Impl {
         a.Mci = (const C *)c->Mc[c->cur];
         a.Mco = (C *)c->Mc[nxt];
         a.INo = (C *)c->IN[nxt];
-        a.mlpP = c->mlp_params;
-        a.mlpW2b = c->mlp_w2b;
-        a.mlpNorm = c->mlp_norm;
-        a.mlpTol = (float)c->p.mlp_tol;
-        a.mlpCount = c->mlp_counters;
+        a.Tin = (const C *)c->Tsur;
         const dim3 grid((unsigned)(c->ntx * c->nty * c->nseg));
         // full tiles and periodic x, y: the specialisation without wall and
         // partial-tile handling
@@ -300,7 +295,22 @@ template <int D, class S> struct Impl {
         c->cur = nxt;
         c->pulled = 1;
     }
+    // surrogate form: T of every cell by the network pass (kind 2 of
+    // step_timed), ahead of the fused step that reads it
+    static void fused_eos(lbm_ctx *c) {
+        if constexpr (std::is_same<C, float>::value) {
+            if (!mlp(c)) return;
+            // 64 x 4 columns per workgroup, marching through chunks of 32 planes
+            const int zchunk = D == 3 ? 32 : 1;
+            const dim3 grid((unsigned)((c->p.nx + 63) / 64), (unsigned)((c->p.ny + 3) / 4),
+                            (unsigned)((c->p.nz + zchunk - 1) / zchunk));
+            hipLaunchKernelGGL(k_eos_surrogate<D>, grid, dim3(256), 0, c->stream, c->grid, make_phys<float>(c->p),
+                               (const float *)c->Mc[c->cur], (float *)c->Tsur, c->mlp_params, c->mlp_w2b,
+                               c->mlp_norm, (float)c->p.mlp_tol, c->mlp_counters, zchunk);
+        }
+    }
     static void fused_launch(lbm_ctx *c) {
+        fused_eos(c);
         fused_main(c);
         fused_fixup(c);
     }
@@ -356,25 +366,30 @@ template <int D, class S> struct Impl {
         for (int k = 0; k < 5; k++)
             if (hipEventCreate(&ev[k]) != hipSuccess) return LBM_EDEVICE;
         if (c->fused) {
-            double acc[2] = {0, 0};
+            // kinds: 0 k_fused, 1 k_fused_fixup, 2 k_eos_surrogate
+            double acc[3] = {0, 0, 0};
+            const int kind_of[3] = {2, 0, 1};
             int rc = LBM_OK;
             for (int s = 0; s < n && rc == LBM_OK; s++) {
                 (void)hipEventRecord(ev[0], c->stream);
-                fused_main(c);
+                fused_eos(c);
                 (void)hipEventRecord(ev[1], c->stream);
-                fused_fixup(c);
+                fused_main(c);
                 (void)hipEventRecord(ev[2], c->stream);
+                fused_fixup(c);
+                (void)hipEventRecord(ev[3], c->stream);
                 rc = last_launch();
-                for (int k = 0; k < 2 && rc == LBM_OK; k++) {
+                for (int k = 0; k < 3 && rc == LBM_OK; k++) {
                     float ms = 0;
                     if (hipEventSynchronize(ev[k + 1]) != hipSuccess ||
                         hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess)
                         rc = LBM_EDEVICE;
-                    acc[k] += ms;
+                    acc[kind_of[k]] += ms;
                 }
             }
             for (int k = 0; k < 5; k++) (void)hipEventDestroy(ev[k]);
-            for (int k = 0; k < LBM_NUM_KERNELS; k++) host_ms[k] = (k < 2 && n > 0) ? acc[k] / n : 0.0;
+            for (int k = 0; k < LBM_NUM_KERNELS; k++) host_ms[k] = (k < 3 && n > 0) ? acc[k] / n : 0.0;
+            if (!mlp(c)) host_ms[2] = 0.0;
             return rc;
         }
         double acc[4] = {0, 0, 0, 0};
@@ -595,7 +610,8 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
     }
     if (c->fused) {
         ok = hipMalloc(&c->Mc[0], c->mc_bytes) == hipSuccess && hipMalloc(&c->Mc[1], c->mc_bytes) == hipSuccess &&
-             hipMalloc(&c->IN[0], c->in_bytes) == hipSuccess && hipMalloc(&c->IN[1], c->in_bytes) == hipSuccess;
+             hipMalloc(&c->IN[0], c->in_bytes) == hipSuccess && hipMalloc(&c->IN[1], c->in_bytes) == hipSuccess &&
+             (params->eos != LBM_EOS_MLP || hipMalloc(&c->Tsur, sizeof(float) * (size_t)N) == hipSuccess);
         if (!ok) {
             lbm_note(hipGetLastError());
             lbm_destroy(c);
@@ -615,7 +631,8 @@ void lbm_destroy(lbm_ctx *c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
     void *ptrs[] = {c->f[0], c->f[1], c->work, c->red_partials, c->red_out,
-                    c->mlp_counters, c->mlp_params, c->mlp_norm, c->mlp_w2b, c->Mc[0], c->Mc[1], c->IN[0], c->IN[1]};
+                    c->mlp_counters, c->mlp_params, c->mlp_norm, c->mlp_w2b, c->Mc[0], c->Mc[1], c->IN[0], c->IN[1],
+                    c->Tsur};
     for (void *p : ptrs)
         if (p) hipFree(p);
     delete c;
@@ -679,7 +696,9 @@ const char *lbm_last_error(void) { return g_last_error; }
 
 const char *lbm_kernel_name(const lbm_ctx *c, int k) {
     static const char *names[LBM_NUM_KERNELS] = {"k_moments", "k_lap", "k_fields", "k_collide"};
-    if (c && c->fused) return k == 0 ? "k_fused" : (k == 1 ? "k_fused_fixup" : "");
+    if (c && c->fused)
+        return k == 0 ? "k_fused"
+                      : (k == 1 ? "k_fused_fixup" : (k == 2 && c->p.eos == LBM_EOS_MLP ? "k_eos_surrogate" : ""));
     return k >= 0 && k < LBM_NUM_KERNELS ? names[k] : "";
 }
 

@@ -87,11 +87,7 @@ template <class C, class T> struct FusedArgs {
     const C *Mci;  // complete moments of the input state, [5][nlay][ny][nx]
     C *Mco, *INo;  // output: tile-own partial sums, inbound slots [tiles][nlay][5][NR]
     // surrogate equation of state (kernels built with MLP)
-    const float *mlpP;             // FP32 parameters
-    const uint16_t *mlpW2b;        // BF16 copy of the hidden weights
-    const float *mlpNorm;          // normalisation constants
-    float mlpTol;                  // residual threshold
-    unsigned long long *mlpCount;  // [0] fallbacks, [1] evaluations
+    const C *Tin;  // surrogate form: T of every cell from k_eos_surrogate (layout of one z plane after another)
 };
 
 // ring cell r of a w x h tile: bottom row, top row, left column, right column
@@ -324,6 +320,119 @@ template <class C> struct CenterF {
 // FAST: every tile is full and the x, y axes are periodic (no zero-gradient
 // wall in the tile plane); the per-lane wall and partial-tile cases then fold
 // away at compile time.
+// Surrogate equation of state, one pass per step ahead of the fused step.
+// The network stands in for the caloric inversion T(rho, e) (Section 3.2,
+// after eq. lbm_temp).  For every cell: rho, j, G from the complete moment
+// side channel; the Korteweg force F = kappa rho grad(lap rho) from the rho
+// stencil (central differences, ghosts of zero-gradient axes take the
+// clamped cell's values, as in the fused step); u, E and e (eqs. def_u,
+// def_E); the network's T_hat; the caloric residual
+// |e(rho, T_hat) - e| / (c_v T_hat) against the threshold, and one FP64
+// Newton step on e(rho, T) = e where it fails (exact for van der Waals).
+// Writes T of every cell; the fused step reads it in place of the explicit
+// inversion.  A workgroup takes a 64 x 4 block of (x, y) columns (one row per
+// wavefront) and marches through `zchunk` planes, keeping the Laplacian of
+// its own column for planes z-1, z, z+1 in registers.
+template <int D>
+__global__ void __launch_bounds__(256) k_eos_surrogate(Grid g, Phys<float> ph, const float *__restrict__ Mc,
+                                                       float *__restrict__ Tout, const float *__restrict__ P,
+                                                       const uint16_t *__restrict__ W2b,
+                                                       const float *__restrict__ norm, float tol,
+                                                       unsigned long long *count, int zchunk) {
+    constexpr int W2LD = 72;  // padded BF16 rows: conflict-free 16-byte A-operand reads
+    __shared__ float sNet[mlp::OFF_W2 + 2 * mlp::H + 2];
+    __shared__ __attribute__((aligned(16))) uint16_t sW2[mlp::H * W2LD];
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int r = tid; r < mlp::OFF_W2; r += 256) sNet[r] = P[r];
+    for (int r = tid; r < 2 * mlp::H; r += 256) sNet[mlp::OFF_W2 + r] = P[mlp::OFF_B2 + r];  // b2, w3 row of T
+    if (tid == 0) sNet[mlp::OFF_W2 + 2 * mlp::H] = P[mlp::OFF_B3];
+    for (int r = tid; r < mlp::H * mlp::H; r += 256) sW2[(r / mlp::H) * W2LD + r % mlp::H] = W2b[r];
+    __syncthreads();
+    const mlp::Net net{sNet + mlp::OFF_W1, sNet + mlp::OFF_B1, sW2, nullptr, sNet + mlp::OFF_W2,
+                       sNet + mlp::OFF_W2 + mlp::H, sNet + mlp::OFF_W2 + 2 * mlp::H, W2LD};
+
+    const int nx = g.nx, ny = g.ny, nz = D == 3 ? g.nz : 1;
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    // lattice coordinate of a stencil point: wrapped (periodic) or clamped
+    auto ax = [](int v, int n, int clamp) {
+        return clamp ? (v < 0 ? 0 : (v >= n ? n - 1 : v)) : (v < 0 ? v + n : (v >= n ? v - n : v));
+    };
+    const int x = blockIdx.x * 64 + lane, y = blockIdx.y * 4 + (tid >> 6);
+    const bool act = x < nx && y < ny;  // other lanes evaluate a clamped cell and write nothing
+    const int xc = min(x, nx - 1), yc = min(y, ny - 1);
+    // x and y coordinates of the column, of its neighbours and of theirs (a
+    // ghost point is the clamped cell: its Laplacian is that cell's)
+    const int xm = ax(xc - 1, nx, g.clampx), xp = ax(xc + 1, nx, g.clampx);
+    const int xmm = ax(xm - 1, nx, g.clampx), xmp = ax(xm + 1, nx, g.clampx);
+    const int xpm = ax(xp - 1, nx, g.clampx), xpp = ax(xp + 1, nx, g.clampx);
+    const int ym = ax(yc - 1, ny, g.clampy), yp = ax(yc + 1, ny, g.clampy);
+    const int ymm = ax(ym - 1, ny, g.clampy), ymp = ax(ym + 1, ny, g.clampy);
+    const int ypm = ax(yp - 1, ny, g.clampy), ypp = ax(yp + 1, ny, g.clampy);
+    const unsigned oc = xc + nx * yc;
+    // rho of layer z at cell offset o (side channel, layer-major)
+    auto rho = [&](int z, unsigned o) -> float { return Mc[(size_t)z * 5 * plane + o]; };
+    // Laplacian at the lattice point (xs, ys) of plane z (expression order as
+    // in the fused step); xsm .. ysp are its neighbours' coordinates
+    auto lap = [&](int z, int zm, int zp, int xs, int xsm, int xsp, int ys, int ysm, int ysp) -> float {
+        const unsigned o = xs + nx * ys;
+        const float r0 = rho(z, o);
+        float s = rho(z, xsp + nx * ys) + rho(z, xsm + nx * ys) - 2.0f * r0 + rho(z, xs + nx * ysp) +
+                  rho(z, xs + nx * ysm) - 2.0f * r0;
+        if (D == 3) s += rho(zp, o) + rho(zm, o) - 2.0f * r0;
+        return s;
+    };
+    auto zw = [&](int z) { return D == 3 ? ax(z, nz, 0) : 0; };
+    auto lap_col = [&](int z) { return lap(zw(z), zw(z - 1), zw(z + 1), xc, xm, xp, yc, ym, yp); };
+
+    const int z0 = D == 3 ? blockIdx.z * zchunk : 0;
+    const int z1 = D == 3 ? min(nz, z0 + zchunk) : 1;
+    unsigned long long n_fb = 0, n_eval = 0;
+    float Lm = D == 3 ? lap_col(z0 - 1) : 0.0f, L0 = lap_col(z0);
+    for (int z = z0; z < z1; z++) {
+        const float Lp = D == 3 ? lap_col(z + 1) : 0.0f;
+        const int zz = zw(z), zm = zw(z - 1), zp = zw(z + 1);
+        const float *M = Mc + (size_t)zz * 5 * plane + oc;
+        const float r = M[0], j0 = M[plane], j1 = M[2 * plane], j2 = M[3 * plane], G = M[4 * plane];
+        const float inv_rho = 1.0f / r;
+        float F[3];
+        F[0] = ph.kappa * r * 0.5f *
+               (lap(zz, zm, zp, xp, xpm, xpp, yc, ym, yp) - lap(zz, zm, zp, xm, xmm, xmp, yc, ym, yp));
+        F[1] = ph.kappa * r * 0.5f *
+               (lap(zz, zm, zp, xc, xm, xp, yp, ypm, ypp) - lap(zz, zm, zp, xc, xm, xp, ym, ymm, ymp));
+        F[2] = D == 3 ? ph.kappa * r * 0.5f * (Lp - Lm) : 0.0f;
+        const float jv[3] = {j0, j1, j2};
+        float uF = 0.0f, u2 = 0.0f;
+        for (int d = 0; d < 3; d++) {
+            const float u = d < D ? (jv[d] + 0.5f * F[d]) * inv_rho : 0.0f;
+            uF += u * F[d];
+            u2 += u * u;
+        }
+        const float E = (G + 0.5f * uF) * inv_rho;
+        const float e = E - 0.5f * u2;
+        float x0n, x1n, yh[1];
+        mlp::normalise(norm, r, e, x0n, x1n);
+        mlp::forward_wave<1, 2>(x0n, x1n, net, yh);
+        float Th = yh[0] * norm[5] + norm[4];
+        const float res = fabsf(ph.cv * Th - ph.a * r - e) / (ph.cv * fabsf(Th));
+        const bool fb = !(res <= tol);
+        if (fb) {
+            double Td = (double)Th;
+            Td = Td - ((double)ph.cv * Td - (double)ph.a * (double)r - (double)e) / (double)ph.cv;
+            Th = (float)Td;
+        }
+        if (act) Tout[(size_t)zz * plane + oc] = Th;
+        n_fb += __popcll(__ballot(fb && act));
+        n_eval += __popcll(__ballot(act));
+        Lm = L0;
+        L0 = Lp;
+    }
+    (void)L0;
+    if (lane == 0 && n_eval) {
+        atomicAdd(&count[0], n_fb);
+        atomicAdd(&count[1], n_eval);
+    }
+}
+
 // Waves per SIMD asked of the compiler: two for the 16-bit forms without the
 // surrogate (their LDS, with a 16-bit exchange, fits two workgroups per CU;
 // measured 1.4x faster than one), one otherwise (the registers then hold the
@@ -345,7 +454,6 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
     constexpr int NR2 = (TL::R2 + NT - 1) / NT;
     constexpr int NW = (NT + 63) / 64;  // wavefronts per workgroup
     // 32-sample halves of the surrogate needed for a wave's ring cells
-    constexpr int RING_HALVES = (TL::NR + NW - 1) / NW <= 32 ? 1 : 2;
     // ring fields on R1 (x, y neighbours of the collision): u_x, u_y, T, h,
     // Lambda_x, Lambda_y
     enum { RUX, RUY, RT, RH, RLX, RLY, NRF };
@@ -498,6 +606,12 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
             jo[k] = mom(r, 1 + k, own_off);
             jr[k] = mom(r, 1 + k, ring_off);
         }
+        if constexpr (MLP) {
+            // the surrogate form's temperatures of the own and the ring cell
+            const Rsrc rt = make_rsrc(a.Tin + (long long)zwrap(p) * plane, (unsigned)(plane * (long long)sizeof(C)));
+            buf_ld(rt, own_off * (unsigned)sizeof(C), 0u, jo[4]);
+            buf_ld(rt, ring_off * (unsigned)sizeof(C), 0u, jr[4]);
+        }
     };
     auto make_lap = [&](int p) {
         const C *rc = sRho[s4(p)];
@@ -515,29 +629,10 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         }
     };
 
-    unsigned long long n_fb = 0, n_eval = 0;  // surrogate statistics (lane 0 of each wave)
-    // surrogate: all parameters in LDS; the BF16 hidden weights in rows padded
-    // to 72 elements (144 B), so that the 16-byte A-operand reads of eight
-    // consecutive rows fall on disjoint banks
-    constexpr int W2LD = 72;
-    __shared__ float sNet[MLP ? mlp::OFF_W2 + 2 * mlp::H + 2 : 1];
-    __shared__ __attribute__((aligned(16))) uint16_t sW2[MLP ? mlp::H * W2LD : 1];
-    mlp::Net net{};
-    if constexpr (MLP) {
-        for (int r = tid; r < mlp::OFF_W2; r += NT) sNet[r] = a.mlpP[r];
-        // b2 and the temperature row of w3 are contiguous; b3[0] follows all
-        // output rows of w3
-        for (int r = tid; r < 2 * mlp::H; r += NT) sNet[mlp::OFF_W2 + r] = a.mlpP[mlp::OFF_B2 + r];
-        if (tid == 0) sNet[mlp::OFF_W2 + 2 * mlp::H] = a.mlpP[mlp::OFF_B3];
-        for (int r = tid; r < mlp::H * mlp::H; r += NT) sW2[(r / mlp::H) * W2LD + r % mlp::H] = a.mlpW2b[r];
-        net = mlp::Net{sNet + mlp::OFF_W1, sNet + mlp::OFF_B1, sW2, nullptr, sNet + mlp::OFF_W2,
-                       sNet + mlp::OFF_W2 + mlp::H, sNet + mlp::OFF_W2 + 2 * mlp::H, W2LD};
-    }
     // fields of logical plane p at one cell: R3 index c3, R2 index c2 of the
-    // evaluation point, j, G of the cell.  With MLP the call is collective
-    // over the wavefront.
-    auto eval_cell = [&](int p, int c3, int c2, const C *jg, bool act, bool ring_call, C u[3], C F[3], C &rho,
-                         C &Tt, C &ee, C &P, C &cs2, C &hh, C Lam[3]) {
+    // evaluation point, j, G (and T of the surrogate form) of the cell
+    auto eval_cell = [&](int p, int c3, int c2, const C *jg, C u[3], C F[3], C &rho, C &Tt, C &ee, C &P, C &cs2,
+                         C &hh, C Lam[3]) {
         const C *lc = sLap[s4(p)];
         const C *lm = sLap[s4(p - 1)];
         const C *lp = sLap[s4(p + 1)];
@@ -555,26 +650,7 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         const C E = (jg[3] + C(0.5) * uF) * inv_rho;
         const C e = E - C(0.5) * u2;
         if constexpr (MLP) {
-            // surrogate temperature, accepted when the caloric residual
-            // |e(rho, T_hat) - e| / (c_v T_hat) is within the threshold;
-            // otherwise one FP64 Newton step on e(rho, T) = e (exact for
-            // van der Waals).  P and c_s^2 from the EOS at the accepted T.
-            float x0n, x1n, yh[1];
-            mlp::normalise(a.mlpNorm, (float)rho, (float)e, x0n, x1n);
-            if (ring_call && RING_HALVES == 1) mlp::forward_wave<1, 1>(x0n, x1n, net, yh);
-            else mlp::forward_wave<1, 2>(x0n, x1n, net, yh);
-            float Th = yh[0] * a.mlpNorm[5] + a.mlpNorm[4];
-            const float res = fabsf((float)a.ph.cv * Th - (float)a.ph.a * (float)rho - (float)e) /
-                              ((float)a.ph.cv * fabsf(Th));
-            const bool fb = !(res <= a.mlpTol);
-            if (fb) {
-                double Td = (double)Th;
-                Td = Td - ((double)a.ph.cv * Td - (double)a.ph.a * (double)rho - (double)e) / (double)a.ph.cv;
-                Th = (float)Td;
-            }
-            Tt = (C)Th;
-            n_fb += __popcll(__ballot(fb && act));
-            n_eval += __popcll(__ballot(act));
+            Tt = jg[4];  // the surrogate's accepted (or fallback) temperature
         } else {
             Tt = (e + a.ph.a * rho) * a.ph.inv_cv;  // eq. lbm_temp
         }
@@ -590,7 +666,7 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         C *rf = &sRing[s2(p)][0][0];
         {
             C u[3], F[3], rho, Tt, ee, P, cs2, hh, Lam[3];
-            eval_cell(p, c3o, c2o, jo, own, false, u, F, rho, Tt, ee, P, cs2, hh, Lam);
+            eval_cell(p, c3o, c2o, jo, u, F, rho, Tt, ee, P, cs2, hh, Lam);
             if (own) {
                 rf[RUX * TL::R1 + c1o] = u[0];
                 rf[RUY * TL::R1 + c1o] = u[1];
@@ -613,7 +689,7 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         }
         if ((tid >> 6) < nring) {  // wavefronts holding ring cells (lane 0 holds ring cell `wave`)
             C u[3], F[3], rho, Tt, ee, P, cs2, hh, Lam[3];
-            eval_cell(p, c3r, c2r, jr, ring, true, u, F, rho, Tt, ee, P, cs2, hh, Lam);
+            eval_cell(p, c3r, c2r, jr, u, F, rho, Tt, ee, P, cs2, hh, Lam);
             if (ring) {
                 rf[RUX * TL::R1 + c1r] = u[0];
                 rf[RUY * TL::R1 + c1r] = u[1];
@@ -729,7 +805,8 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
 
     // -- prologue: rho(z0-3 .. z0+4), L(z0-2 .. z0+2), fields of z0-1, z0 -----
     CenterF<C> Zc, Zm4;  // centre fields of plane z; plane z-1 (u_z, T, h, Lambda_z used)
-    C jo[4], jr[4];
+    constexpr int NJ = MLP ? 5 : 4;  // j, G (and T of the surrogate form) per cell
+    C jo[NJ], jr[NJ];
     {
         C rv[NR3];
         if (D == 3) {
@@ -809,7 +886,7 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
     for (int z = z0; z < z1; z++) {
         // -- prefetch of rho(z+5) and j, G(z+2); phase A: L(z+3), fields of
         //    plane z+1 ------------------------------------------------------------
-        C rv[NR3], jon[4], jrn[4];
+        C rv[NR3], jon[NJ], jrn[NJ];
         CenterF<C> Zp;
         if (D == 3) {
             load_rho_regs(z + 5, rv);
@@ -860,7 +937,7 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         if (D == 3) {
             store_rho(z + 5, rv);
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
+            for (int k = 0; k < NJ; k++) {
                 jo[k] = jon[k];
                 jr[k] = jrn[k];
             }
@@ -915,12 +992,6 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         flush(z1 - 1, z1 - 1);
         shift_acc();
         flush(z1, nz + 2 * seg + 1);
-    }
-    if constexpr (MLP) {
-        if (lane == 0 && n_eval) {
-            atomicAdd(&a.mlpCount[0], n_fb);
-            atomicAdd(&a.mlpCount[1], n_eval);
-        }
     }
 }
 

@@ -1,5 +1,5 @@
 // Learned equation-of-state surrogate (rho, e) -> (T, P, c_s^2): a
-// 2 -> 64 -> 64 -> 3 tanh network standing in for the caloric inversion of
+// 2 -> 64 -> 64 -> 3 ReLU network standing in for the caloric inversion of
 // Section 3.2 (explicit for van der Waals, eq. lbm_temp; iterative for a
 // general equation of state).  Inference runs inside the per-cell fields pass
 // with a residual check and an exact FP64 Newton fallback; training uses the
@@ -80,7 +80,7 @@ __device__ __forceinline__ void forward_wave_lds(float x0, float x1, const float
     const int lane = threadIdx.x & 63;
     for (int j = 0; j < H; j++) {
         float z = fmaf(P[OFF_W1 + 2 * j], x0, fmaf(P[OFF_W1 + 2 * j + 1], x1, P[OFF_B1 + j]));
-        lds[lane * LD + j] = fast_tanh(z);
+        lds[lane * LD + j] = relu(z);
     }
     __syncthreads();
     float acc[64];
@@ -90,7 +90,7 @@ __device__ __forceinline__ void forward_wave_lds(float x0, float x1, const float
     for (int t = 0; t < 4; t++)
         for (int v = 0; v < 16; v++) {
             const int r = acc_row(t >> 1, v, lane), cidx = acc_col(t & 1, lane);
-            lds[r * LD + cidx] = fast_tanh(acc[t * 16 + v] + P[OFF_B2 + cidx]);
+            lds[r * LD + cidx] = relu(acc[t * 16 + v] + P[OFF_B2 + cidx]);
         }
     __syncthreads();
     for (int k = 0; k < 3; k++) {
@@ -202,14 +202,14 @@ __global__ void __launch_bounds__(64) k_train_partial(const float *__restrict__ 
     X[2 * lane] = x0;
     X[2 * lane + 1] = x1;
     for (int j = 0; j < H; j++)
-        H1[lane * LD + j] = fast_tanh(fmaf(P[OFF_W1 + 2 * j], x0, fmaf(P[OFF_W1 + 2 * j + 1], x1, P[OFF_B1 + j])));
+        H1[lane * LD + j] = relu(fmaf(P[OFF_W1 + 2 * j], x0, fmaf(P[OFF_W1 + 2 * j + 1], x1, P[OFF_B1 + j])));
     __syncthreads();
     float acc[64];
     wave_gemm64<MFMA>(H1, LD, 1, P + OFF_W2, 1, H, acc);   // Z2 = H1 W2^T
     for (int t = 0; t < 4; t++)
         for (int v = 0; v < 16; v++) {
             const int r = acc_row(t >> 1, v, lane), cc = acc_col(t & 1, lane);
-            H2[r * LD + cc] = fast_tanh(acc[t * 16 + v] + P[OFF_B2 + cc]);
+            H2[r * LD + cc] = relu(acc[t * 16 + v] + P[OFF_B2 + cc]);
         }
     __syncthreads();
     const float scale = 2.0f / (3.0f * (float)B);
@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(64) k_train_partial(const float *__restrict__ 
         float h2 = H2[bb * LD + lane];
         float d = DY[3 * bb] * P[OFF_W3 + lane] + DY[3 * bb + 1] * P[OFF_W3 + H + lane] +
                   DY[3 * bb + 2] * P[OFF_W3 + 2 * H + lane];
-        DZ[bb * LD + lane] = d * (1.0f - h2 * h2);
+        DZ[bb * LD + lane] = h2 > 0.0f ? d : 0.0f;  // ReLU'
     }
     __syncthreads();
     {   // db2[n] = sum_b dZ2[b][n]
@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(64) k_train_partial(const float *__restrict__ 
         for (int v = 0; v < 16; v++) {
             const int r = acc_row(t >> 1, v, lane), cc = acc_col(t & 1, lane);
             float h1 = H1[r * LD + cc];
-            H2[r * LD + cc] = acc[t * 16 + v] * (1.0f - h1 * h1);  // dZ1, reusing H2
+            H2[r * LD + cc] = h1 > 0.0f ? acc[t * 16 + v] : 0.0f;  // dZ1, reusing H2
         }
     __syncthreads();
     {   // dW1[j][i] = sum_b dZ1[b][j] X[b][i]; db1[j] = sum_b dZ1[b][j]

@@ -23,13 +23,8 @@ constexpr int OFF_W1 = 0, OFF_B1 = 128, OFF_W2 = 192, OFF_B2 = 4288, OFF_W3 = 43
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// tanh x = 1 - 2 / (1 + e^{2x}): one exp2, one reciprocal and an FMA; both
-// saturations come out exactly (e^{2x} = inf gives 1, e^{2x} = 0 gives -1);
-// absolute error about 2e-7
-__device__ __forceinline__ float fast_tanh(float x) {
-    const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // 2 log2(e)
-    return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
-}
+// hidden activation: ReLU, max(z, 0)
+__device__ __forceinline__ float relu(float z) { return fmaxf(z, 0.0f); }
 
 __device__ __forceinline__ __bf16 to_bf16(float v) { return __builtin_bit_cast(__bf16, bf16_hw(v)); }
 
@@ -81,7 +76,7 @@ __device__ __forceinline__ void forward_wave(float x0, float x1, const Net &p, f
 #pragma unroll
             for (int j = 0; j < 8; j++) {
                 const int k = 16 * ks + 8 * hh + j;
-                hv[j] = fast_tanh(fmaf(p.w1[2 * k], xs0, fmaf(p.w1[2 * k + 1], xs1, p.b1[k])));
+                hv[j] = relu(fmaf(p.w1[2 * k], xs0, fmaf(p.w1[2 * k + 1], xs1, p.b1[k])));
             }
             // two activations per convert
             uint4 bp;
@@ -116,7 +111,7 @@ __device__ __forceinline__ void forward_wave(float x0, float x1, const Net &p, f
 #pragma unroll
             for (int v = 0; v < 16; v++) {
                 const int o = 32 * mt + 8 * (v >> 2) + 4 * hh + (v & 3);
-                const float h2 = fast_tanh(acc[mt][v] + p.b2[o]);
+                const float h2 = relu(acc[mt][v] + p.b2[o]);
 #pragma unroll
                 for (int k = 0; k < NOUT; k++) ys[k] = fmaf(p.w3[k * H + o], h2, ys[k]);
             }

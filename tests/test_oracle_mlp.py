@@ -1,8 +1,9 @@
 """Pins of the FP64 surrogate reference and of the precision codec.
 
 * backpropagation against central finite differences of the loss;
-* the network reduces to its output bias when the hidden weights vanish,
-  and to the linear map W3 W2 W1 x in the small-weight limit;
+* the network reduces to its output bias when the hidden weights vanish, to
+  the affine map W3 (W2 (W1 x + b1) + b2) + b3 when every unit is active, and
+  to a constant when the first layer is inactive (ReLU);
 * Adam: the first step from zero moments moves each parameter by lr sign(g);
 * BF16 round-to-nearest-even on hand-built bit patterns (halfway cases tie
   to even) and against an FP64 nearest-value search; FP16 against known
@@ -38,15 +39,24 @@ def test_backprop_matches_finite_differences():
 
 def test_forward_special_cases():
     xn, _ = _batch()
+    # hidden weights zero: the output bias
     p = np.zeros(mlp.N_PARAMS)
     p[-3:] = [0.5, -1.0, 2.0]
     y, _ = mlp.forward(p, xn)
     np.testing.assert_array_equal(y, np.tile([0.5, -1.0, 2.0], (xn.shape[0], 1)))
-    q = inputs.mlp_params(3) * 1e-4
-    W1, b1, W2, b2, W3, b3 = mlp.unpack(q)
+    # every pre-activation positive: the affine map W3 (W2 (W1 x + b1) + b2) + b3
+    rng = np.random.default_rng(11)
+    W1 = rng.uniform(0.1, 1.0, (64, 2)); b1 = np.full(64, 3.0)
+    W2 = rng.uniform(0.0, 0.1, (64, 64)); b2 = rng.uniform(0.1, 1.0, 64)
+    W3 = rng.normal(size=(3, 64)); b3 = rng.normal(size=3)
+    q = mlp.pack(W1, b1, W2, b2, W3, b3)
+    y, (x, h1, h2) = mlp.forward(q, xn)
+    assert (xn @ W1.T + b1).min() > 0 and h1.min() > 0 and h2.min() > 0
+    np.testing.assert_allclose(y, (((xn @ W1.T + b1) @ W2.T + b2) @ W3.T + b3), rtol=1e-13, atol=1e-13)
+    # every first-layer pre-activation negative: the layers above see zeros
+    q = mlp.pack(W1, -b1, W2, b2, W3, b3)
     y, _ = mlp.forward(q, xn)
-    lin = xn @ (W3 @ W2 @ W1).T
-    np.testing.assert_allclose(y, lin, rtol=1e-6, atol=1e-18)
+    np.testing.assert_allclose(y, np.tile(np.maximum(b2, 0) @ W3.T + b3, (xn.shape[0], 1)), rtol=1e-13)
 
 
 def test_adam_first_step():
