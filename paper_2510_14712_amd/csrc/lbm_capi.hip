@@ -192,8 +192,8 @@ static void make_ref(const lbm_params &p, int D, RefPops &ref) {
 // ---------------------------------------------------------------------------
 // tile of the fused step.  FP64 uses a smaller tile to fit the LDS budget;
 // the other forms take a wide 64 x 4 tile (fewer x-shifted row fragments per
-// plane), except with the surrogate, whose 32 x 8 tile has 84 ring cells: 21
-// per wavefront, one 32-sample half of the network.
+// plane; measured faster than 32 x 8 for FP32 and, fix-up pass included,
+// for BF16).
 template <class S, bool MLP>
 using TileOf = typename std::conditional<std::is_same<S, StoreF64>::value, Tile<16, 8>, Tile<64, 4>>::type;
 

@@ -189,3 +189,30 @@ def test_deviation_storage_error_per_field(storage):
     errs = {k: rel_l2(mom[k], ref[k]) for k in ("rho", "u", "T")}
     _say(f"  per-field rel-L2 {errs}")
     assert errs["rho"] <= 1e-3
+
+
+def test_surrogate_bf16_form_density_error():
+    """The form the throughput comparison runs: BF16 deviation storage, the
+    surrogate EOS (threshold 1e-6) with FP64 fallback, FP32 collision, on the
+    Taylor-Green recipe for 200 steps: density within 1e-3 of the FP64
+    oracle; u and T errors reported beside it."""
+    lbm = _lbm()
+    params, norm, _ = _train()
+    c = ST["tgv_3d_256"]
+    shape = (40, 32, 24)
+    steps = 200
+    rho, u, T = inputs.taylor_green(shape, c["seed"], c["rho0"], c["T0"], c["U0"], c["noise"])
+    _say(f"case surrogate + bf16, {steps} steps")
+    with lbm.Lattice(3, shape, storage="bf16", eos="mlp", mlp_tol=1e-6, ref_rho=c["rho0"], ref_T=c["T0"],
+                     **KW) as lat:
+        lat.mlp_set(params, norm)
+        lat.init(rho, u, T).step(steps)
+        mom = {k: v.cpu().numpy() for k, v in lat.moments().items()}
+        frac = lat.mlp_stats()
+    p = oracle.Params(3, shape, **KW)
+    fr, gr = oracle.run(p, *oracle.init(p, rho, u, T), steps)
+    ref = oracle.fields(p, fr, gr)
+    errs = {k: rel_l2(mom[k], ref[k]) for k in ("rho", "u", "T")}
+    _say(f"  fallback fraction {frac:.4f}, per-field rel-L2 {errs}")
+    assert errs["rho"] <= 1e-3
+    assert errs["T"] <= 1e-2
