@@ -216,3 +216,26 @@ def test_surrogate_bf16_form_density_error():
     _say(f"  fallback fraction {frac:.4f}, per-field rel-L2 {errs}")
     assert errs["rho"] <= 1e-3
     assert errs["T"] <= 1e-2
+
+
+def test_surrogate_pass_2d_walls_partial_tiles():
+    """D2Q9 surrogate form with a zero-gradient x axis and partial tiles
+    (70 x 40): threshold 1e-6, so every cell the network cannot resolve takes
+    the exact fallback and the run matches the FP64 oracle to the FP32 bar."""
+    lbm = _lbm()
+    params, norm, _ = _train(epochs=10)
+    shape = (70, 40)
+    rho, u, T = inputs.random_state(2, shape, 13, ST["critical"]["rho"], 1.1 * ST["critical"]["T"])
+    _say("case surrogate D2Q9 70x40 bc x zero-gradient")
+    with lbm.Lattice(2, shape, bc=(1, 0, 0), storage="f32", eos="mlp", mlp_tol=1e-6, **KW) as lat:
+        lat.mlp_set(params, norm)
+        lat.init(rho, u, T).step(50)
+        mom = {k: v.cpu().numpy() for k, v in lat.moments().items()}
+        frac = lat.mlp_stats()
+    p = oracle.Params(2, shape, bc=(1, 0, 0), **KW)
+    ref = oracle.fields(p, *oracle.run(p, *oracle.init(p, rho, u, T), 50))
+    _say(f"  fallback fraction {frac:.4f}")
+    for k in ("rho", "u", "T"):
+        e = rel_l2(mom[k], ref[k])
+        _say(f"  {k} rel-L2 {e:.2e}")
+        assert e <= 1e-5
