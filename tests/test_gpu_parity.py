@@ -276,3 +276,66 @@ def test_full_size_tgv_256_sampled_cells():
                 gg = float(g1[i * N + d])
                 assert abs(fg - fo[i * 729 + mid]) <= 2e-6 * abs(fo).max()
                 assert abs(gg - go[i * 729 + mid]) <= 2e-6 * abs(go).max()
+
+
+@pytest.mark.parametrize("form", ["plain_fp32", "surrogate_bf16"])
+def test_full_size_tgv_512_sampled_cells(form):
+    """The benchmark's workload and launch shape: D3Q27 Taylor-Green at 512^3
+    in both of its forms, one step; 12 sampled cells checked against the
+    oracle's collision on local patches of the same (decoded) populations.
+    FP32: to FP32 rounding.  BF16 deviations + surrogate EOS: the stored
+    deviation is rounded to 8 significant bits (half an ulp, 2^-8 of the
+    deviation from the reference population), plus FP32 rounding."""
+    import torch
+    lbm = _lbm()
+    c = ST["tgv_3d_512"]
+    shape = tuple(c["shape"])
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    rho, u, T = inputs.taylor_green(shape, c["seed"], c["rho0"], c["T0"], c["U0"], c["noise"])
+    rng = np.random.default_rng(2)
+    cells = [tuple(int(v) for v in (rng.integers(5, n - 5) for n in shape)) for _ in range(12)]
+    kw = dict(KW, ref_rho=c["rho0"], ref_T=c["T0"])
+    if form == "plain_fp32":
+        kw.update(storage="f32")
+    else:
+        kw.update(storage="bf16", eos="mlp", mlp_tol=1e-6)
+    _say(f"case full-size TGV 512^3 {form}, 1 step")
+    with lbm.Lattice(3, shape, **kw) as lat:
+        if form == "surrogate_bf16":
+            box = ST["shock_drop_3d"]["mlp_box"]
+            p0 = inputs.mlp_params(4).astype(np.float32)
+            params, norm, _ = lbm.mlp_train([box["rho"][0], box["rho"][1], box["T"][0], box["T"][1]], 131072, 4, 20,
+                                            4096, 3e-3, p0, a=CONST["a"], b=CONST["b"], R=CONST["R"], cv=CONST["cv"])
+            lat.mlp_set(params, norm)
+        lat.init(rho, u, T)
+        f0, g0 = lat.get_populations()
+        patches = []
+        for (x, y, z) in cells:
+            R = 4
+            xs, ys, zs = (torch.arange(-R, R + 1, device="cuda") + v for v in (x, y, z))
+            Z, Y, X = torch.meshgrid(zs, ys, xs, indexing="ij")
+            idx = (X + nx * (Y + ny * Z)).reshape(-1)
+            patches.append((f0.view(27, N)[:, idx].cpu().numpy(), g0.view(27, N)[:, idx].cpu().numpy()))
+        del f0, g0
+        torch.cuda.empty_cache()
+        lat.step(1)
+        f1, g1 = lat.get_populations()
+        cvec = oracle.velocities(3)
+        # reference populations of the deviation storage: the rest equilibrium at (rho0, T0)
+        p1 = oracle.Params(3, (1, 1, 1), **KW)
+        fr, gr = oracle.init(p1, np.array([c["rho0"]]), np.zeros(3), np.array([c["T0"]]))
+        bf16 = form == "surrogate_bf16"
+        for (x, y, z), (fp, gp) in zip(cells, patches):
+            p = oracle.Params(3, (9, 9, 9), **KW)
+            fo, go, _ = oracle.collide(p, np.ascontiguousarray(fp).reshape(-1), np.ascontiguousarray(gp).reshape(-1))
+            mid = (729 - 1) // 2
+            for i in range(27):
+                d = (x + cvec[i, 0]) + nx * ((y + cvec[i, 1]) + ny * (z + cvec[i, 2]))
+                fe, ge = fo[i * 729 + mid], go[i * 729 + mid]
+                tf = 2e-6 * abs(fo).max() + (2.0 ** -8 * abs(fe - fr[i]) if bf16 else 0.0)
+                tg = 2e-6 * abs(go).max() + (2.0 ** -8 * abs(ge - gr[i]) if bf16 else 0.0)
+                assert abs(float(f1[i * N + d]) - fe) <= tf
+                assert abs(float(g1[i * N + d]) - ge) <= tg
+        del f1, g1
+        torch.cuda.empty_cache()
