@@ -1003,20 +1003,22 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
 template <int D, class TL, class C>
 __global__ void __launch_bounds__(BX) k_fused_fixup(Grid g, int ntx, int nty, int nseg, int nlay, int mode, C *Mc,
                                                     const C *IN) {
+    // 32-bit index arithmetic throughout (tiles x perimeter slots, planes and
+    // layers all fit); the z plane and its segment are uniform per block
     const int nz = g.nz;
-    int z, gxv, gyv;
-    int s = 0;
+    int z, s = 0;
+    int gxv, gyv;
     if (mode == 0) {
         z = blockIdx.y;
         if (D == 3) {
             s = seg_of(z, nz, nseg);
             if (z == seg_lo(s, nz, nseg) || z == seg_lo(s + 1, nz, nseg) - 1) return;
         }
-        const long long idx = (long long)blockIdx.x * BX + threadIdx.x;
-        const long long tile = idx / TL::PMAX;
-        int q = (int)(idx - tile * TL::PMAX);
-        if (tile >= (long long)ntx * nty) return;
-        const int tx = (int)(tile % ntx), ty = (int)(tile / ntx);
+        const unsigned idx = blockIdx.x * (unsigned)BX + threadIdx.x;
+        const unsigned tile = idx / (unsigned)TL::PMAX;  // compile-time divisor
+        const int q = (int)(idx - tile * (unsigned)TL::PMAX);
+        if (tile >= (unsigned)(ntx * nty)) return;
+        const int tx = (int)(tile % (unsigned)ntx), ty = (int)(tile / (unsigned)ntx);
         const int w = min(TL::TX, g.nx - tx * TL::TX), h = min(TL::TY, g.ny - ty * TL::TY);
         int lx, ly;
         if (w == 1 || h == 1) {
@@ -1037,32 +1039,32 @@ __global__ void __launch_bounds__(BX) k_fused_fixup(Grid g, int ntx, int nty, in
         const int zlo = seg_lo(s, nz, nseg), zhi = seg_lo(s + 1, nz, nseg) - 1;
         if ((blockIdx.y & 1) && zhi == zlo) return;
         z = (blockIdx.y & 1) ? zhi : zlo;
-        const long long c = (long long)blockIdx.x * BX + threadIdx.x;
-        if (c >= (long long)g.nx * g.ny) return;
-        gxv = (int)(c % g.nx);
-        gyv = (int)(c / g.nx);
+        const unsigned c = blockIdx.x * (unsigned)BX + threadIdx.x;
+        if (c >= (unsigned)g.nx * (unsigned)g.ny) return;
+        gxv = (int)(c % (unsigned)g.nx);
+        gyv = (int)(c / (unsigned)g.nx);
     }
     const int tx = gxv / TL::TX, ty = gyv / TL::TY;
     const int lx = gxv - tx * TL::TX, ly = gyv - ty * TL::TY;
     const int w = min(TL::TX, g.nx - tx * TL::TX), h = min(TL::TY, g.ny - ty * TL::TY);
-    const long long tile = (long long)ty * ntx + tx;
-    const long long plane = (long long)g.nx * g.ny;
-    const long long cell = gxv + (long long)g.nx * gyv;
-    const int zlo = seg_lo(s, nz, nseg), zhi = seg_lo(s + 1, nz, nseg) - 1;
-    const int lay_hi = nz + 2 * ((s + nseg - 1) % nseg) + 1;  // plane z0 of segment s, from segment s-1
-    const int lay_lo = nz + 2 * ((s + 1) % nseg);             // plane z1-1 of segment s, from segment s+1
-    for (int k = 0; k < 5; k++) {
-        const long long mi = ((long long)z * 5 + k) * plane + cell;
-        C v = Mc[mi] + inbound_sum<TL>(IN + ((tile * nlay + z) * 5 + k) * TL::NR, lx, ly, w, h);
-        if (D == 3 && mode == 1) {
-            if (z == zlo)
-                v += Mc[((long long)lay_hi * 5 + k) * plane + cell] +
-                     inbound_sum<TL>(IN + ((tile * nlay + lay_hi) * 5 + k) * TL::NR, lx, ly, w, h);
-            if (z == zhi)
-                v += Mc[((long long)lay_lo * 5 + k) * plane + cell] +
-                     inbound_sum<TL>(IN + ((tile * nlay + lay_lo) * 5 + k) * TL::NR, lx, ly, w, h);
+    const unsigned tile = (unsigned)(ty * ntx + tx);
+    const unsigned plane = (unsigned)g.nx * (unsigned)g.ny;
+    const unsigned cell = (unsigned)gxv + (unsigned)g.nx * (unsigned)gyv;
+    // layer-major side channel: one layer's moments lie within 5 nx ny values
+    auto mc = [&](int layer, int k) -> C & { return Mc[(size_t)(layer * 5 + k) * plane + cell]; };
+    auto in = [&](int layer, int k) { return IN + ((size_t)(tile * (unsigned)nlay + (unsigned)layer) * 5 + k) * TL::NR; };
+    if (D == 3 && mode == 1) {
+        const int zlo = seg_lo(s, nz, nseg), zhi = seg_lo(s + 1, nz, nseg) - 1;
+        const int lay_hi = nz + 2 * ((s + nseg - 1) % nseg) + 1;  // plane z0 of segment s, from segment s-1
+        const int lay_lo = nz + 2 * ((s + 1) % nseg);             // plane z1-1 of segment s, from segment s+1
+        for (int k = 0; k < 5; k++) {
+            C v = mc(z, k) + inbound_sum<TL>(in(z, k), lx, ly, w, h);
+            if (z == zlo) v += mc(lay_hi, k) + inbound_sum<TL>(in(lay_hi, k), lx, ly, w, h);
+            if (z == zhi) v += mc(lay_lo, k) + inbound_sum<TL>(in(lay_lo, k), lx, ly, w, h);
+            mc(z, k) = v;
         }
-        Mc[mi] = v;
+    } else {
+        for (int k = 0; k < 5; k++) mc(z, k) = mc(z, k) + inbound_sum<TL>(in(z, k), lx, ly, w, h);
     }
 }
 
