@@ -176,11 +176,14 @@ const char *lbm_last_error(void);
  *   lo_rho, hi_rho, lo_e, hi_e, mean_T, std_T, mean_P, std_P, mean_c2, std_c2
  * Inputs are scaled to [-1, 1]: xhat = 2 (x - lo)/(hi - lo) - 1; outputs are
  * yhat * std + mean.  The 64x64 layer runs on BF16 MFMA with FP32 accumulate
- * (LBM_MLP_BF16) or in FP32 on the vector ALU (LBM_MLP_F32). */
+ * (LBM_MLP_BF16) or in FP32 on the vector ALU (LBM_MLP_F32); LBM_MLP_BF16_L1
+ * (forward only) also runs the first layer on BF16 MFMA with the inputs and
+ * its weights rounded to BF16 -- the form the step's surrogate pass uses. */
 #define LBM_MLP_NPARAMS 4547
 #define LBM_MLP_NNORM 10
 #define LBM_MLP_BF16 0
 #define LBM_MLP_F32 1
+#define LBM_MLP_BF16_L1 2
 
 /* Train a surrogate on the GPU with the library's own forward, backward and
  * Adam kernels.  Samples (rho, T) are drawn uniformly from the box
@@ -206,7 +209,8 @@ int lbm_mlp_set(lbm_ctx *ctx, const float *host_params, const float *host_norm);
 int lbm_mlp_stats(lbm_ctx *ctx, double *host_fallback_fraction);
 
 /* Stand-alone surrogate forward pass: dev_x[2*B] raw (rho, e) pairs,
- * dev_y[3*B] de-normalised (T, P, c_s^2); dev_params[4547], dev_norm[10].
+ * dev_y[3*B] de-normalised (T, P, c_s^2); dev_params[4547], dev_norm[10];
+ * precision LBM_MLP_BF16, LBM_MLP_F32 or LBM_MLP_BF16_L1.
  * B >= 0 any size.  Asynchronous on `stream`. */
 int lbm_mlp_forward(const float *dev_params, const float *dev_norm, const float *dev_x,
                     float *dev_y, int B, int precision, void *stream);

@@ -326,7 +326,7 @@ template <class C> struct CenterF {
 // side channel; the Korteweg force F = kappa rho grad(lap rho) from the rho
 // stencil (central differences, ghosts of zero-gradient axes take the
 // clamped cell's values, as in the fused step); u, E and e (eqs. def_u,
-// def_E); the network's T_hat; the caloric residual
+// def_E); the network's T_hat (both hidden layers on MFMA); the caloric residual
 // |e(rho, T_hat) - e| / (c_v T_hat) against the threshold, and one FP64
 // Newton step on e(rho, T) = e where it fails (exact for van der Waals).
 // Writes T of every cell; the fused step reads it in place of the explicit
@@ -334,7 +334,7 @@ template <class C> struct CenterF {
 // wavefront) and marches through `zchunk` planes, keeping the Laplacian of
 // its own column for planes z-1, z, z+1 in registers.
 template <int D>
-__global__ void __launch_bounds__(256) k_eos_surrogate(Grid g, Phys<float> ph, const float *__restrict__ Mc,
+__global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph, const float *__restrict__ Mc,
                                                        float *__restrict__ Tout, const float *__restrict__ P,
                                                        const uint16_t *__restrict__ W2b,
                                                        const float *__restrict__ norm, float tol,
@@ -346,10 +346,16 @@ __global__ void __launch_bounds__(256) k_eos_surrogate(Grid g, Phys<float> ph, c
     for (int r = tid; r < mlp::OFF_W2; r += 256) sNet[r] = P[r];
     for (int r = tid; r < 2 * mlp::H; r += 256) sNet[mlp::OFF_W2 + r] = P[mlp::OFF_B2 + r];  // b2, w3 row of T
     if (tid == 0) sNet[mlp::OFF_W2 + 2 * mlp::H] = P[mlp::OFF_B3];
-    for (int r = tid; r < mlp::H * mlp::H; r += 256) sW2[(r / mlp::H) * W2LD + r % mlp::H] = W2b[r];
+    // W2 with its columns in the order of the layer-1 accumulator (see
+    // forward_wave_l1mfma)
+    for (int r = tid; r < mlp::H * mlp::H; r += 256) {
+        const int m = r / mlp::H, k = r % mlp::H;
+        sW2[m * W2LD + k] = W2b[m * mlp::H + mlp::w2_perm_col(k)];
+    }
     __syncthreads();
     const mlp::Net net{sNet + mlp::OFF_W1, sNet + mlp::OFF_B1, sW2, nullptr, sNet + mlp::OFF_W2,
                        sNet + mlp::OFF_W2 + mlp::H, sNet + mlp::OFF_W2 + 2 * mlp::H, W2LD};
+    const mlp::L1Ops l1 = mlp::l1_operands(sNet + mlp::OFF_W1, sNet + mlp::OFF_B1);
 
     const int nx = g.nx, ny = g.ny, nz = D == 3 ? g.nz : 1;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
@@ -411,7 +417,7 @@ __global__ void __launch_bounds__(256) k_eos_surrogate(Grid g, Phys<float> ph, c
         const float e = E - 0.5f * u2;
         float x0n, x1n, yh[1];
         mlp::normalise(norm, r, e, x0n, x1n);
-        mlp::forward_wave<1, 2>(x0n, x1n, net, yh);
+        mlp::forward_wave_l1mfma<1>(x0n, x1n, net, l1, yh);
         float Th = yh[0] * norm[5] + norm[4];
         const float res = fabsf(ph.cv * Th - ph.a * r - e) / (ph.cv * fabsf(Th));
         const bool fb = !(res <= tol);

@@ -116,6 +116,25 @@ __global__ void __launch_bounds__(64) k_forward(const float *P, const float *nor
         for (int k = 0; k < 3; k++) y[3 * b + k] = o[k] * norm[5 + 2 * k] + norm[4 + 2 * k];
 }
 
+// stand-alone forward in the surrogate pass's form (both hidden layers on
+// BF16 MFMA, W2 columns permuted): grid ceil(B / 64) blocks of one wave
+__global__ void __launch_bounds__(64) k_forward_l1mfma(const float *P, const float *norm, const float *x, float *y,
+                                                       int B) {
+    __shared__ __attribute__((aligned(16))) uint16_t sW2[H * 72];
+    for (int r = threadIdx.x; r < H * H; r += 64)
+        sW2[(r / H) * 72 + r % H] = bf16_hw(P[OFF_W2 + (r / H) * H + w2_perm_col(r % H)]);
+    __syncthreads();
+    const Net net{P + OFF_W1, P + OFF_B1, sW2, nullptr, P + OFF_B2, P + OFF_W3, P + OFF_B3, 72};
+    const L1Ops l1 = l1_operands(P + OFF_W1, P + OFF_B1);
+    const int b = blockIdx.x * 64 + threadIdx.x;
+    const int bc = b < B ? b : B - 1;
+    float x0, x1, o[3];
+    normalise(norm, x[2 * bc], x[2 * bc + 1], x0, x1);
+    forward_wave_l1mfma<3>(x0, x1, net, l1, o);
+    if (b < B)
+        for (int k = 0; k < 3; k++) y[3 * b + k] = o[k] * norm[5 + 2 * k] + norm[4 + 2 * k];
+}
+
 // ---------------------------------------------------------------------------
 // Per-cell fields with the surrogate: as the exact fields pass, but T, P and
 // c_s^2 come from the network; a cell whose caloric residual
@@ -417,11 +436,14 @@ extern "C" {
 
 int lbm_mlp_forward(const float *params, const float *norm, const float *x, float *y, int B, int precision,
                     void *stream) {
-    if (B < 0 || (precision != LBM_MLP_BF16 && precision != LBM_MLP_F32)) return LBM_EINVAL;
+    if (B < 0 || (precision != LBM_MLP_BF16 && precision != LBM_MLP_F32 && precision != LBM_MLP_BF16_L1))
+        return LBM_EINVAL;
     if (B == 0) return LBM_OK;
     if (!params || !norm || !x || !y) return LBM_EINVAL;
     dim3 gr((unsigned)((B + 63) / 64));
-    if (precision == LBM_MLP_BF16)
+    if (precision == LBM_MLP_BF16_L1)
+        hipLaunchKernelGGL(mlp::k_forward_l1mfma, gr, dim3(64), 0, (hipStream_t)stream, params, norm, x, y, B);
+    else if (precision == LBM_MLP_BF16)
         hipLaunchKernelGGL(mlp::k_forward<true>, gr, dim3(64), 0, (hipStream_t)stream, params, norm, x, y, B);
     else
         hipLaunchKernelGGL(mlp::k_forward<false>, gr, dim3(64), 0, (hipStream_t)stream, params, norm, x, y, B);

@@ -126,5 +126,105 @@ __device__ __forceinline__ void forward_wave(float x0, float x1, const Net &p, f
     }
 }
 
+// ---------------------------------------------------------------------------
+// Both hidden layers on MFMA (the surrogate pass's form).  Layer 1 is the
+// contraction of [w1_0, w1_1, b1] with [x0, x1, 1] padded to K = 16: one
+// v_mfma_f32_32x32x16_bf16 per 32 neurons and 32 samples, its operands
+// rounded to BF16.  Its accumulator gives lane l (h = l / 32) neurons
+// 32 mt + 8 q + 4 h + r (q, r < 4) of its sample; the layer-2 B operand of
+// k-step ks wants 8 consecutive k-indices 16 ks + 8 h + j.  Numbering the
+// layer-2 inputs by
+//   sigma(16 ks + 8 h + j) = 32 (ks / 2) + 8 (2 (ks % 2) + j / 4) + 4 h + j % 4
+// makes that operand the accumulator entries 8 (ks % 2) + j of tile ks / 2,
+// so no value crosses lanes; the A operand reads W2 with its columns in the
+// same order (w2_perm_col).  Layer 2 starts its accumulators at b2.
+__host__ __device__ constexpr int w2_perm_col(int k) {
+    return 32 * ((k >> 4) >> 1) + 8 * (2 * ((k >> 4) & 1) + ((k & 7) >> 2)) + 4 * ((k >> 3) & 1) + (k & 3);
+}
+// per-lane layer-1 A operands (neurons 32 mt + l % 32 in lanes 0..31: their
+// w1 row and bias; zero in lanes 32..63)
+struct L1Ops {
+    bf16x8 a[2];
+};
+__device__ __forceinline__ L1Ops l1_operands(const float *w1, const float *b1) {
+    const int lane = threadIdx.x & 63, c = lane & 31;
+    L1Ops o;
+#pragma unroll
+    for (int mt = 0; mt < 2; mt++) {
+        uint4 u = {0u, 0u, 0u, 0u};
+        if (lane < 32) {
+            const int m = 32 * mt + c;
+            u.x = bf16x2_hw(w1[2 * m], w1[2 * m + 1]);
+            u.y = bf16x2_hw(b1[m], 0.0f);
+        }
+        o.a[mt] = __builtin_bit_cast(bf16x8, u);
+    }
+    return o;
+}
+// normalised outputs 0..NOUT-1 of this lane's sample; uniform control flow.
+// p.w2b: BF16 W2 with permuted columns (row stride p.w2_ld elements).
+template <int NOUT>
+__device__ __forceinline__ void forward_wave_l1mfma(float x0, float x1, const Net &p, const L1Ops &l1, float y[NOUT]) {
+    const int lane = threadIdx.x & 63;
+    const int hh = lane >> 5, c = lane & 31;
+    const unsigned a_off = (unsigned)(c * p.w2_ld + 8 * hh) * 2u;
+#pragma unroll
+    for (int nt = 0; nt < 2; nt++) {
+        const float xs0 = __shfl(x0, 32 * nt + c, 64), xs1 = __shfl(x1, 32 * nt + c, 64);
+        uint4 bu = {0u, 0u, 0u, 0u};
+        if (hh == 0) {
+            bu.x = bf16x2_hw(xs0, xs1);
+            bu.y = bf16x2_hw(1.0f, 0.0f);
+        }
+        const bf16x8 b1 = __builtin_bit_cast(bf16x8, bu);
+        f32x16 z1[2];
+#pragma unroll
+        for (int mt = 0; mt < 2; mt++) {
+#pragma unroll
+            for (int v = 0; v < 16; v++) z1[mt][v] = 0.0f;
+            z1[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(l1.a[mt], b1, z1[mt], 0, 0, 0);
+        }
+        // layer 2, accumulators seeded with b2 of the output neurons
+        f32x16 acc[2];
+#pragma unroll
+        for (int mt = 0; mt < 2; mt++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) acc[mt][v] = p.b2[32 * mt + 8 * (v >> 2) + 4 * hh + (v & 3)];
+#pragma unroll
+        for (int ks = 0; ks < 4; ks++) {
+            const int t = ks >> 1, o = 8 * (ks & 1);
+            uint4 bp;
+            bp.x = bf16x2_hw(relu(z1[t][o + 0]), relu(z1[t][o + 1]));
+            bp.y = bf16x2_hw(relu(z1[t][o + 2]), relu(z1[t][o + 3]));
+            bp.z = bf16x2_hw(relu(z1[t][o + 4]), relu(z1[t][o + 5]));
+            bp.w = bf16x2_hw(relu(z1[t][o + 6]), relu(z1[t][o + 7]));
+            const bf16x8 b = __builtin_bit_cast(bf16x8, bp);
+#pragma unroll
+            for (int mt = 0; mt < 2; mt++) {
+                const uint4 raw =
+                    *(const uint4 *)((const char *)p.w2b + a_off + (unsigned)((32 * mt * p.w2_ld + 16 * ks) * 2));
+                acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, raw), b, acc[mt], 0, 0, 0);
+            }
+        }
+        float ys[NOUT];
+#pragma unroll
+        for (int k = 0; k < NOUT; k++) ys[k] = 0.0f;
+#pragma unroll
+        for (int mt = 0; mt < 2; mt++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) {
+                const int o = 32 * mt + 8 * (v >> 2) + 4 * hh + (v & 3);
+                const float h2 = relu(acc[mt][v]);
+#pragma unroll
+                for (int k = 0; k < NOUT; k++) ys[k] = fmaf(p.w3[k * H + o], h2, ys[k]);
+            }
+#pragma unroll
+        for (int k = 0; k < NOUT; k++) {
+            ys[k] += __shfl_xor(ys[k], 32, 64);
+            if (hh == nt) y[k] = ys[k] + p.b3[k];
+        }
+    }
+}
+
 }  // namespace mlp
 }  // namespace lbm

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm_hip.so")
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ENAN, LBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 STORAGE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 EOS = {"vdw": 0, "mlp": 1}
-MLP_BF16, MLP_F32 = 0, 1
+MLP_BF16, MLP_F32, MLP_BF16_L1 = 0, 1, 2
 MLP_NPARAMS, MLP_NNORM = 4547, 10
 # dead zone of the upwind switch: |u| at or below takes the central average
 UPWIND_EPS = 1e-6

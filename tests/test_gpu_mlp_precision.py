@@ -49,7 +49,7 @@ def _norm_vec():
     return np.array([r0, r1, CV * T0 - A * r1, CV * T1 - A * r0, 0.2, 0.03, 0.3, 0.2, 0.3, 0.3], np.float32)
 
 
-@pytest.mark.parametrize("precision,tol", [(1, 2e-5), (0, 3e-2)])
+@pytest.mark.parametrize("precision,tol", [(1, 2e-5), (0, 3e-2), (2, 5e-2)])
 def test_forward_matches_oracle(precision, tol):
     lbm = _lbm()
     params = inputs.mlp_params(21).astype(np.float32)
