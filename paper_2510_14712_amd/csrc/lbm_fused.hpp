@@ -300,16 +300,19 @@ __device__ __forceinline__ void pair_ld(Rsrc r, unsigned vo, unsigned so, uint16
     f = (uint16_t)v;
     g = (uint16_t)(v >> 16);
 }
+// Population stores carry the non-temporal cache policy (aux bit 1): the post-collision set is read back only
+// in the next step, after the whole lattice has streamed through L2, so keeping it there only evicts the
+// neighbour planes the loads reuse.
 __device__ __forceinline__ void pair_st(Rsrc r, unsigned vo, unsigned so, float f, float g) {
     __builtin_amdgcn_raw_buffer_store_b64((u32x2){__builtin_bit_cast(unsigned, f), __builtin_bit_cast(unsigned, g)}, r,
-                                          vo, so, 0);
+                                          vo, so, 2);
 }
 __device__ __forceinline__ void pair_st(Rsrc r, unsigned vo, unsigned so, double f, double g) {
     const u32x2 a = __builtin_bit_cast(u32x2, f), b = __builtin_bit_cast(u32x2, g);
-    __builtin_amdgcn_raw_buffer_store_b128((u32x4){a.x, a.y, b.x, b.y}, r, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b128((u32x4){a.x, a.y, b.x, b.y}, r, vo, so, 2);
 }
 __device__ __forceinline__ void pair_st(Rsrc r, unsigned vo, unsigned so, uint16_t f, uint16_t g) {
-    __builtin_amdgcn_raw_buffer_store_b32((unsigned)f | ((unsigned)g << 16), r, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b32((unsigned)f | ((unsigned)g << 16), r, vo, so, 2);
 }
 
 // fields of one plane's cell kept in registers between marching positions
