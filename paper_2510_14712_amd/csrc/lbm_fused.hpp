@@ -142,6 +142,22 @@ __device__ __forceinline__ C inbound_sum(const C *in, int lx, int ly, int w, int
     return v;
 }
 
+// inbound_sum for a tile of at least 2 x 2 cells, where a cell receives at
+// most one side, one bottom/top and one corner contribution.  The three slots
+// are loaded unconditionally (each index stays inside the slot array for any
+// lx < w, ly < h) and absent ones replaced by zero, so the loads of a thread
+// overlap instead of waiting one after another; the sum has inbound_sum's
+// order (adding a zero leaves a value unchanged).
+template <class TL, class C>
+__device__ __forceinline__ C inbound_sum_2x2(const C *in, int lx, int ly, int w, int h) {
+    const bool l = lx == 0, r = lx == w - 1, b = ly == 0, t = ly == h - 1;
+    const C sh = in[(l ? TL::FROM_L : TL::FROM_R) + ly];
+    const C sv = in[(b ? TL::FROM_B : TL::FROM_T) + lx];
+    const C sc = in[TL::FROM_BL + (r ? 1 : 0) + (t ? 2 : 0)];
+    const bool hs = l || r, vs = b || t;
+    return ((hs ? sh : (C)0) + (vs ? sv : (C)0)) + ((hs && vs) ? sc : (C)0);
+}
+
 // global coordinate along an axis for a tile-relative offset, and the
 // effective tile-relative offset at which a field is evaluated (ghost cells of
 // zero-gradient axes take the clamped cell's value)
@@ -1010,8 +1026,8 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
 // ends, grid (ceil(tiles * PMAX / BX), nz); mode 1 (D = 3): every cell of the
 // first and last plane of each segment, grid (ceil(nx ny / BX), 2 nseg).
 template <int D, class TL, class C>
-__global__ void __launch_bounds__(BX) k_fused_fixup(Grid g, int ntx, int nty, int nseg, int nlay, int mode, C *Mc,
-                                                    const C *IN) {
+__global__ void __launch_bounds__(BX) k_fused_fixup(Grid g, int ntx, int nty, int nseg, int nlay, int mode,
+                                                    C *__restrict__ Mc, const C *__restrict__ IN) {
     // 32-bit index arithmetic throughout (tiles x perimeter slots, planes and
     // layers all fit); the z plane and its segment are uniform per block
     const int nz = g.nz;
@@ -1073,7 +1089,20 @@ __global__ void __launch_bounds__(BX) k_fused_fixup(Grid g, int ntx, int nty, in
             mc(z, k) = v;
         }
     } else {
-        for (int k = 0; k < 5; k++) mc(z, k) = mc(z, k) + inbound_sum<TL>(in(z, k), lx, ly, w, h);
+        // all loads of the cell first, then the stores: one memory round trip
+        // per thread instead of one per moment
+        C v[5];
+#pragma unroll
+        for (int k = 0; k < 5; k++) v[k] = mc(z, k);
+        if (w >= 2 && h >= 2) {
+#pragma unroll
+            for (int k = 0; k < 5; k++) v[k] += inbound_sum_2x2<TL>(in(z, k), lx, ly, w, h);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 5; k++) v[k] += inbound_sum<TL>(in(z, k), lx, ly, w, h);
+        }
+#pragma unroll
+        for (int k = 0; k < 5; k++) mc(z, k) = v[k];
     }
 }
 
