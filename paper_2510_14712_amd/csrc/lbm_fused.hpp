@@ -394,20 +394,31 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     const int ymm = ax(ym - 1, ny, g.clampy), ymp = ax(ym + 1, ny, g.clampy);
     const int ypm = ax(yp - 1, ny, g.clampy), ypp = ax(yp + 1, ny, g.clampy);
     const unsigned oc = xc + nx * yc;
-    // rho of layer z at cell offset o (side channel, layer-major)
-    auto rho = [&](int z, unsigned o) -> float { return Mc[(size_t)z * 5 * plane + o]; };
-    // Laplacian at the lattice point (xs, ys) of plane z (expression order as
-    // in the fused step); xsm .. ysp are its neighbours' coordinates
-    auto lap = [&](int z, int zm, int zp, int xs, int xsm, int xsp, int ys, int ysm, int ysp) -> float {
+    // One buffer resource per layer of the side channel (its 5 moments, the
+    // moment picked by a uniform offset) and per plane of T; the lane offsets
+    // of the stencil points do not change along the march, so a load needs
+    // no address arithmetic.  The host keeps 5 nx ny values below 2^31 bytes.
+    const unsigned mc_bytes = 5u * plane * (unsigned)sizeof(float);
+    auto mcr = [&](int layer) { return make_rsrc(Mc + (size_t)layer * 5 * plane, mc_bytes); };
+    // rho of a layer at cell offset o
+    auto rho = [&](Rsrc r, unsigned o) -> float {
+        float v;
+        buf_ld(r, o * (unsigned)sizeof(float), 0u, v);
+        return v;
+    };
+    // Laplacian at the lattice point (xs, ys) of the plane of r (expression
+    // order as in the fused step); rm, rp: the planes below and above; xsm ..
+    // ysp are the point's neighbours' coordinates
+    auto lap = [&](Rsrc r, Rsrc rm, Rsrc rp, int xs, int xsm, int xsp, int ys, int ysm, int ysp) -> float {
         const unsigned o = xs + nx * ys;
-        const float r0 = rho(z, o);
-        float s = rho(z, xsp + nx * ys) + rho(z, xsm + nx * ys) - 2.0f * r0 + rho(z, xs + nx * ysp) +
-                  rho(z, xs + nx * ysm) - 2.0f * r0;
-        if (D == 3) s += rho(zp, o) + rho(zm, o) - 2.0f * r0;
+        const float r0 = rho(r, o);
+        float s = rho(r, xsp + nx * ys) + rho(r, xsm + nx * ys) - 2.0f * r0 + rho(r, xs + nx * ysp) +
+                  rho(r, xs + nx * ysm) - 2.0f * r0;
+        if (D == 3) s += rho(rp, o) + rho(rm, o) - 2.0f * r0;
         return s;
     };
     auto zw = [&](int z) { return D == 3 ? ax(z, nz, 0) : 0; };
-    auto lap_col = [&](int z) { return lap(zw(z), zw(z - 1), zw(z + 1), xc, xm, xp, yc, ym, yp); };
+    auto lap_col = [&](int z) { return lap(mcr(zw(z)), mcr(zw(z - 1)), mcr(zw(z + 1)), xc, xm, xp, yc, ym, yp); };
 
     const int z0 = D == 3 ? blockIdx.z * zchunk : 0;
     const int z1 = D == 3 ? min(nz, z0 + zchunk) : 1;
@@ -415,15 +426,21 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     float Lm = D == 3 ? lap_col(z0 - 1) : 0.0f, L0 = lap_col(z0);
     for (int z = z0; z < z1; z++) {
         const float Lp = D == 3 ? lap_col(z + 1) : 0.0f;
-        const int zz = zw(z), zm = zw(z - 1), zp = zw(z + 1);
-        const float *M = Mc + (size_t)zz * 5 * plane + oc;
-        const float r = M[0], j0 = M[plane], j1 = M[2 * plane], j2 = M[3 * plane], G = M[4 * plane];
+        const int zz = zw(z);
+        const Rsrc rz = mcr(zz), rzm = mcr(zw(z - 1)), rzp = mcr(zw(z + 1));
+        const unsigned vo = oc * (unsigned)sizeof(float), ko = plane * (unsigned)sizeof(float);
+        float r, j0, j1, j2, G;
+        buf_ld(rz, vo, 0u, r);
+        buf_ld(rz, vo, ko, j0);
+        buf_ld(rz, vo, 2u * ko, j1);
+        buf_ld(rz, vo, 3u * ko, j2);
+        buf_ld(rz, vo, 4u * ko, G);
         const float inv_rho = 1.0f / r;
         float F[3];
         F[0] = ph.kappa * r * 0.5f *
-               (lap(zz, zm, zp, xp, xpm, xpp, yc, ym, yp) - lap(zz, zm, zp, xm, xmm, xmp, yc, ym, yp));
+               (lap(rz, rzm, rzp, xp, xpm, xpp, yc, ym, yp) - lap(rz, rzm, rzp, xm, xmm, xmp, yc, ym, yp));
         F[1] = ph.kappa * r * 0.5f *
-               (lap(zz, zm, zp, xc, xm, xp, yp, ypm, ypp) - lap(zz, zm, zp, xc, xm, xp, ym, ymm, ymp));
+               (lap(rz, rzm, rzp, xc, xm, xp, yp, ypm, ypp) - lap(rz, rzm, rzp, xc, xm, xp, ym, ymm, ymp));
         F[2] = D == 3 ? ph.kappa * r * 0.5f * (Lp - Lm) : 0.0f;
         const float jv[3] = {j0, j1, j2};
         float uF = 0.0f, u2 = 0.0f;
@@ -445,7 +462,7 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
             Td = Td - ((double)ph.cv * Td - (double)ph.a * (double)r - (double)e) / (double)ph.cv;
             Th = (float)Td;
         }
-        if (act) Tout[(size_t)zz * plane + oc] = Th;
+        if (act) buf_st(make_rsrc(Tout + (size_t)zz * plane, ko), vo, 0u, Th);
         n_fb += __popcll(__ballot(fb && act));
         n_eval += __popcll(__ballot(act));
         Lm = L0;

@@ -23,8 +23,20 @@ constexpr int OFF_W1 = 0, OFF_B1 = 128, OFF_W2 = 192, OFF_B2 = 4288, OFF_W3 = 43
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// hidden activation: ReLU, max(z, 0)
-__device__ __forceinline__ float relu(float z) { return fmaxf(z, 0.0f); }
+// hidden activation: ReLU, max(z, 0), taken on the bit pattern: a set sign bit reads as a negative
+// integer and gives +0, a positive value passes unchanged.  One integer max
+// per value; the float max would first quiet its input (a second
+// instruction per value on matrix-core results).  Differs from fmaxf only
+// for a NaN input, which the residual check sends to the fallback anyway.
+__device__ __forceinline__ float relu(float z) { return __int_as_float(max(__float_as_int(z), 0)); }
+
+// ReLU of two BF16 values packed in a word, as a 16-bit integer max with 0
+// on each half.  Rounding to BF16 is monotone and keeps the sign, so this
+// equals rounding relu(a), relu(b): bit for bit, also for -0 and NaN.
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t p) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p), (s16x2){0, 0}));
+}
 
 __device__ __forceinline__ __bf16 to_bf16(float v) { return __builtin_bit_cast(__bf16, bf16_hw(v)); }
 
@@ -194,10 +206,10 @@ __device__ __forceinline__ void forward_wave_l1mfma(float x0, float x1, const Ne
         for (int ks = 0; ks < 4; ks++) {
             const int t = ks >> 1, o = 8 * (ks & 1);
             uint4 bp;
-            bp.x = bf16x2_hw(relu(z1[t][o + 0]), relu(z1[t][o + 1]));
-            bp.y = bf16x2_hw(relu(z1[t][o + 2]), relu(z1[t][o + 3]));
-            bp.z = bf16x2_hw(relu(z1[t][o + 4]), relu(z1[t][o + 5]));
-            bp.w = bf16x2_hw(relu(z1[t][o + 6]), relu(z1[t][o + 7]));
+            bp.x = relu_bf16x2(bf16x2_hw(z1[t][o + 0], z1[t][o + 1]));
+            bp.y = relu_bf16x2(bf16x2_hw(z1[t][o + 2], z1[t][o + 3]));
+            bp.z = relu_bf16x2(bf16x2_hw(z1[t][o + 4], z1[t][o + 5]));
+            bp.w = relu_bf16x2(bf16x2_hw(z1[t][o + 6], z1[t][o + 7]));
             const bf16x8 b = __builtin_bit_cast(bf16x8, bp);
 #pragma unroll
             for (int mt = 0; mt < 2; mt++) {
