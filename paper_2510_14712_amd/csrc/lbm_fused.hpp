@@ -423,6 +423,11 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     const int z0 = D == 3 ? blockIdx.z * zchunk : 0;
     const int z1 = D == 3 ? min(nz, z0 + zchunk) : 1;
     unsigned long long n_fb = 0, n_eval = 0;
+    // per-block constants: the input map x = 2 (v - lo) / (hi - lo) - 1 as
+    // (v - lo) s - 1, the residual bound tol c_v, and 1 / c_v for the Newton step
+    const float s0 = 2.0f / (norm[1] - norm[0]), s1 = 2.0f / (norm[3] - norm[2]);
+    const float tol_cv = tol * ph.cv;
+    const double inv_cv = 1.0 / (double)ph.cv;
     float Lm = D == 3 ? lap_col(z0 - 1) : 0.0f, L0 = lap_col(z0);
     for (int z = z0; z < z1; z++) {
         const float Lp = D == 3 ? lap_col(z + 1) : 0.0f;
@@ -435,7 +440,7 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
         buf_ld(rz, vo, 2u * ko, j1);
         buf_ld(rz, vo, 3u * ko, j2);
         buf_ld(rz, vo, 4u * ko, G);
-        const float inv_rho = 1.0f / r;
+        const float inv_rho = __builtin_amdgcn_rcpf(r);  // 1 ulp; feeds the network input and the residual
         float F[3];
         F[0] = ph.kappa * r * 0.5f *
                (lap(rz, rzm, rzp, xp, xpm, xpp, yc, ym, yp) - lap(rz, rzm, rzp, xm, xmm, xmp, yc, ym, yp));
@@ -451,15 +456,16 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
         }
         const float E = (G + 0.5f * uF) * inv_rho;
         const float e = E - 0.5f * u2;
-        float x0n, x1n, yh[1];
-        mlp::normalise(norm, r, e, x0n, x1n);
+        float yh[1];
+        const float x0n = (r - norm[0]) * s0 - 1.0f, x1n = (e - norm[2]) * s1 - 1.0f;
         mlp::forward_wave_l1mfma<1>(x0n, x1n, net, l1, yh);
         float Th = yh[0] * norm[5] + norm[4];
-        const float res = fabsf(ph.cv * Th - ph.a * r - e) / (ph.cv * fabsf(Th));
-        const bool fb = !(res <= tol);
+        // relative residual |c_v T - a rho - e| / (c_v |T|) <= tol, without the
+        // division; a NaN fails the test and takes the fallback
+        const bool fb = !(fabsf(ph.cv * Th - ph.a * r - e) <= tol_cv * fabsf(Th));
         if (fb) {
             double Td = (double)Th;
-            Td = Td - ((double)ph.cv * Td - (double)ph.a * (double)r - (double)e) / (double)ph.cv;
+            Td = Td - ((double)ph.cv * Td - (double)ph.a * (double)r - (double)e) * inv_cv;
             Th = (float)Td;
         }
         if (act) buf_st(make_rsrc(Tout + (size_t)zz * plane, ko), vo, 0u, Th);
