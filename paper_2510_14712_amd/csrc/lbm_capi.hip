@@ -284,12 +284,12 @@ template <int D, class S> struct Impl {
         const int nxt = 1 - c->cur;
         const long long per = (long long)c->ntx * c->nty * TL::PMAX;
         hipLaunchKernelGGL((k_fused_fixup<D, TL, C>), dim3((unsigned)((per + BX - 1) / BX), c->p.nz), dim3(BX), 0,
-                           c->stream, c->grid, c->ntx, c->nty, c->nseg, c->nlay, 0, (C *)c->Mc[nxt],
+                           c->stream, c->grid, c->ntx, c->nty, c->nseg, 0, (C *)c->Mc[nxt],
                            (const C *)c->IN[nxt]);
         if (D == 3) {
             const long long plane = (long long)c->p.nx * c->p.ny;
             hipLaunchKernelGGL((k_fused_fixup<D, TL, C>), dim3((unsigned)((plane + BX - 1) / BX), 2 * c->nseg),
-                               dim3(BX), 0, c->stream, c->grid, c->ntx, c->nty, c->nseg, c->nlay, 1,
+                               dim3(BX), 0, c->stream, c->grid, c->ntx, c->nty, c->nseg, 1,
                                (C *)c->Mc[nxt], (const C *)c->IN[nxt]);
         }
         c->cur = nxt;
@@ -602,10 +602,10 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
         auto tiles = [&]() { DISPATCH_VOID(c, tiles(c)); };
         tiles();
         // its buffer resources (one plane of populations, one side-channel
-        // layer, the inbound slots) must stay below 2^31 bytes; larger
-        // lattices take the multi-kernel path
+        // layer, one layer of inbound slots) must stay below 2^31 bytes;
+        // larger planes take the multi-kernel path
         const long long plane = (long long)params->nx * params->ny, lim = 1LL << 31;
-        if (2LL * c->Q * plane * sb >= lim || 5 * plane * cb >= lim || (long long)c->in_bytes >= lim)
+        if (2LL * c->Q * plane * sb >= lim || 5 * plane * cb >= lim || (long long)(c->in_bytes / c->nlay) >= lim)
             c->fused = false;
     }
     if (c->fused) {

@@ -84,8 +84,8 @@ template <class C, class T> struct FusedArgs {
     C rsf_hi, rsf_lo, rsg_hi, rsg_lo;
     const T *fi;  // input pair buffer (f_i, g_i side by side)
     T *fo;        // output pair buffer
-    const C *Mci;  // complete moments of the input state, [5][nlay][ny][nx]
-    C *Mco, *INo;  // output: tile-own partial sums, inbound slots [tiles][nlay][5][NR]
+    const C *Mci;  // complete moments of the input state, [nlay][5][ny][nx]
+    C *Mco, *INo;  // output: tile-own partial sums, inbound slots [nlay][tiles][5][NR]
     // surrogate equation of state (kernels built with MLP)
     const C *Tin;  // surrogate form: T of every cell from k_eos_surrogate (layout of one z plane after another)
 };
@@ -757,7 +757,10 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
     for (int q = 0; q < 3; q++)
 #pragma unroll
         for (int k = 0; k < 5; k++) acc[q][k] = C(0);
-    const Rsrc rIN = make_rsrc(a.INo, (unsigned)((long long)a.ntx * a.nty * a.nlay * 5 * TL::NR * sizeof(C)));
+    // inbound slots, layer-major: one resource per layer over every tile's
+    // slots (the whole array may exceed what one resource addresses)
+    const unsigned in_layer = (unsigned)(a.ntx * a.nty) * 5u * TL::NR;
+    auto in_rsrc = [&](int layer) { return make_rsrc(a.INo + (size_t)layer * in_layer, in_layer * (unsigned)sizeof(C)); };
     // write plane p (own: acc[0]) to `layer`, then clear its ring slot; the
     // reference sums enter once per cell, with the tile-own part of its plane
     auto flush = [&](int p, int layer) {
@@ -774,12 +777,11 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         }
         if (ring) {
             C *ra = &sRacc[s3(p)][0][0];
+            const Rsrc rIN = in_rsrc(layer);
 #pragma unroll
             for (int k = 0; k < 5; k++) {
                 if (ring_dst)
-                    buf_st(rIN,
-                           (((unsigned)rtile * (unsigned)a.nlay + (unsigned)layer) * 5u * TL::NR + (unsigned)rslot) *
-                               (unsigned)sizeof(C),
+                    buf_st(rIN, ((unsigned)rtile * 5u * TL::NR + (unsigned)rslot) * (unsigned)sizeof(C),
                            (unsigned)(k * TL::NR * sizeof(C)), ra[k * TL::NR + rid]);
                 ra[k * TL::NR + rid] = C(0);
             }
@@ -1049,7 +1051,7 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
 // ends, grid (ceil(tiles * PMAX / BX), nz); mode 1 (D = 3): every cell of the
 // first and last plane of each segment, grid (ceil(nx ny / BX), 2 nseg).
 template <int D, class TL, class C>
-__global__ void __launch_bounds__(BX) k_fused_fixup(Grid g, int ntx, int nty, int nseg, int nlay, int mode,
+__global__ void __launch_bounds__(BX) k_fused_fixup(Grid g, int ntx, int nty, int nseg, int mode,
                                                     C *__restrict__ Mc, const C *__restrict__ IN) {
     // 32-bit index arithmetic throughout (tiles x perimeter slots, planes and
     // layers all fit); the z plane and its segment are uniform per block
@@ -1100,7 +1102,11 @@ __global__ void __launch_bounds__(BX) k_fused_fixup(Grid g, int ntx, int nty, in
     const unsigned cell = (unsigned)gxv + (unsigned)g.nx * (unsigned)gyv;
     // layer-major side channel: one layer's moments lie within 5 nx ny values
     auto mc = [&](int layer, int k) -> C & { return Mc[(size_t)(layer * 5 + k) * plane + cell]; };
-    auto in = [&](int layer, int k) { return IN + ((size_t)(tile * (unsigned)nlay + (unsigned)layer) * 5 + k) * TL::NR; };
+    // inbound slots, layer-major [nlay][tiles][5][NR]
+    const unsigned ntile = (unsigned)(ntx * nty);
+    auto in = [&](int layer, int k) {
+        return IN + (size_t)layer * ntile * 5u * TL::NR + ((size_t)tile * 5u + (unsigned)k) * TL::NR;
+    };
     if (D == 3 && mode == 1) {
         const int zlo = seg_lo(s, nz, nseg), zhi = seg_lo(s + 1, nz, nseg) - 1;
         const int lay_hi = nz + 2 * ((s + nseg - 1) % nseg) + 1;  // plane z0 of segment s, from segment s-1

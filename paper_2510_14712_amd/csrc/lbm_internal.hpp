@@ -31,7 +31,7 @@ struct lbm_ctx {
     bool fused = false;
     void *Mc[2] = {nullptr, nullptr};  // [nlay][5][ny][nx]
     void *Tsur = nullptr;              // surrogate form: T of every cell for the fused step
-    void *IN[2] = {nullptr, nullptr};  // [tiles][nlay][5][slots]
+    void *IN[2] = {nullptr, nullptr};  // [nlay][tiles][5][slots]
     size_t mc_bytes = 0, in_bytes = 0;
     int ntx = 0, nty = 0, nseg = 1, nlay = 0, chunk = 0;
 };

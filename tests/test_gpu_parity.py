@@ -286,10 +286,23 @@ def test_full_size_tgv_512_sampled_cells(form):
     FP32: to FP32 rounding.  BF16 deviations + surrogate EOS: the stored
     deviation is rounded to 8 significant bits (half an ulp, 2^-8 of the
     deviation from the reference population), plus FP32 rounding."""
+    c = ST["tgv_3d_512"]
+    _sampled_cells_one_step(tuple(c["shape"]), c, form)
+
+
+def test_fused_path_beyond_2gib_of_inbound_slots():
+    """1024 x 1024 x 192 cells, BF16 deviations + surrogate EOS: the fused
+    step's inbound slots span 2.2 GB (4096 tiles x 194 layers x 5 x 140
+    floats), more than one 32-bit buffer resource addresses; they are
+    addressed one layer at a time, so the lattice stays on the fused path.
+    One step, 12 sampled cells as in the 512^3 case."""
+    c = ST["tgv_3d_512"]
+    _sampled_cells_one_step((1024, 1024, 192), c, "surrogate_bf16", expect_fused=True)
+
+
+def _sampled_cells_one_step(shape, c, form, expect_fused=None):
     import torch
     lbm = _lbm()
-    c = ST["tgv_3d_512"]
-    shape = tuple(c["shape"])
     nx, ny, nz = shape
     N = nx * ny * nz
     rho, u, T = inputs.taylor_green(shape, c["seed"], c["rho0"], c["T0"], c["U0"], c["noise"])
@@ -300,8 +313,10 @@ def test_full_size_tgv_512_sampled_cells(form):
         kw.update(storage="f32")
     else:
         kw.update(storage="bf16", eos="mlp", mlp_tol=1e-6)
-    _say(f"case full-size TGV 512^3 {form}, 1 step")
+    _say(f"case full-size TGV {shape} {form}, 1 step")
     with lbm.Lattice(3, shape, **kw) as lat:
+        if expect_fused is not None:
+            assert lat.fused == expect_fused
         if form == "surrogate_bf16":
             box = ST["shock_drop_3d"]["mlp_box"]
             p0 = inputs.mlp_params(4).astype(np.float32)
