@@ -453,10 +453,36 @@ template <int D, class S> struct Impl {
         } else if (c->p.zsegments > 0) {
             c->nseg = c->p.zsegments;
         } else {
-            // enough workgroups for two resident per compute unit on 256 CUs,
-            // segments of at least 16 planes
-            int s = (int)((1024 + ntiles - 1) / ntiles);
-            c->nseg = std::max(1, std::min(s, c->p.nz / 16));
+            // segments of at least 16 planes; the count minimises the
+            // workgroup rounds times the planes per segment (no half-empty
+            // last round), and among equal costs reaches 1024 workgroups for
+            // load balance.  Resident workgroups: compute units x the fused
+            // kernel's occupancy; if the device cannot be queried, the first
+            // count giving 1024 workgroups.
+            const int smax = std::max(1, c->p.nz / 16);
+            int dev = 0, ncu = 0, nb = 0;
+            const bool known =
+                hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused<D, S, TL, M, false>, TL::NT, 0) ==
+                    hipSuccess &&
+                ncu > 0 && nb > 0;
+            if (!known) {
+                (void)hipGetLastError();
+                c->nseg = std::max(1, std::min((int)((1024 + ntiles - 1) / ntiles), smax));
+            } else {
+                const long long res = (long long)ncu * nb;
+                long long best_cost = -1;
+                int best = 1;
+                for (int s = 1; s <= smax; s++) {
+                    const long long cost = ((ntiles * s + res - 1) / res) * ((c->p.nz + s - 1) / s);
+                    if (best_cost < 0 || cost < best_cost || (cost == best_cost && ntiles * best < 1024)) {
+                        best_cost = cost;
+                        best = s;
+                    }
+                }
+                c->nseg = best;
+            }
         }
         c->nlay = D == 3 ? c->p.nz + 2 * c->nseg : 1;
         const long long total = ntiles * c->nseg;
