@@ -34,8 +34,9 @@
 //            arrived populations of plane z+1 (from planes z..z+2)  | barrier
 //   gather   moment sums of planes z-1, z, z+1 for the tile and its ring;
 //            plane z-1 is complete and is written out.
-// One workgroup per compute unit: the registers hold the prefetched plane and
-// the LDS the whole exchange, with two barriers per plane.
+// One workgroup per compute unit for FP32 and FP64, two for the 16-bit forms
+// (their exchange holds 16-bit codes): the registers hold the prefetched
+// plane and the LDS the whole exchange, with two barriers per plane.
 // Ghost cells of zero-gradient axes take the field of the clamped cell.
 #pragma once
 
