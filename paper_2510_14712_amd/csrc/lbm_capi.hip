@@ -457,14 +457,16 @@ template <int D, class S> struct Impl {
             // workgroup rounds times the planes per segment (no half-empty
             // last round), and among equal costs reaches 1024 workgroups for
             // load balance.  Resident workgroups: compute units x the fused
-            // kernel's occupancy; if the device cannot be queried, the first
-            // count giving 1024 workgroups.
+            // kernel's occupancy (the instance the step launches); if the
+            // device cannot be queried, the first count giving 1024
+            // workgroups.
             const int smax = std::max(1, c->p.nz / 16);
             int dev = 0, ncu = 0, nb = 0;
             const bool known =
                 hipGetDevice(&dev) == hipSuccess &&
                 hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused<D, S, TL, M, false>, TL::NT, 0) ==
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &nb, k_fused<D, S, TL, M && std::is_same<C, float>::value, false>, TL::NT, 0) ==
                     hipSuccess &&
                 ncu > 0 && nb > 0;
             if (!known) {
