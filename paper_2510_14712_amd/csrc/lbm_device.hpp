@@ -44,6 +44,25 @@ template <class C> __device__ __forceinline__ C vdw_cs2(const Phys<C> &p, C rho,
     return p.R * T * (C(1) + p.R * p.inv_cv) / (omb * omb) - C(2) * p.a * rho;
 }
 
+// a / b in the form's arithmetic: exact in FP64; in FP32 a times the hardware
+// reciprocal (1 ulp), a tenth of the instructions of the correctly rounded
+// division, well inside the FP32 form's error against the FP64 method
+template <class C> __device__ __forceinline__ C fdiv(C a, C b) { return a / b; }
+template <> __device__ __forceinline__ float fdiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+// pressure and adiabatic sound speed squared together (eqs. Pvdw,
+// vdW_speed_of_sound); FP32 shares one reciprocal of 1 - b rho, FP64 takes the
+// two closed forms as written
+template <class C> __device__ __forceinline__ void vdw_p_cs2(const Phys<C> &p, C rho, C T, C &P, C &cs2) {
+    P = vdw_pressure(p, rho, T);
+    cs2 = vdw_cs2(p, rho, T);
+}
+template <> __device__ __forceinline__ void vdw_p_cs2<float>(const Phys<float> &p, float rho, float T, float &P,
+                                                             float &cs2) {
+    const float r = __builtin_amdgcn_rcpf(1.0f - p.b * rho);
+    P = rho * p.R * T * r - p.a * rho * rho;
+    cs2 = p.R * T * (1.0f + p.R * p.inv_cv) * (r * r) - 2.0f * p.a * rho;
+}
+
 // ---------------------------------------------------------------------------
 // Boundary index rules for an offset of at most one cell
 // ---------------------------------------------------------------------------

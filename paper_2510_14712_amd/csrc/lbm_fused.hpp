@@ -199,7 +199,7 @@ template <int D, class C>
 __device__ __forceinline__ void collide_cell(const Phys<C> &ph, const CollideIn<C> &in, C *f, C *g) {
     constexpr int Q = Lattice<D>::Q;
     const C rho = in.rho, P = in.P;
-    const C inv_rho = C(1) / rho;
+    const C inv_rho = fdiv(C(1), rho);
     const C theta = P * inv_rho;
     C qc[3], Phi[3], FF = 0;
     for (int d = 0; d < D; d++) {
@@ -211,8 +211,8 @@ __device__ __forceinline__ void collide_cell(const Phys<C> &ph, const CollideIn<
         else dL = C(0.5) * (in.Lp[d] - in.Lm[d]);
         Phi[d] = -dL * inv_rho;
     }
-    const C beta = P / (P + C(2) * ph.mu);
-    const C alpha = C(D + 2) / C(D) - rho * in.cs2 / P - ph.eta_over_mu;
+    const C beta = fdiv(P, P + C(2) * ph.mu);
+    const C alpha = C(D + 2) / C(D) - fdiv(rho * in.cs2, P) - ph.eta_over_mu;
     const C thetas = theta + alpha * theta * in.du;
     // e(rho, T*) with T* = T - |F|^2 / (2 rho^2 c_v) (eq. sh_T_1): for van der
     // Waals e is linear in T, so e(rho, T*) = e - |F|^2 / (2 rho^2), taken
@@ -686,7 +686,7 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         const C *lm = sLap[s4(p - 1)];
         const C *lp = sLap[s4(p + 1)];
         rho = sRho[s4(p)][c3];
-        const C inv_rho = C(1) / rho;
+        const C inv_rho = fdiv(C(1), rho);
         C uF = 0, u2 = 0;
         F[0] = a.ph.kappa * rho * C(0.5) * (lc[c2 + 1] - lc[c2 - 1]);
         F[1] = a.ph.kappa * rho * C(0.5) * (lc[c2 + TL::W2] - lc[c2 - TL::W2]);
@@ -703,8 +703,7 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         } else {
             Tt = (e + a.ph.a * rho) * a.ph.inv_cv;  // eq. lbm_temp
         }
-        P = vdw_pressure(a.ph, rho, Tt);
-        cs2 = vdw_cs2(a.ph, rho, Tt);
+        vdw_p_cs2(a.ph, rho, Tt, P, cs2);
         const C theta = P * inv_rho;
         for (int d = 0; d < 3; d++) Lam[d] = rho * u[d] * (u[d] * u[d] + C(3) * (theta - C(1.0 / 3.0)));
         hh = e + theta;
