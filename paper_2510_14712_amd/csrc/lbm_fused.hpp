@@ -231,6 +231,16 @@ __device__ __forceinline__ void collide_cell(const Phys<C> &ph, const CollideIn<
         pf[d] = psi3(us, thetas + us * us + Phi[d]);
     }
     const C w_keep = C(1) - C(2) * beta, w_eq = C(3) * beta - C(1), w_st = C(1) - beta;
+    // The attractors enter only as w_eq (f^eq, g^eq) + w_st (f*, g*), and
+    // they are products over the axes, so with r_x = 2 eps p_x + q_x
+    //   w_eq f^eq_i = (w_eq rho) p_x p_y p_z
+    //   w_eq g^eq_i = (w_eq rho / 2) [(r_x p_y + p_x q_y) p_z + p_x p_y q_z]
+    // and likewise f*, g* with (s, t, eps*) and the f* factors pf: the x-y
+    // products are formed once per (x, y) pair, the weights ride on the z
+    // factors, and a direction costs a few multiply-adds.
+    const C Af = w_eq * rho, Ag = C(0.5) * Af, Sf = w_st * rho, Sg = C(0.5) * Sf;
+    C hq[3];
+    for (int d = 0; d < 3; d++) hq[d] = d < D ? C(0.5) * w_st * qc[d] : C(0);  // w_st x the q^c term
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         const int ix = cx_of(i), iy = cy_of(i), iz = D == 3 ? cz_of(i) : 0;
@@ -238,31 +248,23 @@ __device__ __forceinline__ void collide_cell(const Phys<C> &ph, const CollideIn<
         const C qx = pick(eq[0].q, ix), qy = pick(eq[1].q, iy);
         const C sx = pick(st[0].p, ix), sy = pick(st[1].p, iy);
         const C tx = pick(st[0].q, ix), ty = pick(st[1].q, iy);
-        const C fsx = pick(pf[0], ix), fsy = pick(pf[1], iy);
-        C feq, geqs, fst, gsts, sp;
+        const C rx = C(2) * eps_eq * px + qx, rsx = C(2) * eps_st * sx + tx;
+        const C pxy = px * py, sxy = sx * sy, fxy = pick(pf[0], ix) * pick(pf[1], iy);
+        const C cxy = rx * py + px * qy, dxy = rsx * sy + sx * ty;
+        C fa, ga;  // w_eq f^eq + w_st f*,  w_eq g^eq + w_st g*
         if (D == 2) {
-            feq = rho * px * py;
-            geqs = qx * py + px * qy;
-            fst = rho * fsx * fsy;
-            gsts = tx * sy + sx * ty;
-            sp = sx * sy;
+            fa = Af * pxy + Sf * fxy;
+            ga = Ag * cxy + Sg * dxy;
         } else {
             const C pz = pick(eq[2].p, iz), qz = pick(eq[2].q, iz);
             const C sz = pick(st[2].p, iz), tz = pick(st[2].q, iz);
-            feq = rho * px * py * pz;
-            geqs = (qx * py + px * qy) * pz + px * py * qz;
-            fst = rho * fsx * fsy * pick(pf[2], iz);
-            gsts = (tx * sy + sx * ty) * sz + sx * sy * tz;
-            sp = sx * sy * sz;
+            fa = pxy * (Af * pz) + fxy * (Sf * pick(pf[2], iz));
+            ga = cxy * (Ag * pz) + pxy * (Ag * qz) + dxy * (Sg * sz) + sxy * (Sg * tz);
         }
-        const C geq = feq * eps_eq + C(0.5) * rho * geqs;
-        C gst = rho * sp * eps_st + C(0.5) * rho * gsts;
-        if (csq_of<D>(i) == 1) {
-            const C cq = ix ? (ix > 0 ? qc[0] : -qc[0]) : (iy ? (iy > 0 ? qc[1] : -qc[1]) : (iz > 0 ? qc[2] : -qc[2]));
-            gst += C(0.5) * cq;
-        }
-        f[i] = w_keep * f[i] + w_eq * feq + w_st * fst;
-        g[i] = w_keep * g[i] + w_eq * geq + w_st * gst;
+        if (csq_of<D>(i) == 1)
+            ga += ix ? (ix > 0 ? hq[0] : -hq[0]) : (iy ? (iy > 0 ? hq[1] : -hq[1]) : (iz > 0 ? hq[2] : -hq[2]));
+        f[i] = w_keep * f[i] + fa;
+        g[i] = w_keep * g[i] + ga;
     }
 }
 
