@@ -813,20 +813,25 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
             const unsigned off = (src[k / 2] >> (16 * (k & 1))) & 0xffffu;
             return S::xdec(*(const XT *)(X + (size_t)row * XS * sizeof(XT) + off));
         };
-        const C cz = D == 3 ? C(r - 1) : C(0);
+        // moment sums of the 3 x 3 in-plane directions k = (c_x + 1) + 3 (c_y + 1):
+        // row sums first, then rho, j_y from the rows and j_x from the two
+        // outer columns (14 additions instead of 21); no sum starts from zero
         auto sums = [&](const unsigned *src, C &s0, C &sx, C &sy, C &sg) {
-            s0 = sx = sy = sg = 0;
+            s0 = sx = sy = sg = C(0);
+            if (w & 1) {
+                C v[9];
 #pragma unroll
-            for (int k = 0; k < 9; k++) {
-                if (w & 1) {
-                    const C v = xv(i0 + k, src, k);
-                    s0 += v;
-                    if (k % 3 == 0) sx -= v;
-                    if (k % 3 == 2) sx += v;
-                    if (k / 3 == 0) sy -= v;
-                    if (k / 3 == 2) sy += v;
-                }
-                if (w & 2) sg += xv(GROW + i0 + k, src, k);
+                for (int k = 0; k < 9; k++) v[k] = xv(i0 + k, src, k);
+                const C r0 = v[0] + v[1] + v[2], r1 = v[3] + v[4] + v[5], r2 = v[6] + v[7] + v[8];
+                s0 = r0 + r1 + r2;
+                sy = r2 - r0;
+                sx = (v[2] + v[5] + v[8]) - (v[0] + v[3] + v[6]);
+            }
+            if (w & 2) {
+                C t = xv(GROW + i0, src, 0);
+#pragma unroll
+                for (int k = 1; k < 9; k++) t += xv(GROW + i0 + k, src, k);
+                sg = t;
             }
         };
         {
@@ -836,7 +841,7 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
                 acc[q][0] += s0;
                 acc[q][1] += sx;
                 acc[q][2] += sy;
-                acc[q][3] += cz * s0;
+                if (D == 3 && r != 1) acc[q][3] += r == 2 ? s0 : -s0;  // j_z: c_z s0, zero for c_z = 0
             }
             if (w & 2) acc[q][4] += sg;
         }
@@ -848,7 +853,7 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
                 ra[0 * TL::NR + rid] += s0;
                 ra[1 * TL::NR + rid] += sx;
                 ra[2 * TL::NR + rid] += sy;
-                ra[3 * TL::NR + rid] += cz * s0;
+                if (D == 3 && r != 1) ra[3 * TL::NR + rid] += r == 2 ? s0 : -s0;
             }
             if (w & 2) ra[4 * TL::NR + rid] += sg;
         }
@@ -1176,8 +1181,8 @@ __global__ void __launch_bounds__(BX) k_fused_moments(Grid g, RefPops ref, typen
         const int cz = D == 3 ? 1 - r : 0;  // the march meets sources at z-1 first
         int cls = 0;
         if (D == 3) cls = z - cz < z0 ? 1 : (z - cz >= z1 ? 2 : 0);
-        C s0[9], sx[9], sy[9], sg[9];
-        for (int q = 0; q < 9; q++) s0[q] = sx[q] = sy[q] = sg[q] = C(0);
+        C v[9], vg[9];
+        int src[9];
         for (int k = 0; k < 9; k++) {
             const int cx = k % 3 - 1, cy = k / 3 - 1;
             const int i = k + (D == 3 ? 9 * (cz + 1) : 0);
@@ -1185,26 +1190,28 @@ __global__ void __launch_bounds__(BX) k_fused_moments(Grid g, RefPops ref, typen
             // itself on a zero-gradient wall when c points inward)
             const int sxl = (g.clampx && ((x == 0 && cx == 1) || (x == g.nx - 1 && cx == -1))) ? lx : lx - cx;
             const int syl = (g.clampy && ((y == 0 && cy == 1) || (y == g.ny - 1 && cy == -1))) ? ly : ly - cy;
-            const int src = ((syl < 0 ? -1 : (syl >= h ? 1 : 0)) + 1) * 3 + (sxl < 0 ? -1 : (sxl >= w ? 1 : 0)) + 1;
+            src[k] = ((syl < 0 ? -1 : (syl >= h ? 1 : 0)) + 1) * 3 + (sxl < 0 ? -1 : (sxl >= w ? 1 : 0)) + 1;
             const long long pi = arrived_index<D>(g, i, x, y, D == 3 ? z : 0, pull);
-            const C v = S::dev(fi, pi, (C)ref.f[i]);
-            const C vg = S::dev(gi, pi, (C)ref.g[i]);
-            for (int q = 0; q < 9; q++) {
-                const C vq = q == src ? v : C(0);
-                s0[q] += vq;
-                if (k % 3 == 0) sx[q] -= vq;
-                if (k % 3 == 2) sx[q] += vq;
-                if (k / 3 == 0) sy[q] -= vq;
-                if (k / 3 == 2) sy[q] += vq;
-                sg[q] += q == src ? vg : C(0);
-            }
+            v[k] = S::dev(fi, pi, (C)ref.f[i]);
+            vg[k] = S::dev(gi, pi, (C)ref.g[i]);
         }
+        // per source tile, the gather's sums over its share of the 3 x 3
+        // directions (the others read as zero), in the gather's order
         for (int q = 0; q < 9; q++) {
-            acc[cls][q][0] += s0[q];
-            acc[cls][q][1] += sx[q];
-            acc[cls][q][2] += sy[q];
-            acc[cls][q][3] += C(cz) * s0[q];
-            acc[cls][q][4] += sg[q];
+            C a[9], b[9];
+            for (int k = 0; k < 9; k++) {
+                a[k] = src[k] == q ? v[k] : C(0);
+                b[k] = src[k] == q ? vg[k] : C(0);
+            }
+            const C r0 = a[0] + a[1] + a[2], r1 = a[3] + a[4] + a[5], r2 = a[6] + a[7] + a[8];
+            const C s0 = r0 + r1 + r2;
+            C sg = b[0];
+            for (int k = 1; k < 9; k++) sg += b[k];
+            acc[cls][q][0] += s0;
+            acc[cls][q][1] += (a[2] + a[5] + a[8]) - (a[0] + a[3] + a[6]);
+            acc[cls][q][2] += r2 - r0;
+            if (cz != 0) acc[cls][q][3] += cz > 0 ? s0 : -s0;
+            acc[cls][q][4] += sg;
         }
     }
     // inbound part of one class in the order of the fix-up pass
