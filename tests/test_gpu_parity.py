@@ -236,6 +236,56 @@ def test_taylor_green_256_full_run_properties():
     assert umax[-1] < c["U0"]
 
 
+def test_taylor_green_512_surrogate_bf16_200_steps_properties():
+    """The benchmark's own form at full size: 512^3 Taylor-Green, BF16
+    deviation storage with the surrogate EOS (threshold 1e-6, FP64
+    fallback), 200 steps, checked by what holds at any size: fields finite
+    and inside the EOS domain, mass and net momentum kept to the rounding of
+    the 16-bit storage, the vortex's peak velocity bounded by its start.
+
+    Not the workload's 2000 steps: at mu = 0.05 (lattice Reynolds number
+    about 1,370) the peak velocity starts to grow after about 250 steps and
+    the flow diverges after about 350 in every storage form, plain FP32
+    included, and the same Reynolds number diverges sooner
+    at 256^3 (mu = 0.025, 75 steps) and in the FP64 oracle at 64^3 (mu =
+    0.00625, 50 steps): a limit of the scheme without the paper's numerical
+    viscosity, not of the kernels."""
+    lbm = _lbm()
+    c = ST["tgv_3d_512"]
+    shape = tuple(c["shape"])
+    steps = 200
+    rho, u, T = inputs.taylor_green(shape, c["seed"], c["rho0"], c["T0"], c["U0"], c["noise"])
+    box = ST["shock_drop_3d"]["mlp_box"]
+    _say(f"case TGV {shape} BF16 + surrogate, {steps} steps")
+    umax = []
+    with lbm.Lattice(3, shape, storage="bf16", eos="mlp", mlp_tol=1e-6, ref_rho=c["rho0"], ref_T=c["T0"],
+                     **KW) as lat:
+        params, norm, _ = lbm.mlp_train([box["rho"][0], box["rho"][1], box["T"][0], box["T"][1]], 131072, 4, 20,
+                                        4096, 3e-3, inputs.mlp_params(4).astype(np.float32), a=CONST["a"],
+                                        b=CONST["b"], R=CONST["R"], cv=CONST["cv"])
+        lat.mlp_set(params, norm)
+        assert lat.fused
+        lat.init(rho, u, T)
+        del rho, u, T
+        s0 = lat.conservation()
+        for _ in range(2):
+            lat.step(steps // 2)
+            m = lat.moments()
+            assert all(bool(v.isfinite().all()) for v in m.values())
+            umax.append(float(m["u"].abs().max()))
+            r, t, pr = m["rho"], m["T"], m["P"]
+            _say(f"  rho [{float(r.min()):.3f}, {float(r.max()):.3f}], T [{float(t.min()):.4f}, {float(t.max()):.4f}]")
+            assert 0 < float(r.min()) and float(r.max()) < 1 / KW["b"]
+            assert float(t.min()) > 0 and float(pr.min()) > 0
+            del m, r, t, pr
+        s1 = lat.conservation()
+    mass = s0[0]
+    dm, dp = abs(s1[0] - s0[0]) / mass, np.abs(s1[1:4]).max() / mass
+    _say(f"  mass drift {dm:.2e}, net momentum {dp:.2e}, max |u| {umax}")
+    assert dm <= 5e-4 and dp <= 1e-6
+    assert max(umax) < 1.1 * c["U0"]
+
+
 def test_taylor_green_fp32_200_steps():
     """Near-critical Taylor-Green vortex (rho_c, 1.1 T_c, Ma 0.5, 1 % noise) on
     a reduced 40x32x24 periodic lattice, FP32 vs FP64 oracle."""
