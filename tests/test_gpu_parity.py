@@ -164,6 +164,47 @@ def test_fp32_and_16bit_multitile(storage, D, shape, bc, nseg):
         assert ef <= bar and eg <= bar
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+def test_multi_kernel_path_z_walls(storage):
+    """A zero-gradient z axis takes the multi-kernel path (one pass per
+    flowchart box, fields through HBM) instead of the fused step: FP32 and
+    the 16-bit forms on a ragged 70 x 9 x 7 lattice walled in x and z,
+    8 steps against the FP64 oracle, with the bars of the fused multi-tile
+    case (16-bit: infinite upwind dead zone on both sides)."""
+    lbm = _lbm()
+    D, shape, bc, steps = 3, (70, 9, 7), (1, 0, 1), 8
+    rho, u, T = inputs.random_state(D, shape, 29, RHOC, 1.1 * TC, drho=0.04, du=0.08, dT=0.03, white=0.002)
+    kw, okw = dict(KW), dict(KW)
+    if storage != "f32":
+        kw.update(ref_rho=RHOC, ref_T=1.1 * TC, upwind_eps=1e30)
+        okw.update(upwind_eps=1e30)
+    _say(f"case multi-kernel path shape={shape} bc={bc} storage={storage}")
+    with lbm.Lattice(D, shape, bc=bc, storage=storage, **kw) as lat:
+        assert not lat.fused
+        lat.init(rho, u, T).step(steps)
+        f, g = (t.cpu().numpy().astype(np.float64) for t in lat.get_populations())
+        mom = {k: v.cpu().numpy() for k, v in lat.moments().items()}
+    p = oracle.Params(D, shape, bc=bc, **okw)
+    fr, gr = oracle.run(p, *oracle.init(p, rho, u, T), steps)
+    ref = oracle.fields(p, fr, gr)
+    if storage == "f32":
+        for k in ("rho", "u", "T", "P"):
+            e = rel_l2(mom[k], ref[k])
+            _say(f"  {k} rel-L2 {e:.2e}")
+            assert e <= 1e-5, k
+        return
+    e = rel_l2(mom["rho"], ref["rho"])
+    p1 = oracle.Params(D, (1, 1, 1), **KW)
+    f_ref, g_ref = oracle.init(p1, np.array([RHOC]), np.zeros(D), np.array([1.1 * TC]))
+    Q = len(f_ref)
+    ef = np.abs(f - fr).max() / np.abs(fr.reshape(Q, -1) - f_ref[:, None]).max()
+    eg = np.abs(g - gr).max() / np.abs(gr.reshape(Q, -1) - g_ref[:, None]).max()
+    _say(f"  rho rel-L2 {e:.2e}, f {ef:.2e}, g {eg:.2e} of the largest deviation")
+    assert e <= 1e-3
+    bar = 2 * steps * (2.0 ** -9 if storage == "bf16" else 2.0 ** -12)
+    assert ef <= bar and eg <= bar
+
+
 @pytest.mark.parametrize("variant", ["vdw", "ideal"])
 def test_shock_tube_fp64_200_steps(variant):
     """512x4 D2Q9 shock tube at T = 0.9 T_c, rho = 0.9 / 0.3 rho_c; the ideal
