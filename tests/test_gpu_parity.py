@@ -517,6 +517,18 @@ def test_fused_path_beyond_2gib_of_inbound_slots():
                             _random_cells(shape, 12), (c["rho0"], c["T0"]), expect_fused=True)
 
 
+def test_plane_beyond_fused_limit_takes_multi_kernel_path():
+    """3200 x 3200 x 11 cells, FP32: one plane of populations (2 Q nx ny x 4 B
+    = 2.2 GB) exceeds what a 32-bit buffer resource addresses, so the
+    lattice takes the multi-kernel path (64-bit cell indices); one step, 12
+    sampled cells against the oracle's collision of the same populations."""
+    c = ST["tgv_3d_256"]
+    shape = (3200, 3200, 11)
+    state = inputs.taylor_green(shape, c["seed"], c["rho0"], c["T0"], c["U0"], c["noise"])
+    _sampled_cells_one_step(3, shape, (0, 0, 0), state, dict(storage="f32"), _random_cells(shape, 12),
+                            expect_fused=False)
+
+
 def _shock_drop_cells(c, shape):
     """Cells that see each part of the shock-drop: the drop's centre, its
     interface on four sides, the shock front, the post-shock state and the
