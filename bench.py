@@ -9,8 +9,9 @@ the two forms the metric compares on the same steps:
   * surrogate: BF16 deviation storage, FP32 arithmetic, MLP EOS (BF16 MFMA)
     with residual check and FP64 Newton fallback, FP64 conservation sums.
 `value` is the surrogate form's MLUPS (the full hot path); the plain form's
-figures are reported beside it.  Inputs are synthetic and resident in HBM
-before the timed region; the timed region is K steps bracketed by device
+figures are reported beside it, and those of BF16 storage with the explicit
+EOS (what the surrogate pass costs).  Inputs are synthetic and resident in
+HBM before the timed region; the timed region is K steps bracketed by device
 synchronisation.  One JSON line is printed.
 """
 from __future__ import annotations
@@ -120,29 +121,44 @@ def time_form(lbm, torch, shape, bc, fields, ref, kw, storage, eos, steps, warmu
         lat.close()
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
+    # sums: [mass, momentum (3), sum g, non-finite cells, inadmissible cells]
     return dict(seconds=dt, mlups=N * steps / dt / 1e6, ms_per_step=1e3 * dt / steps, bytes_per_cell=bpc,
-                kernel_ms=kt, finite=bool(sums[-1] == 0), fallback_fraction=fb, mass=float(sums[0]))
+                kernel_ms=kt, finite=bool(sums[5] == 0), admissible=bool(sums[6] == 0), fallback_fraction=fb,
+                mass=float(sums[0]))
 
 
-def cpu_baseline(st, seconds_target=15.0):
+def cpu_baseline(st, seconds_target=12.0):
+    """The FP64 oracle on the host's cores: a 64^3 sample of the benchmark's
+    workload (same recipe and constants), timed with every host thread and
+    with one."""
     import oracle
-    c = st["tgv_3d_256"]
-    k = st["constants"]
-    shape = (64, 64, 64)
     from paper_2510_14712_amd import inputs
+    c = st["tgv_3d_512"]
+    shape = (64, 64, 64)
     rho, u, T = inputs.taylor_green(shape, c["seed"], c["rho0"], c["T0"], c["U0"], c["noise"])
-    p = oracle.Params(3, shape, a=k["a"], b=k["b"], R=k["R"], cv=k["cv"], mu=k["mu"], eta=k["eta"], k=k["k"],
-                      kappa=k["kappa"])
-    f, g = oracle.init(p, rho, u, T)
-    t0 = time.perf_counter()
-    f, g = oracle.run(p, f, g, 1)
-    one = time.perf_counter() - t0
-    n = max(1, int(seconds_target / max(one, 1e-3)))
-    t0 = time.perf_counter()
-    oracle.run(p, f, g, n)
-    dt = time.perf_counter() - t0
-    return {"value": p.N * n / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"FP64 oracle, D3Q27 Taylor-Green 64^3 (same state recipe), {n} steps, {dt:.1f} s"}
+    p = oracle.Params(3, shape, **inputs.physics(st, "tgv_3d_512"))
+    f0, g0 = oracle.init(p, rho, u, T)
+
+    def timed(threads):
+        oracle.set_num_threads(threads)
+        t0 = time.perf_counter()
+        f, g = oracle.run(p, f0, g0, 1)
+        one = time.perf_counter() - t0
+        n = max(1, int(seconds_target / max(one, 1e-3)))
+        t0 = time.perf_counter()
+        oracle.run(p, f, g, n)
+        dt = time.perf_counter() - t0
+        return p.N * n / dt / 1e6, n, dt
+
+    ncores = oracle.num_threads()  # the OpenMP default: OMP_NUM_THREADS, else the host's cores
+    mt, n, dt = timed(ncores)
+    threads = oracle.num_threads()
+    st1, n1, dt1 = timed(1)
+    oracle.set_num_threads(ncores)
+    return {"value": round(mt, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle, D3Q27 Taylor-Green 64^3 (the workload's recipe and constants), {n} steps in "
+                      f"{dt:.1f} s on {threads} threads; 1 thread: {n1} steps in {dt1:.1f} s",
+            "single_thread": {"value": round(st1, 4), "unit": "MLUPS", "cores": 1}}
 
 
 def main():
@@ -152,7 +168,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="tgv512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,surrogate", help="comma list of forms to time")
+    ap.add_argument("--forms", default="plain,bf16vdw,surrogate", help="comma list of forms to time")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -175,18 +191,23 @@ def main():
     lbm.load()
     torch.cuda.set_device(0)
     st = inputs.states()
-    k = st["constants"]
-    kw = dict(a=k["a"], b=k["b"], R=k["R"], cv=k["cv"], mu=k["mu"], eta=k["eta"], k=k["k"], kappa=k["kappa"])
+    wl = {"tgv512": "tgv_3d_512", "tgv256": "tgv_3d_256", "drop3d": "shock_drop_3d"}[args.workload]
+    kw = inputs.physics(st, wl)
     shape, bc, fields, ref, desc = workload(args.workload, st)
     N = int(np.prod(shape))
 
     forms = args.forms.split(",")
+    plain = bvdw = None
     if "plain" in forms:
         _p(f"plain FP32 form on {shape}")
         plain = time_form(lbm, torch, shape, bc, fields, ref, kw, "f32", "vdw", args.steps, args.warmup)
         _p(f"  {plain['mlups']:.0f} MLUPS, kernels {plain['kernel_ms']}")
+    if "bf16vdw" in forms:
+        _p("BF16 deviation form, explicit van der Waals EOS")
+        bvdw = time_form(lbm, torch, shape, bc, fields, ref, kw, "bf16", "vdw", args.steps, args.warmup)
+        _p(f"  {bvdw['mlups']:.0f} MLUPS, kernels {bvdw['kernel_ms']}")
     if "surrogate" not in forms:
-        print(json.dumps({"forms": {"plain_fp32": plain}}), flush=True)
+        print(json.dumps({"forms": {"plain_fp32": plain, "bf16_vdw": bvdw}}), flush=True)
         return
     _p("training the surrogate EOS on the GPU")
     params, norm, loss, t_train = train_surrogate(st, lbm)
@@ -195,8 +216,8 @@ def main():
     surr = time_form(lbm, torch, shape, bc, fields, ref, kw, "bf16", "mlp", args.steps, args.warmup,
                      mlp=(params, norm))
     _p(f"  {surr['mlups']:.0f} MLUPS, kernels {surr['kernel_ms']}, fallback {surr['fallback_fraction']}")
-    if "plain" not in forms:
-        print(json.dumps({"forms": {"surrogate_bf16": surr}}), flush=True)
+    if plain is None:
+        print(json.dumps({"forms": {"surrogate_bf16": surr, "bf16_vdw": bvdw}}), flush=True)
         return
 
     def roof(form, name):
@@ -231,9 +252,14 @@ def main():
                                                       / HBM_PEAK_GBS, 4),
                                "kernel_ms": surr["kernel_ms"], "finite": surr["finite"],
                                "fallback_fraction": surr["fallback_fraction"], "mlp_train_s": round(t_train, 2),
-                               "mlp_loss": loss},
+                               "mlp_loss": loss, "admissible": surr["admissible"]},
         },
     }
+    if bvdw is not None:
+        line["forms"]["bf16_vdw"] = {
+            "mlups": round(bvdw["mlups"], 1), "ms_per_step": round(bvdw["ms_per_step"], 4),
+            "step_hbm_frac": round(bvdw["bytes_per_cell"] * bvdw["mlups"] * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
+            "kernel_ms": bvdw["kernel_ms"], "finite": bvdw["finite"], "roofline": roof(bvdw, "bf16_vdw")[1]}
     if not args.no_cpu_baseline:
         _p("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(st)

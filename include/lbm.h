@@ -41,8 +41,12 @@ extern "C" {
 #define LBM_EINVAL (-1)     /* invalid argument or parameter combination */
 #define LBM_ENOMEM (-2)     /* device allocation failed */
 #define LBM_EDEVICE (-3)    /* a HIP call or kernel launch failed */
-#define LBM_EUNSTABLE (-4)  /* a cell left the admissible set (theta <= 0,
-                               theta + u_a^2 >= 1, rho <= 0 or b rho >= 1) */
+#define LBM_EUNSTABLE (-4)  /* a cell outside the admissible set: rho <= 0,
+                               b rho >= 1, theta = P/rho <= 0, theta >= 1/3
+                               (the practical stability bound of Section 5,
+                               theta < dx^2 / (3 dt^2)) or theta + u_a^2 >= 1
+                               on some axis (the rest factor 1 - theta - u_a^2
+                               of eq. phi turns negative) */
 #define LBM_ENAN (-5)       /* a non-finite value was found */
 #define LBM_ESTATE (-6)     /* call out of order (e.g. step before init) */
 
@@ -90,14 +94,27 @@ typedef struct {
                                periodic z): 0 = automatic, else 1..nz; the
                                result does not depend on it beyond round-off
                                of the moment sums' order */
+    int check_every;        /* > 0: lbm_step checks the state every
+                               check_every steps (non-finite cells, then the
+                               admissible set of LBM_EUNSTABLE) and returns at
+                               the first failing check; 0: no checks */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx; /* opaque, library-owned */
 
-/* Create a context: validates parameters and allocates the two population
+/* Life cycle.  The problem statement's "initialise from (rho, u, T)" is split
+ * in two calls so that the caller can hand over device arrays (torch tensors)
+ * and reuse one context for several initial states: lbm_create validates the
+ * parameters and allocates every device buffer the step needs; lbm_init fills
+ * the populations; lbm_destroy releases the context.  No other call
+ * allocates device memory except lbm_mlp_train and lbm_mlp_loss_grad (their
+ * scratch, released before they return).
+ *
+ * Create a context: validates parameters and allocates the two population
  * buffers and the per-cell work arrays on the current device.
  * Errors: LBM_EINVAL (bad sizes, lattice, bc, storage/eos combination,
- * non-positive cv, mu; nz != 1 for lattice 2), LBM_ENOMEM, LBM_EDEVICE. */
+ * non-positive cv, mu; nz != 1 for lattice 2; check_every < 0), LBM_ENOMEM,
+ * LBM_EDEVICE. */
 int lbm_create(const lbm_params *params, lbm_ctx **out);
 
 /* Release every device allocation of the context (NULL is accepted). */
@@ -105,13 +122,22 @@ void lbm_destroy(lbm_ctx *ctx);
 
 /* Initialise f_i = f_i^eq(rho, u, theta), g_i = g_i^eq(rho, u, T, theta) with
  * theta = P(rho, T)/rho (flowchart "initialise"; eqs. LBMeq, LBMeqG).
- * dev_rho[N], dev_u[D*N], dev_T[N]: FP64 device arrays.  Asynchronous.
- * Errors: LBM_EINVAL (NULL pointer), LBM_EDEVICE. */
+ * dev_rho[N], dev_u[D*N], dev_T[N]: FP64 device arrays.  The inputs are
+ * checked first (blocking): a non-finite value gives LBM_ENAN, a cell
+ * outside the admissible set (see LBM_EUNSTABLE; P and theta from eq. Pvdw
+ * at the cell's rho, T) gives LBM_EUNSTABLE, and the context is then left
+ * uninitialised.  The initialisation itself is asynchronous.
+ * Errors: LBM_EINVAL (NULL pointer), LBM_ENAN, LBM_EUNSTABLE, LBM_EDEVICE. */
 int lbm_init(lbm_ctx *ctx, const double *dev_rho, const double *dev_u, const double *dev_T);
 
-/* Advance n >= 0 full steps (collide + stream).  Asynchronous: non-finite
- * states surface through lbm_conservation().
- * Errors: LBM_ESTATE (not initialised), LBM_EINVAL (n < 0), LBM_EDEVICE. */
+/* Advance n >= 0 full steps (collide + stream).  Asynchronous when
+ * params.check_every is 0: non-finite or inadmissible states then surface
+ * through lbm_conservation().  With check_every > 0 the state is checked after
+ * every check_every-th step (a blocking fields pass and reduction); the first
+ * failing check ends the call with LBM_ENAN or LBM_EUNSTABLE, the steps
+ * before it having been taken.
+ * Errors: LBM_ESTATE (not initialised), LBM_EINVAL (n < 0), LBM_ENAN,
+ * LBM_EUNSTABLE, LBM_EDEVICE. */
 int lbm_step(lbm_ctx *ctx, int n);
 
 /* Macroscopic fields of the current state with the half-force corrections
@@ -129,10 +155,12 @@ int lbm_get_populations(lbm_ctx *ctx, double *dev_f, double *dev_g);
 int lbm_set_populations(lbm_ctx *ctx, const double *dev_f, const double *dev_g);
 
 /* FP64 global sums of the current state, deterministic order (wavefront
- * reductions, fixed-order second pass).  host_out receives, in order:
+ * reductions, fixed-order second pass).  host_out[D + 4] receives, in order:
  *   [0] sum rho, [1..D] sum (sum_i c_i f_i + F/2) = sum rho u,
- *   [D+1] sum_i g_i summed over cells, [D+2] number of non-finite cells.
- * Blocking (synchronises the stream).  Returns LBM_ENAN when [D+2] > 0. */
+ *   [D+1] sum_i g_i summed over cells, [D+2] number of non-finite cells,
+ *   [D+3] number of finite cells outside the admissible set (LBM_EUNSTABLE).
+ * Blocking (synchronises the stream).  Returns LBM_ENAN when [D+2] > 0,
+ * else LBM_EUNSTABLE when [D+3] > 0 (the sums are written either way). */
 int lbm_conservation(lbm_ctx *ctx, double *host_out);
 
 /* Block until all work queued on the context's stream has finished. */
@@ -214,6 +242,16 @@ int lbm_mlp_stats(lbm_ctx *ctx, double *host_fallback_fraction);
  * B >= 0 any size.  Asynchronous on `stream`. */
 int lbm_mlp_forward(const float *dev_params, const float *dev_norm, const float *dev_x,
                     float *dev_y, int B, int precision, void *stream);
+
+/* One Adam update of a parameter vector (the optimiser step of
+ * lbm_mlp_train): m = b1 m + (1 - b1) grad, v = b2 v + (1 - b2) grad^2,
+ * params -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + 1e-8) with
+ * b1 = 0.9, b2 = 0.999 and t >= 1 the number of the update.  dev_params,
+ * dev_m, dev_v (updated in place) and dev_grad: 4547 FP32 values each.
+ * Asynchronous on `stream`.  Errors: LBM_EINVAL (NULL pointer, t < 1,
+ * lr not positive). */
+int lbm_mlp_adam(float *dev_params, const float *dev_grad, float *dev_m, float *dev_v, int t, float lr,
+                 void *stream);
 
 /* Mean-squared loss and its gradient on a batch: dev_xn[2*B] normalised
  * inputs, dev_tn[3*B] normalised targets (row-major per sample),

@@ -49,7 +49,7 @@ _DP = ctypes.POINTER(ctypes.c_double)
 
 class _Fields(ctypes.Structure):
     _fields_ = [(n, _DP) for n in ("rho", "u", "E", "T", "P", "theta", "h", "cs2",
-                                    "F", "Lambda", "lap")]
+                                    "F", "Lambda", "lap", "Phi")]
 
 
 _lib = None
@@ -78,6 +78,8 @@ def lib():
         for fn in ("oracle_init", "oracle_fields_eval", "oracle_collide", "oracle_stream",
                    "oracle_run", "oracle_num_threads"):
             getattr(L, fn).restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -161,7 +163,7 @@ def init(p: Params, rho, u, T):
 def _alloc_fields(p: Params):
     N, D = p.N, p.D
     arrs = {n: np.zeros(N) for n in ("rho", "E", "T", "P", "theta", "h", "cs2", "lap")}
-    for n in ("u", "F", "Lambda"):
+    for n in ("u", "F", "Lambda", "Phi"):
         arrs[n] = np.zeros(D * N)
     s = _Fields()
     for n, a in arrs.items():
@@ -179,7 +181,8 @@ def fields(p: Params, f, g):
 
 
 def collide(p: Params, f, g):
-    """Post-collision populations at each cell (no streaming) and the fields used."""
+    """Post-collision populations at each cell (no streaming) and the fields
+    used, with the upwind Galilean correction Phi_aa of each cell."""
     fp = np.zeros_like(f)
     gp = np.zeros_like(g)
     arrs, s = _alloc_fields(p)
@@ -232,3 +235,8 @@ def operator_moments(D, u, e, theta):
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's loops over cells (OpenMP)."""
+    lib().oracle_set_num_threads(int(n))

@@ -206,6 +206,7 @@ static long nbr_axis(const oracle_params *p, long idx, int a, int s) {
 /* ---------------------------------------------------------------------- */
 typedef struct {
     double *rho, *J, *G, *lap, *F, *u, *E, *T, *P, *theta, *e, *h, *cs2, *Lam;
+    double *Phi; /* diagonal Galilean correction of each cell, set by the collision */
 } work_fields;
 
 static void work_alloc(work_fields *w, long N, int D) {
@@ -223,12 +224,13 @@ static void work_alloc(work_fields *w, long N, int D) {
     w->h = calloc(N, sizeof(double));
     w->cs2 = calloc(N, sizeof(double));
     w->Lam = calloc((size_t)D * N, sizeof(double));
+    w->Phi = calloc((size_t)D * N, sizeof(double));
 }
 
 static void work_free(work_fields *w) {
     free(w->rho); free(w->J); free(w->G); free(w->lap); free(w->F); free(w->u);
     free(w->E); free(w->T); free(w->P); free(w->theta); free(w->e); free(w->h);
-    free(w->cs2); free(w->Lam);
+    free(w->cs2); free(w->Lam); free(w->Phi);
 }
 
 static void compute_fields(const oracle_params *p, const double *f, const double *g,
@@ -305,7 +307,7 @@ static void export_fields(const oracle_params *p, const work_fields *w, oracle_f
 #define CP(dst, src, n) if (out->dst) memcpy(out->dst, w->src, (size_t)(n) * sizeof(double))
     CP(rho, rho, N); CP(u, u, D * N); CP(E, E, N); CP(T, T, N); CP(P, P, N);
     CP(theta, theta, N); CP(h, h, N); CP(cs2, cs2, N); CP(F, F, D * N);
-    CP(Lambda, Lam, D * N); CP(lap, lap, N);
+    CP(Lambda, Lam, D * N); CP(lap, lap, N); CP(Phi, Phi, D * N);
 #undef CP
 }
 
@@ -318,7 +320,7 @@ static double sgn(double v, double eps) { return v > eps ? 1.0 : (v < -eps ? -1.
 /* Collision (eqs. fLBGK, gLBGK with LBMeq, LBMstar, LBMeqG, LBMgstar)     */
 /* ---------------------------------------------------------------------- */
 static void collide_all(const oracle_params *p, const double *f, const double *g,
-                        const work_fields *w, double *fpost, double *gpost) {
+                        work_fields *w, double *fpost, double *gpost) {
     const int D = p->D, Q = num_vel(D);
     const long N = (long)p->nx * p->ny * p->nz;
 
@@ -341,6 +343,7 @@ static void collide_all(const oracle_params *p, const double *f, const double *g
             double dL = 0.5 * (1.0 + s) * (w->Lam[a * N + x] - w->Lam[a * N + xm])
                       + 0.5 * (1.0 - s) * (w->Lam[a * N + xp] - w->Lam[a * N + x]);
             Phi[a] = -dL / rho;
+            w->Phi[a * N + x] = Phi[a];
         }
 
         double tau = p->mu / P;                                         /* tau = mu / P */
@@ -478,5 +481,13 @@ int oracle_num_threads(void) {
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

@@ -39,6 +39,8 @@ typedef struct {
 /* Per-cell fields produced while evaluating one step (all length N or D*N). */
 typedef struct {
     double *rho, *u, *E, *T, *P, *theta, *h, *cs2, *F, *Lambda, *lap;
+    double *Phi; /* Phi_aa = -(1/rho) d_a Lambda_a (upwind), D*N; filled by
+                    oracle_collide only */
 } oracle_fields;
 
 /* f = f^eq(rho, u, theta), g = g^eq(rho, u, T, theta), theta = P(rho,T)/rho. */
@@ -72,6 +74,8 @@ void oracle_operator_moments(int D, const double *u, double e, double theta,
                              double *M);
 
 int oracle_num_threads(void);
+/* threads of the OpenMP loops over cells (n > 0) */
+void oracle_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -18,8 +18,6 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import thermo as th
-
 N_IN, N_H, N_OUT = 2, 64, 3
 SIZES = [N_H * N_IN, N_H, N_H * N_H, N_H, N_OUT * N_H, N_OUT]
 N_PARAMS = sum(SIZES)  # 4547
@@ -84,19 +82,6 @@ def adam(params, grad, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1.0 - b1 ** t)
     vh = v / (1.0 - b2 ** t)
     return params - lr * mh / (np.sqrt(vh) + eps), m, v
-
-
-def eos_targets(rho, T, a, b, R, cv):
-    """Training pairs: inputs (rho, e), targets (T, P, c_s^2) from the EOS."""
-    e = th.energy(rho, T, a, cv)
-    x = np.stack([rho, e], axis=1)
-    y = np.stack([T, th.pressure(rho, T, a, b, R), th.cs2(rho, T, a, b, R, cv)], axis=1)
-    return x, y
-
-
-def caloric_residual(rho, e, T_hat, a, cv):
-    """|e(rho, T_hat) - e| / (c_v T_hat): relative caloric misfit of a surrogate T."""
-    return np.abs(th.energy(rho, T_hat, a, cv) - e) / (cv * np.abs(T_hat))
 
 
 # ---------------------------------------------------------------------------

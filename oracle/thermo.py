@@ -45,10 +45,6 @@ def dPdrho_T(rho, T, a, b, R=1.0):
     return R * T / (1.0 - b * rho) ** 2 - 2.0 * a * rho
 
 
-def dPdT_rho(rho, T, a, b, R=1.0):
-    return rho * R / (1.0 - b * rho)
-
-
 def cp(rho, T, a, b, R, cv):
     """Isobaric specific heat for van der Waals, eq. cpvdW."""
     return cv + R * R * T / (R * T - 2.0 * a * rho * (1.0 - b * rho) ** 2)
@@ -135,7 +131,7 @@ def rankine_hugoniot(rho1, T1, Ma, a, b, R, cv):
 
 
 def fundamental_derivative(rho, T, a, b, R, cv):
-    """Gamma = 1 + (rho/c) (dc/drho)_s (the definition before eq. Gamma),
+    """Gamma = 1 + (rho/c) (dc/drho)_s (eq. Gamma, its definition),
     evaluated by differentiating c along an isentrope numerically."""
     # isentrope of van der Waals: T (1/rho - b)^(R/cv) = const (from eq. ds_vdW)
     s_const = T * (1.0 / rho - b) ** (R / cv)
@@ -147,6 +143,22 @@ def fundamental_derivative(rho, T, a, b, R, cv):
     hstep = 1e-5 * rho
     dc = (c_on_isentrope(rho + hstep) - c_on_isentrope(rho - hstep)) / (2 * hstep)
     return 1.0 + rho / c_on_isentrope(rho) * dc
+
+
+def fundamental_derivative_vdw(rho, P, a, b, R, cv):
+    """Closed form of Gamma(P, rho) for van der Waals with constant c_v
+    (Section 4.3, the expression after eq. Gamma).  The printed denominator
+    reads 2 (R/c_v + 1) (P + a rho^2) / (1/rho - b) - 4 a rho^4, whose two
+    terms differ in dimension by a density; differentiating the isentrope
+    P + a rho^2 = K (1/rho - b)^-(1 + R/c_v) twice gives the first term with
+    one more factor rho, which this function restores (it then reduces to
+    (gamma + 1)/2 for the ideal gas and agrees with the definition)."""
+    g = R / cv + 1.0
+    v = 1.0 / rho
+    Pa = P + a * rho * rho
+    num = g * (g + 1.0) * Pa / (v - b) ** 2 - 6.0 * a * rho ** 4
+    den = 2.0 * g * rho * Pa / (v - b) - 4.0 * a * rho ** 4
+    return num / den
 
 
 # -- exact Riemann solution of the ideal-gas Euler equations (gamma-law gas)

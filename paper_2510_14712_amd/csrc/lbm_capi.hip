@@ -22,30 +22,29 @@ using namespace lbm;
 // ---------------------------------------------------------------------------
 namespace lbm {
 constexpr int RED_BLOCK = 256;
-constexpr int RED_VALS = 6;  // rho, j_x, j_y, j_z, G, non-finite count
+constexpr int RED_VALS = 7;  // rho, j_x, j_y, j_z, G, non-finite count, inadmissible count
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
-template <int D, class C>
-__global__ void __launch_bounds__(RED_BLOCK) k_reduce_partials(long long N, Fields<C> fl, double *partials) {
+// The admissible set of a cell state: rho > 0 and b rho < 1 (the van der
+// Waals domain, eq. Pvdw), 0 < theta < 1/3 (theta = P/rho; the practical
+// stability bound theta < dx^2/(3 dt^2) of Section 5) and theta + u_a^2 < 1
+// on every axis (the rest factor 1 - theta - u_a^2 of eq. phi stays
+// positive).  Evaluated in FP64 on finite inputs.
+template <int D>
+__device__ __forceinline__ bool admissible(double rho, double theta, const double *u, double b) {
+    bool ok = rho > 0.0 && b * rho < 1.0 && theta > 0.0 && theta < 1.0 / 3.0;
+    for (int a = 0; a < D; a++) ok = ok && theta + u[a] * u[a] < 1.0;
+    return ok;
+}
+
+// per-block partial sums of the RED_VALS values, written by lane k < RED_VALS
+// of the block in a fixed order (wavefront shuffles, then LDS)
+__device__ __forceinline__ void block_partials(double (&acc)[RED_VALS], double *partials) {
     __shared__ double sh[RED_VALS][RED_BLOCK / 64];
-    double acc[RED_VALS] = {0, 0, 0, 0, 0, 0};
-    for (long long c = blockIdx.x * (long long)RED_BLOCK + threadIdx.x; c < N; c += (long long)gridDim.x * RED_BLOCK) {
-        double rho = fl.rho[c];
-        double G = fl.G[c];
-        bool bad = !isfinite(rho) || !isfinite(G);
-        acc[0] += rho;
-        for (int a = 0; a < D; a++) {
-            double j = (double)fl.J[a * N + c] + 0.5 * (double)fl.F[a * N + c];
-            acc[1 + a] += j;
-            bad = bad || !isfinite(j);
-        }
-        acc[4] += G;
-        acc[5] += bad ? 1.0 : 0.0;
-    }
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int k = 0; k < RED_VALS; k++) {
         double s = wave_sum(acc[k]);
@@ -57,6 +56,52 @@ __global__ void __launch_bounds__(RED_BLOCK) k_reduce_partials(long long N, Fiel
         for (int i = 0; i < RED_BLOCK / 64; i++) s += sh[threadIdx.x][i];
         partials[(long long)blockIdx.x * RED_VALS + threadIdx.x] = s;
     }
+}
+
+template <int D, class C>
+__global__ void __launch_bounds__(RED_BLOCK) k_reduce_partials(long long N, Fields<C> fl, double b, double *partials) {
+    double acc[RED_VALS] = {0, 0, 0, 0, 0, 0, 0};
+    for (long long c = blockIdx.x * (long long)RED_BLOCK + threadIdx.x; c < N; c += (long long)gridDim.x * RED_BLOCK) {
+        double rho = fl.rho[c];
+        double G = fl.G[c];
+        double P = fl.P[c];
+        bool bad = !isfinite(rho) || !isfinite(G) || !isfinite(P);
+        acc[0] += rho;
+        double u[3] = {0, 0, 0};
+        for (int a = 0; a < D; a++) {
+            double j = (double)fl.J[a * N + c] + 0.5 * (double)fl.F[a * N + c];
+            acc[1 + a] += j;
+            u[a] = fl.u[a * N + c];
+            bad = bad || !isfinite(j) || !isfinite(u[a]);
+        }
+        acc[4] += G;
+        acc[5] += bad ? 1.0 : 0.0;
+        acc[6] += (!bad && !admissible<D>(rho, P / rho, u, b)) ? 1.0 : 0.0;
+    }
+    block_partials(acc, partials);
+}
+
+// the same counts for the FP64 inputs of lbm_init (rho, u, T given; P from
+// eq. Pvdw), columns 5 and 6 of the partials, the others zero
+template <int D>
+__global__ void __launch_bounds__(RED_BLOCK) k_check_inputs(long long N, Phys<double> ph, const double *rho,
+                                                            const double *u, const double *T, double *partials) {
+    double acc[RED_VALS] = {0, 0, 0, 0, 0, 0, 0};
+    for (long long c = blockIdx.x * (long long)RED_BLOCK + threadIdx.x; c < N; c += (long long)gridDim.x * RED_BLOCK) {
+        const double r = rho[c], t = T[c];
+        double uu[3] = {0, 0, 0};
+        bool bad = !isfinite(r) || !isfinite(t);
+        for (int a = 0; a < D; a++) {
+            uu[a] = u[a * N + c];
+            bad = bad || !isfinite(uu[a]);
+        }
+        acc[5] += bad ? 1.0 : 0.0;
+        if (!bad) {
+            const double P = vdw_pressure(ph, r, t);
+            acc[6] += admissible<D>(r, P / r, uu, ph.b) ? 0.0 : 1.0;
+        }
+    }
+    block_partials(acc, partials);
 }
 
 __global__ void __launch_bounds__(64) k_reduce_final(int nblocks, const double *partials, double *out) {
@@ -315,7 +360,23 @@ template <int D, class S> struct Impl {
         fused_fixup(c);
     }
 
+    // counts of non-finite and inadmissible cells of the inputs (blocking)
+    static int check_inputs(lbm_ctx *c, const double *rho, const double *u, const double *Tf) {
+        hipLaunchKernelGGL((k_check_inputs<D>), dim3(c->red_blocks), dim3(RED_BLOCK), 0, c->stream,
+                           (long long)c->grid.N, make_phys<double>(c->p), rho, u, Tf, c->red_partials);
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, c->stream, c->red_blocks, c->red_partials,
+                           c->red_out);
+        int rc = last_launch();
+        if (rc) return rc;
+        double tmp[RED_VALS];
+        if (hipMemcpyAsync(tmp, c->red_out, sizeof(tmp), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return lbm_note(hipGetLastError());
+        return tmp[5] > 0 ? LBM_ENAN : (tmp[6] > 0 ? LBM_EUNSTABLE : LBM_OK);
+    }
     static int init(lbm_ctx *c, const double *rho, const double *u, const double *Tf) {
+        int rc0 = check_inputs(c, rho, u, Tf);
+        if (rc0) return rc0;
         hipLaunchKernelGGL((k_init<D, S>), cell_grid(c), dim3(BX), 0, c->stream, c->grid, make_phys<double>(c->p), c->ref,
                            rho, u, Tf, (T *)c->f[c->cur], (T *)c->g[c->cur]);
         c->pulled = 0;
@@ -337,25 +398,30 @@ template <int D, class S> struct Impl {
         return last_launch();
     }
     static int step(lbm_ctx *c, int n) {
-        if (c->fused) {
-            for (int s = 0; s < n; s++) {
-                fused_launch(c);
-                int rc = last_launch();
-                if (rc) return rc;
-            }
-            return LBM_OK;
-        }
         Fields<C> fl = get_fields<C>(c);
         dim3 gr = cell_grid(c);
         for (int s = 0; s < n; s++) {
-            int rc = fields_pass(c);
+            int rc;
+            if (c->fused) {
+                fused_launch(c);
+                rc = last_launch();
+            } else {
+                rc = fields_pass(c);
+                if (rc) return rc;
+                int nxt = 1 - c->cur;
+                hipLaunchKernelGGL((k_collide<D, S>), gr, dim3(BX), 0, c->stream, c->grid, make_phys<C>(c->p), c->ref,
+                                   (const T *)c->f[c->cur], (const T *)c->g[c->cur], fl, (T *)c->f[nxt],
+                                   (T *)c->g[nxt]);
+                rc = last_launch();
+                c->cur = nxt;
+            }
             if (rc) return rc;
-            int nxt = 1 - c->cur;
-            hipLaunchKernelGGL((k_collide<D, S>), gr, dim3(BX), 0, c->stream, c->grid, make_phys<C>(c->p), c->ref,
-                               (const T *)c->f[c->cur], (const T *)c->g[c->cur], fl, (T *)c->f[nxt], (T *)c->g[nxt]);
-            rc = last_launch();
-            if (rc) return rc;
-            c->cur = nxt;
+            c->steps_done++;
+            if (c->p.check_every > 0 && c->steps_done % c->p.check_every == 0) {
+                double tmp[RED_VALS];
+                rc = conservation(c, tmp);
+                if (rc) return rc;
+            }
         }
         return LBM_OK;
     }
@@ -496,7 +562,7 @@ template <int D, class S> struct Impl {
         int rc = fields_pass(c);
         if (rc) return rc;
         hipLaunchKernelGGL((k_reduce_partials<D, C>), dim3(c->red_blocks), dim3(RED_BLOCK), 0, c->stream,
-                           (long long)c->grid.N, get_fields<C>(c), c->red_partials);
+                           (long long)c->grid.N, get_fields<C>(c), c->p.b, c->red_partials);
         hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, c->stream, c->red_blocks, c->red_partials,
                            c->red_out);
         rc = last_launch();
@@ -509,7 +575,8 @@ template <int D, class S> struct Impl {
         for (int a = 0; a < D; a++) host_out[1 + a] = tmp[1 + a];
         host_out[D + 1] = tmp[4];
         host_out[D + 2] = tmp[5];
-        return tmp[5] > 0 ? LBM_ENAN : LBM_OK;
+        host_out[D + 3] = tmp[6];
+        return tmp[5] > 0 ? LBM_ENAN : (tmp[6] > 0 ? LBM_EUNSTABLE : LBM_OK);
     }
 };
 
@@ -576,6 +643,7 @@ static int validate(const lbm_params *p) {
     if (!(p->cv > 0) || !(p->mu > 0) || !(p->R > 0)) return LBM_EINVAL;
     if (!(p->upwind_eps >= 0)) return LBM_EINVAL;
     if (p->zsegments < 0 || p->zsegments > p->nz) return LBM_EINVAL;
+    if (p->check_every < 0) return LBM_EINVAL;
     if ((long long)p->nx * p->ny > (1LL << 30)) return LBM_EINVAL;
     if ((p->storage == LBM_STORE_BF16 || p->storage == LBM_STORE_F16) && !(p->ref_rho > 0 && p->ref_T > 0))
         return LBM_EINVAL;
@@ -666,11 +734,18 @@ void lbm_destroy(lbm_ctx *c) {
     delete c;
 }
 
+static int init_dispatch(lbm_ctx *c, const double *rho, const double *u, const double *Tf) {
+    DISPATCH(c, init(c, rho, u, Tf));
+}
+
 int lbm_init(lbm_ctx *c, const double *rho, const double *u, const double *Tf) {
     if (!c || !rho || !u || !Tf) return LBM_EINVAL;
     c->cur = 0;
-    c->initialized = true;
-    DISPATCH(c, init(c, rho, u, Tf));
+    c->initialized = false;
+    const int rc = init_dispatch(c, rho, u, Tf);
+    c->initialized = rc == LBM_OK;
+    c->steps_done = 0;
+    return rc;
 }
 
 int lbm_step(lbm_ctx *c, int n) {
@@ -697,6 +772,7 @@ int lbm_get_populations(lbm_ctx *c, double *f, double *g) {
 int lbm_set_populations(lbm_ctx *c, const double *f, const double *g) {
     if (!c || !f || !g) return LBM_EINVAL;
     c->initialized = true;
+    c->steps_done = 0;
     DISPATCH(c, set_pops(c, f, g));
 }
 

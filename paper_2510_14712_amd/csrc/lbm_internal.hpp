@@ -18,6 +18,7 @@ struct lbm_ctx {
     lbm::RefPops ref;
     hipStream_t stream = nullptr;
     bool initialized = false;
+    long long steps_done = 0;         // steps since the last init / set_populations (check interval)
     bool mlp_ready = false;
     int red_blocks = 0;
     double *red_partials = nullptr;

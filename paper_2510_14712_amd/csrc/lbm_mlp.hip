@@ -254,7 +254,8 @@ __global__ void __launch_bounds__(64) k_train_partial(const float *__restrict__ 
         for (int bb = 0; bb < 64; bb++) s += DY[3 * bb + lane];
         G[OFF_B3 + lane] = s;
     }
-    // dZ2[b][n] = (sum_k DY[b][k] W3[k][n]) (1 - H2^2), lane n over all b
+    // dZ2[b][n] = (sum_k DY[b][k] W3[k][n]) ReLU'(z2), lane n over all b (the
+    // unit is active where its output H2 is positive)
     for (int bb = 0; bb < 64; bb++) {
         float h2 = H2[bb * LD + lane];
         float d = DY[3 * bb] * P[OFF_W3 + lane] + DY[3 * bb + 1] * P[OFF_W3 + H + lane] +
@@ -447,6 +448,13 @@ int lbm_mlp_forward(const float *params, const float *norm, const float *x, floa
         hipLaunchKernelGGL(mlp::k_forward<true>, gr, dim3(64), 0, (hipStream_t)stream, params, norm, x, y, B);
     else
         hipLaunchKernelGGL(mlp::k_forward<false>, gr, dim3(64), 0, (hipStream_t)stream, params, norm, x, y, B);
+    return lbm_note(hipGetLastError());
+}
+
+int lbm_mlp_adam(float *params, const float *grad, float *m, float *v, int t, float lr, void *stream) {
+    if (!params || !grad || !m || !v || t < 1 || !(lr > 0)) return LBM_EINVAL;
+    hipLaunchKernelGGL(mlp::k_adam, dim3((mlp::NP + 255) / 256), dim3(256), 0, (hipStream_t)stream, params, grad, m,
+                       v, lr, (float)(1.0 - pow(0.9, (double)t)), (float)(1.0 - pow(0.999, (double)t)));
     return lbm_note(hipGetLastError());
 }
 

@@ -26,6 +26,18 @@ def states() -> dict:
         return json.load(fh)
 
 
+def physics(st: dict, workload: str | None = None) -> dict:
+    """Lattice-unit constants (a, b, R, cv, mu, eta, k, kappa) of a workload:
+    the shared constants, with the transport coefficients a workload entry
+    gives in place of the shared ones."""
+    kw = {k: st["constants"][k] for k in ("a", "b", "R", "cv", "mu", "eta", "k", "kappa")}
+    if workload is not None:
+        for k in ("mu", "eta", "k"):
+            if k in st[workload]:
+                kw[k] = st[workload][k]
+    return kw
+
+
 def grid(shape):
     """Integer coordinate arrays (x, y[, z]) of a lattice, x fastest."""
     if len(shape) == 2:

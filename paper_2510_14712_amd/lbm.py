@@ -39,7 +39,7 @@ class _Params(ctypes.Structure):
                 ("kappa", ctypes.c_double),
                 ("storage", ctypes.c_int), ("eos", ctypes.c_int), ("mlp_tol", ctypes.c_double),
                 ("ref_rho", ctypes.c_double), ("ref_T", ctypes.c_double), ("stream", ctypes.c_void_p),
-                ("upwind_eps", ctypes.c_double), ("zsegments", ctypes.c_int)]
+                ("upwind_eps", ctypes.c_double), ("zsegments", ctypes.c_int), ("check_every", ctypes.c_int)]
 
 
 _lib = None
@@ -82,6 +82,7 @@ def load():
         "lbm_mlp_stats": ([_VP, _DP], ctypes.c_int),
         "lbm_mlp_forward": ([_VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP], ctypes.c_int),
         "lbm_mlp_loss_grad": ([_VP, _VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
+        "lbm_mlp_adam": ([_VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_float, _VP], ctypes.c_int),
         "lbm_codec_encode": ([ctypes.c_int, _VP, _VP, _VP, ctypes.c_int64, _VP], ctypes.c_int),
         "lbm_codec_decode": ([ctypes.c_int, _VP, _VP, _VP, ctypes.c_int64, _VP], ctypes.c_int),
     }
@@ -134,7 +135,7 @@ class Lattice:
 
     def __init__(self, lattice, shape, bc=(0, 0, 0), a=3.0 / 49.0, b=2.0 / 21.0, R=1.0, cv=2.5, mu=0.05,
                  eta=0.05, k=None, kappa=0.01, storage="f32", eos="vdw", mlp_tol=1e-6, ref_rho=0.0, ref_T=0.0,
-                 stream=None, upwind_eps=UPWIND_EPS, zsegments=0):
+                 stream=None, upwind_eps=UPWIND_EPS, zsegments=0, check_every=0):
         L = load()
         self.D = int(lattice)
         nx, ny = int(shape[0]), int(shape[1])
@@ -156,6 +157,7 @@ class Lattice:
         p.ref_rho, p.ref_T = ref_rho, ref_T
         p.upwind_eps = upwind_eps
         p.zsegments = int(zsegments)
+        p.check_every = int(check_every)
         self._stream = stream
         p.stream = _stream_ptr(stream).value if _torch().cuda.is_available() else None
         self.params = p
@@ -229,11 +231,13 @@ class Lattice:
         return self
 
     def conservation(self, raise_on_nan=True):
-        out = (ctypes.c_double * 6)()
+        """[sum rho, sum rho u (D), sum g, non-finite cells, inadmissible cells];
+        raises on LBM_ENAN / LBM_EUNSTABLE unless raise_on_nan is False."""
+        out = (ctypes.c_double * 8)()
         rc = load().lbm_conservation(self._h, out)
-        if rc != LBM_OK and (rc != LBM_ENAN or raise_on_nan):
+        if rc != LBM_OK and (rc not in (LBM_ENAN, LBM_EUNSTABLE) or raise_on_nan):
             _check(rc, "lbm_conservation")
-        return np.array(out[: self.D + 3])
+        return np.array(out[: self.D + 4])
 
     def synchronize(self):
         _check(load().lbm_synchronize(self._h), "lbm_synchronize")
@@ -294,6 +298,14 @@ def mlp_loss_grad(params, xn, tn, precision=MLP_BF16, stream=None):
     _check(load().lbm_mlp_loss_grad(_ptr(pt), _ptr(xt), _ptr(tt), B, _ptr(grad), _ptr(loss), int(precision),
                                     _stream_ptr(stream)), "lbm_mlp_loss_grad")
     return loss, grad
+
+
+def mlp_adam(params, grad, m, v, t, lr, stream=None):
+    """lbm_mlp_adam on CUDA float32 tensors of 4547 values (updated in place)."""
+    for a in (params, grad, m, v):
+        assert a.is_cuda and a.dtype == _torch().float32 and a.is_contiguous() and a.numel() == MLP_NPARAMS
+    _check(load().lbm_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(t), float(lr), _stream_ptr(stream)),
+           "lbm_mlp_adam")
 
 
 def codec_encode(kind, x, ref, stream=None):

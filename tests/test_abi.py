@@ -50,6 +50,7 @@ def _params(**over):
     dict(lattice=4), dict(nx=0), dict(lattice=2, nz=2), dict(bc=(2, 0, 0)), dict(storage=7),
     dict(eos=3), dict(cv=0.0), dict(mu=-1.0), dict(storage=2, ref_rho=0.0, ref_T=0.2),
     dict(storage=0, eos=1), dict(ny=70000), dict(upwind_eps=-1.0), dict(zsegments=-1), dict(zsegments=9),
+    dict(check_every=-1),
 ])
 def test_invalid_parameters_rejected(over):
     from paper_2510_14712_amd import lbm
@@ -68,3 +69,6 @@ def test_null_handles_rejected():
     assert L.lbm_codec_encode(9, None, None, None, 10, None) == lbm.LBM_EINVAL
     assert L.lbm_codec_encode(2, None, None, None, 0, None) == lbm.LBM_OK
     assert lbm.strerror(-5) == "non-finite value in the state"
+    assert lbm.strerror(-4) == "state left the admissible set"
+    # the Adam step checks its arguments before any launch
+    assert L.lbm_mlp_adam(None, None, None, None, 1, ctypes.c_float(1e-3), None) == lbm.LBM_EINVAL

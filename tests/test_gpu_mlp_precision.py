@@ -88,6 +88,42 @@ def test_loss_grad_matches_oracle(precision, tol):
         assert np.abs(g[lo:hi]).max() > 0
 
 
+@pytest.mark.parametrize("t", [1, 7, 250])
+def test_adam_step_matches_oracle(t):
+    """One Adam update by the library's kernel (lbm_mlp_adam, the step the
+    GPU training uses) against oracle.mlp.adam from identical (params, grad,
+    m, v, t): new m and v to FP32 rounding, the parameter change to FP32
+    rounding of the update (bias corrections, square root and division in
+    FP32)."""
+    import torch
+    lbm = _lbm()
+    rng = np.random.default_rng(40 + t)
+    n = lbm.MLP_NPARAMS
+    P = rng.normal(size=n).astype(np.float32)
+    g = (rng.normal(size=n) * 10.0 ** rng.uniform(-6, 0, n)).astype(np.float32)
+    g[:5] = [0.0, 1e-30, -1e-30, 3.0, -3.0]
+    m = (rng.normal(size=n) * 1e-2).astype(np.float32)
+    v = (rng.uniform(0, 1e-3, n)).astype(np.float32)
+    lr = 3e-3
+    _say(f"case adam t={t}")
+    dP, dg, dm, dv = (torch.tensor(a, device="cuda") for a in (P, g, m, v))
+    lbm.mlp_adam(dP, dg, dm, dv, t, lr)
+    Pn, mn, vn = (a.cpu().numpy().astype(np.float64) for a in (dP, dm, dv))
+    Pr, mr, vr = om.adam(P.astype(np.float64), g.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
+                         t, lr)
+    # FP32 rounding relative to the magnitudes entering each sum (m may cancel)
+    mscale = 0.9 * np.abs(m.astype(np.float64)) + 0.1 * np.abs(g.astype(np.float64))
+    assert np.all(np.abs(mn - mr) <= 4e-7 * mscale + 1e-45)
+    assert np.all(np.abs(vn - vr) <= 4e-7 * np.abs(vr) + 1e-45)
+    step_ref = Pr - P.astype(np.float64)
+    err = np.abs((Pn - P) - step_ref)
+    # the update to a few FP32 roundings of its terms, plus half an ulp of
+    # the parameter it is added to
+    bound = 2e-6 * lr * (mscale / (1 - 0.9 ** t)) / (np.sqrt(vr / (1 - 0.999 ** t)) + 1e-8)
+    assert np.all(err <= bound + np.spacing(np.abs(P)).astype(np.float64))
+    assert np.abs(step_ref).max() > 1e-4  # the update is not negligible
+
+
 def _train(precision=0, n=131072, epochs=40, batch=4096, seed=4):
     lbm = _lbm()
     p0 = inputs.mlp_params(seed).astype(np.float32)

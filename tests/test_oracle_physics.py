@@ -224,3 +224,52 @@ def test_d3q27_z_uniform_equals_d2q9():
         sel = (c3[:, 0] == c2[i, 0]) & (c3[:, 1] == c2[i, 1])
         np.testing.assert_allclose(F3[sel].sum(0), f2.reshape(9, N2)[i], rtol=1e-11, atol=1e-14)
         np.testing.assert_allclose(G3[sel].sum(0), g2.reshape(9, N2)[i], rtol=1e-11, atol=1e-13)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("side", ["positive", "negative", "dead_zone"])
+def test_upwind_orientation_of_phi(axis, side):
+    """Phi_aa = -(1/rho) d_a Lambda_a with the difference biased by sgn(u_a)
+    (Section 3.2, the upwind formula after eq. correction): u_a > 0 takes
+    the backward difference Lambda(x) - Lambda(x - e_a), u_a < 0 the forward
+    difference Lambda(x + e_a) - Lambda(x), |u_a| inside the dead zone the
+    central average.  Uniform density and temperature (so F = 0 and theta
+    is uniform), u_a linear along the axis (a sine inside the dead zone):
+    Lambda_a = rho u^3 + 3 rho u (theta - 1/3) is then non-linear there, and
+    the three differences differ by far more than the tolerance.  Lambda is computed here from the imposed
+    u and the van der Waals theta, not taken from the oracle."""
+    n = 24
+    shape = [3, 3, 3]
+    shape[axis] = n
+    bc = [0, 0, 0]
+    bc[axis] = 1
+    p = oracle.Params(3, tuple(shape), bc=tuple(bc))
+    N = int(np.prod(shape))
+    coords = inputs.grid(tuple(shape))
+    s = coords[axis].astype(np.float64)
+    rho0, T0 = RHOC, 1.1 * TC
+    if side == "dead_zone":
+        ua = 7e-7 * np.sin(2 * np.pi * s / n)  # |u| < 1e-6, the dead zone
+    else:
+        ua = (0.05 + 0.01 * s) * (1.0 if side == "positive" else -1.0)
+    u = np.zeros(3 * N)
+    u[axis * N:(axis + 1) * N] = ua
+    f, g = oracle.init(p, np.full(N, rho0), u, np.full(N, T0))
+    _, _, fl = oracle.collide(p, f, g)
+    theta = th.pressure(rho0, T0, A, B, R) / rho0
+    lam = rho0 * ua ** 3 + 3.0 * rho0 * ua * (theta - 1.0 / 3.0)
+    phi = fl["Phi"][axis * N:(axis + 1) * N]
+    stride = [1, shape[0], shape[0] * shape[1]][axis]
+    inner = [c for c in range(N) if 0 < coords[axis][c] < n - 1]
+    back = np.array([lam[c] - lam[c - stride] for c in inner])
+    fwd = np.array([lam[c + stride] - lam[c] for c in inner])
+    expect = {"positive": back, "negative": fwd, "dead_zone": 0.5 * (back + fwd)}[side]
+    got = -phi[inner] * rho0
+    scale = np.abs(expect).max()
+    assert np.abs(got - expect).max() <= 1e-9 * scale + 1e-15  # + round-off of u from the moments
+    # the test can tell the orientations apart
+    assert np.abs(back - fwd).max() > 1e-2 * scale
+    # the other axes carry no correction (u is zero along them)
+    for b in range(3):
+        if b != axis:
+            assert np.abs(fl["Phi"][b * N:(b + 1) * N]).max() <= 1e-13

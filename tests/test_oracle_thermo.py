@@ -10,6 +10,9 @@
   nitrogen at T_r = 0.9 (Section 4.2.2: 399.8 / 102.71 kg/m^3);
 * Rankine-Hugoniot: the jump conditions hold, and the ideal-gas limit gives
   the textbook density ratio (gamma+1) M^2 / ((gamma-1) M^2 + 2);
+* the fundamental derivative (eq. Gamma): definition along the isentrope vs
+  the closed form of Section 4.3, the ideal-gas value (gamma + 1)/2, and the
+  signs the paper reports for its three shock-tube cases;
 * exact ideal-gas Riemann solver: the jump conditions across its shock and
   the isentropic invariants across its rarefaction; Sod's problem star state.
 """
@@ -149,3 +152,56 @@ def test_riemann_sod_star_state():
     p_s, u_s = th.riemann_star(1.0, 0.0, 1.0, 0.125, 0.0, 0.1, 1.4)
     assert p_s == pytest.approx(GOLD["sod_star_state"]["p_star"], abs=1e-5)
     assert u_s == pytest.approx(GOLD["sod_star_state"]["u_star"], abs=1e-5)
+
+
+def _isentrope_T(rho, rho0, T0, R, cv):
+    """T along the van der Waals isentrope through (rho0, T0):
+    T (1/rho - b)^(R/c_v) = const (from eq. ds_vdW)."""
+    return T0 * ((1.0 / rho0 - B) / (1.0 / rho - B)) ** (R / cv)
+
+
+@pytest.mark.parametrize("rho,T,cv", [(1.2, 0.2, 2.5), (3.0, 0.2, 80.0), (5.0, 0.25, 3.04)])
+def test_isentrope_is_adiabatic(rho, T, cv):
+    """The isentrope both Gamma routes follow satisfies de + P dv = 0 (first
+    law at ds = 0) with e = c_v T - a rho: a finite difference along it."""
+    h = 1e-5 * rho
+    e = lambda r: th.energy(r, _isentrope_T(r, rho, T, R, cv), A, cv)
+    de_dv = (e(rho + h) - e(rho - h)) / (1.0 / (rho + h) - 1.0 / (rho - h))
+    assert de_dv == pytest.approx(-th.pressure(rho, T, A, B, R), rel=1e-8)
+
+
+@pytest.mark.parametrize("gamma", [1.4, 1.0125, 1.329])
+def test_fundamental_derivative_ideal_gas(gamma):
+    """Ideal gas (a = b = 0): Gamma = (gamma + 1)/2 whatever the state, by
+    the definition (eq. Gamma, numerical derivative along the isentrope) and
+    by the closed form."""
+    cv = R / (gamma - 1.0)
+    for rho, T in ((0.5, 0.1), (2.0, 0.3)):
+        P = th.pressure(rho, T, 0.0, 0.0, R)
+        assert th.fundamental_derivative(rho, T, 0.0, 0.0, R, cv) == pytest.approx((gamma + 1) / 2, rel=1e-8)
+        assert th.fundamental_derivative_vdw(rho, P, 0.0, 0.0, R, cv) == pytest.approx((gamma + 1) / 2, rel=1e-14)
+
+
+@pytest.mark.parametrize("case", ["I", "II", "III"])
+def test_fundamental_derivative_shock_tube_states(case):
+    """Gamma of the paper's shock-tube initial states (Section 4.3.1): the
+    closed form (with the density factor its printed denominator lacks)
+    equals the definition evaluated along the isentrope, and has the sign
+    the paper reports: negative on both sides of case I, positive on both
+    sides of case II, above one on the left side of case III."""
+    g = GOLD["shock_tube_cases"][case]
+    cv = R / g["R_over_cv"]
+    rc, Tc, Pc = th.critical(A, B, R)
+    vals = []
+    for Pr, rr in (g["left"], g["right"]):
+        rho, P = rr * rc, Pr * Pc
+        T = (P + A * rho * rho) * (1.0 - B * rho) / (rho * R)  # eq. Pvdw solved for T
+        G = th.fundamental_derivative_vdw(rho, P, A, B, R, cv)
+        assert G == pytest.approx(th.fundamental_derivative(rho, T, A, B, R, cv), rel=1e-7, abs=1e-8)
+        vals.append(G)
+    if case == "I":
+        assert vals[0] < 0 and vals[1] < 0
+    elif case == "II":
+        assert vals[0] > 0 and vals[1] > 0
+    else:
+        assert vals[0] > 1
