@@ -41,7 +41,8 @@ class _Params(ctypes.Structure):
                 ("nz", ctypes.c_int), ("bc", ctypes.c_int * 3),
                 ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double),
                 ("cv", ctypes.c_double), ("mu", ctypes.c_double), ("eta", ctypes.c_double),
-                ("k", ctypes.c_double), ("kappa", ctypes.c_double), ("upwind_eps", ctypes.c_double)]
+                ("k", ctypes.c_double), ("kappa", ctypes.c_double), ("upwind_eps", ctypes.c_double),
+                ("sc_cmu", ctypes.c_double), ("sc_ceta", ctypes.c_double), ("sc_ck", ctypes.c_double)]
 
 
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -49,7 +50,7 @@ _DP = ctypes.POINTER(ctypes.c_double)
 
 class _Fields(ctypes.Structure):
     _fields_ = [(n, _DP) for n in ("rho", "u", "E", "T", "P", "theta", "h", "cs2",
-                                    "F", "Lambda", "lap", "Phi")]
+                                    "F", "Lambda", "lap", "Phi", "mu_num", "eta_num", "k_num")]
 
 
 _lib = None
@@ -115,7 +116,7 @@ class Params:
     """Lattice and physical parameters (lattice units)."""
 
     def __init__(self, D, shape, bc=(0, 0, 0), a=3.0 / 49.0, b=2.0 / 21.0, R=1.0, cv=2.5,
-                 mu=0.05, eta=0.05, k=None, kappa=0.01, upwind_eps=UPWIND_EPS):
+                 mu=0.05, eta=0.05, k=None, kappa=0.01, upwind_eps=UPWIND_EPS, sc=(0.0, 0.0, 0.0)):
         nx, ny = shape[0], shape[1]
         nz = shape[2] if D == 3 else 1
         self.D, self.nx, self.ny, self.nz = D, nx, ny, nz
@@ -125,6 +126,8 @@ class Params:
         self.k = mu * (cv + R) if k is None else k
         self.kappa = kappa
         self.upwind_eps = upwind_eps
+        # shock-capturing coefficients (C_mu, C_eta, C_k) of Section 4.4; zeros: off
+        self.sc = tuple(float(v) for v in sc)
 
     @property
     def N(self):
@@ -142,6 +145,7 @@ class Params:
         s.a, s.b, s.R, s.cv = self.a, self.b, self.R, self.cv
         s.mu, s.eta, s.k, s.kappa = self.mu, self.eta, self.k, self.kappa
         s.upwind_eps = self.upwind_eps
+        s.sc_cmu, s.sc_ceta, s.sc_ck = self.sc
         return s
 
 
@@ -162,7 +166,8 @@ def init(p: Params, rho, u, T):
 
 def _alloc_fields(p: Params):
     N, D = p.N, p.D
-    arrs = {n: np.zeros(N) for n in ("rho", "E", "T", "P", "theta", "h", "cs2", "lap")}
+    arrs = {n: np.zeros(N) for n in ("rho", "E", "T", "P", "theta", "h", "cs2", "lap", "mu_num", "eta_num",
+                                      "k_num")}
     for n in ("u", "F", "Lambda", "Phi"):
         arrs[n] = np.zeros(D * N)
     s = _Fields()
@@ -172,7 +177,8 @@ def _alloc_fields(p: Params):
 
 
 def fields(p: Params, f, g):
-    """Macroscopic fields of the state (rho, u, E, T, P, theta, h, cs2, F, ...)."""
+    """Macroscopic fields of the state (rho, u, E, T, P, theta, h, cs2, F, ...,
+    and the shock-capturing numerical transport mu_num, eta_num, k_num)."""
     arrs, s = _alloc_fields(p)
     rc = lib().oracle_fields_eval(ctypes.byref(p.c_struct()), _ptr(f), _ptr(g), ctypes.byref(s))
     if rc != 0:

@@ -207,7 +207,11 @@ static long nbr_axis(const oracle_params *p, long idx, int a, int s) {
 typedef struct {
     double *rho, *J, *G, *lap, *F, *u, *E, *T, *P, *theta, *e, *h, *cs2, *Lam;
     double *Phi; /* diagonal Galilean correction of each cell, set by the collision */
+    double *mu_num, *eta_num, *k_num; /* shock-capturing numerical transport */
+    double *sc_a, *sc_b;              /* scratch of the shock-capturing passes */
 } work_fields;
+
+static void shock_capturing(const oracle_params *p, work_fields *w);
 
 static void work_alloc(work_fields *w, long N, int D) {
     w->rho = calloc(N, sizeof(double));
@@ -225,12 +229,18 @@ static void work_alloc(work_fields *w, long N, int D) {
     w->cs2 = calloc(N, sizeof(double));
     w->Lam = calloc((size_t)D * N, sizeof(double));
     w->Phi = calloc((size_t)D * N, sizeof(double));
+    w->mu_num = calloc(N, sizeof(double));
+    w->eta_num = calloc(N, sizeof(double));
+    w->k_num = calloc(N, sizeof(double));
+    w->sc_a = calloc(N, sizeof(double));
+    w->sc_b = calloc(N, sizeof(double));
 }
 
 static void work_free(work_fields *w) {
     free(w->rho); free(w->J); free(w->G); free(w->lap); free(w->F); free(w->u);
     free(w->E); free(w->T); free(w->P); free(w->theta); free(w->e); free(w->h);
     free(w->cs2); free(w->Lam); free(w->Phi);
+    free(w->mu_num); free(w->eta_num); free(w->k_num); free(w->sc_a); free(w->sc_b);
 }
 
 static void compute_fields(const oracle_params *p, const double *f, const double *g,
@@ -298,6 +308,114 @@ static void compute_fields(const oracle_params *p, const double *f, const double
         w->E[x] = E; w->T[x] = T; w->P[x] = P; w->theta[x] = theta;
         w->e[x] = e; w->h[x] = h; w->cs2[x] = cs2;
     }
+
+    /* numerical transport of the shock-capturing scheme (zero when off) */
+    shock_capturing(p, w);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Shock-capturing numerical transport (Section 4.4, eqs. shock_cap and   */
+/* shock_cap_k): with r = 5 and dx = 1                                     */
+/*   {mu, eta}^num = rho C_{mu,eta} filt(|grad^4 S|),                      */
+/*   k^num         = rho c_s C_k   filt(|grad^4 |grad s||),                */
+/*   S = (1/2) sqrt((grad u + grad u^T) : (grad u + grad u^T)),            */
+/*   grad s = (c_v / T) grad T - R / (rho (1 - b rho)) grad rho            */
+/* (entropy gradient of van der Waals, from eq. ds_vdW).  Readings where   */
+/* the paper is silent: grad^4 phi = sum_a d^4 phi / dx_a^4 by the central */
+/* fourth difference along each axis; first derivatives central; the       */
+/* filter is a separable truncated Gaussian, weights exp(-j^2/(2 sigma^2)) */
+/* for |j| <= 4 with sigma = 1.2 cells, normalised to sum one, applied     */
+/* along x, then y, then z; c_s = sqrt(max(c_s^2, 0)).                     */
+/* ---------------------------------------------------------------------- */
+#define SC_FILTER_RADIUS 4
+#define SC_FILTER_SIGMA 1.2
+
+static int sc_enabled(const oracle_params *p) {
+    return p->sc_cmu != 0.0 || p->sc_ceta != 0.0 || p->sc_ck != 0.0;
+}
+
+/* |sum_a (phi(x+2e_a) - 4 phi(x+e_a) + 6 phi(x) - 4 phi(x-e_a) + phi(x-2e_a))| */
+static void abs_fourth_difference(const oracle_params *p, const double *phi, double *out) {
+    const long N = (long)p->nx * p->ny * p->nz;
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < N; x++) {
+        double s = 0.0;
+        for (int a = 0; a < p->D; a++) {
+            long p1 = nbr_axis(p, x, a, 1), p2 = nbr_axis(p, x, a, 2);
+            long m1 = nbr_axis(p, x, a, -1), m2 = nbr_axis(p, x, a, -2);
+            s += phi[p2] - 4.0 * phi[p1] + 6.0 * phi[x] - 4.0 * phi[m1] + phi[m2];
+        }
+        out[x] = fabs(s);
+    }
+}
+
+/* in place: phi <- Gaussian filter of phi along each axis in turn (tmp: scratch) */
+static void gaussian_filter(const oracle_params *p, double *phi, double *tmp) {
+    const long N = (long)p->nx * p->ny * p->nz;
+    double wts[2 * SC_FILTER_RADIUS + 1], wsum = 0.0;
+    for (int j = -SC_FILTER_RADIUS; j <= SC_FILTER_RADIUS; j++) {
+        wts[j + SC_FILTER_RADIUS] = exp(-(double)(j * j) / (2.0 * SC_FILTER_SIGMA * SC_FILTER_SIGMA));
+        wsum += wts[j + SC_FILTER_RADIUS];
+    }
+    for (int j = 0; j <= 2 * SC_FILTER_RADIUS; j++) wts[j] /= wsum;
+    for (int a = 0; a < p->D; a++) {
+#pragma omp parallel for schedule(static)
+        for (long x = 0; x < N; x++) {
+            double s = 0.0;
+            for (int j = -SC_FILTER_RADIUS; j <= SC_FILTER_RADIUS; j++)
+                s += wts[j + SC_FILTER_RADIUS] * phi[nbr_axis(p, x, a, j)];
+            tmp[x] = s;
+        }
+        memcpy(phi, tmp, (size_t)N * sizeof(double));
+    }
+}
+
+static void shock_capturing(const oracle_params *p, work_fields *w) {
+    const int D = p->D;
+    const long N = (long)p->nx * p->ny * p->nz;
+    if (!sc_enabled(p)) {
+        memset(w->mu_num, 0, (size_t)N * sizeof(double));
+        memset(w->eta_num, 0, (size_t)N * sizeof(double));
+        memset(w->k_num, 0, (size_t)N * sizeof(double));
+        return;
+    }
+    /* strain-rate magnitude S into sc_a */
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < N; x++) {
+        double G[3][3] = {{0}}; /* G[a][b] = d u_a / d x_b */
+        for (int b = 0; b < D; b++) {
+            long xp = nbr_axis(p, x, b, 1), xm = nbr_axis(p, x, b, -1);
+            for (int a = 0; a < D; a++) G[a][b] = 0.5 * (w->u[a * N + xp] - w->u[a * N + xm]);
+        }
+        double ss = 0.0;
+        for (int a = 0; a < D; a++)
+            for (int b = 0; b < D; b++) ss += (G[a][b] + G[b][a]) * (G[a][b] + G[b][a]);
+        w->sc_a[x] = 0.5 * sqrt(ss);
+    }
+    abs_fourth_difference(p, w->sc_a, w->mu_num);
+    gaussian_filter(p, w->mu_num, w->sc_b);
+    /* entropy-gradient magnitude |grad s| into sc_a */
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < N; x++) {
+        double rho = w->rho[x], T = w->T[x], g2 = 0.0;
+        for (int a = 0; a < D; a++) {
+            long xp = nbr_axis(p, x, a, 1), xm = nbr_axis(p, x, a, -1);
+            double dT = 0.5 * (w->T[xp] - w->T[xm]), dr = 0.5 * (w->rho[xp] - w->rho[xm]);
+            double ds = p->cv / T * dT - p->R / (rho * (1.0 - p->b * rho)) * dr;
+            g2 += ds * ds;
+        }
+        w->sc_a[x] = sqrt(g2);
+    }
+    abs_fourth_difference(p, w->sc_a, w->k_num);
+    gaussian_filter(p, w->k_num, w->sc_b);
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < N; x++) {
+        double rho = w->rho[x], fS = w->mu_num[x];
+        double cs = sqrt(w->cs2[x] > 0.0 ? w->cs2[x] : 0.0);
+        w->mu_num[x] = rho * p->sc_cmu * fS;
+        w->eta_num[x] = rho * p->sc_ceta * fS;
+        w->k_num[x] = rho * cs * p->sc_ck * w->k_num[x];
+    }
 }
 
 static void export_fields(const oracle_params *p, const work_fields *w, oracle_fields *out) {
@@ -308,6 +426,7 @@ static void export_fields(const oracle_params *p, const work_fields *w, oracle_f
     CP(rho, rho, N); CP(u, u, D * N); CP(E, E, N); CP(T, T, N); CP(P, P, N);
     CP(theta, theta, N); CP(h, h, N); CP(cs2, cs2, N); CP(F, F, D * N);
     CP(Lambda, Lam, D * N); CP(lap, lap, N); CP(Phi, Phi, D * N);
+    CP(mu_num, mu_num, N); CP(eta_num, eta_num, N); CP(k_num, k_num, N);
 #undef CP
 }
 
@@ -346,16 +465,19 @@ static void collide_all(const oracle_params *p, const double *f, const double *g
             w->Phi[a * N + x] = Phi[a];
         }
 
-        double tau = p->mu / P;                                         /* tau = mu / P */
+        /* transport coefficients with the numerical contributions (zero
+         * without shock capturing), Section 4.4 */
+        double mu = p->mu + w->mu_num[x], eta = p->eta + w->eta_num[x], kk = p->k + w->k_num[x];
+        double tau = mu / P;                                            /* tau = mu / P */
         double beta = 1.0 / (2.0 * tau + 1.0);                         /* eq. beta_main, dt = 1 */
-        double alpha = (double)(D + 2) / (double)D - rho * w->cs2[x] / P - p->eta / p->mu; /* eq. corr_bulk */
+        double alpha = (double)(D + 2) / (double)D - rho * w->cs2[x] / P - eta / mu; /* eq. corr_bulk */
 
         double us[3] = {0, 0, 0}, FF = 0.0;
         for (int a = 0; a < D; a++) { us[a] = u[a] + F[a] / rho; FF += F[a] * F[a]; } /* eq. sh_vel_1 */
         double thetas = theta + alpha * theta * divu;                  /* eq. sh_temp_1 */
         double Ts = T - FF / (2.0 * rho * rho * p->cv);                /* eq. sh_T_1 */
         double qc[3] = {0, 0, 0};
-        for (int a = 0; a < D; a++) qc[a] = P * (gh[a] - (p->k / p->mu) * gT[a]); /* eq. qc_1 */
+        for (int a = 0; a < D; a++) qc[a] = P * (gh[a] - (kk / mu) * gT[a]); /* eq. qc_1 */
 
         double e_eq = p->cv * T - p->a * rho;   /* caloric vdW EOS e(rho, T) (eq. de_vdW) */
         double e_st = p->cv * Ts - p->a * rho;  /* e(rho, T*) */

@@ -34,6 +34,9 @@ typedef struct {
     double kappa;       /* capillarity coefficient */
     double upwind_eps;  /* |u_a| <= upwind_eps takes the central average in the
                            upwind-biased derivative of Lambda (sgn(u) = 0) */
+    double sc_cmu, sc_ceta, sc_ck; /* coefficients C_mu, C_eta, C_k of the
+                           shock-capturing numerical transport (Section 4.4);
+                           all zero: off */
 } oracle_params;
 
 /* Per-cell fields produced while evaluating one step (all length N or D*N). */
@@ -41,6 +44,8 @@ typedef struct {
     double *rho, *u, *E, *T, *P, *theta, *h, *cs2, *F, *Lambda, *lap;
     double *Phi; /* Phi_aa = -(1/rho) d_a Lambda_a (upwind), D*N; filled by
                     oracle_collide only */
+    double *mu_num, *eta_num, *k_num; /* numerical transport of each cell
+                    (zero when shock capturing is off), N each */
 } oracle_fields;
 
 /* f = f^eq(rho, u, theta), g = g^eq(rho, u, T, theta), theta = P(rho,T)/rho. */
