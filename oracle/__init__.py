@@ -42,7 +42,9 @@ class _Params(ctypes.Structure):
                 ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double),
                 ("cv", ctypes.c_double), ("mu", ctypes.c_double), ("eta", ctypes.c_double),
                 ("k", ctypes.c_double), ("kappa", ctypes.c_double), ("upwind_eps", ctypes.c_double),
-                ("sc_cmu", ctypes.c_double), ("sc_ceta", ctypes.c_double), ("sc_ck", ctypes.c_double)]
+                ("sc_cmu", ctypes.c_double), ("sc_ceta", ctypes.c_double), ("sc_ck", ctypes.c_double),
+                ("eos", ctypes.c_int), ("pr_m", ctypes.c_double), ("pr_Tc", ctypes.c_double),
+                ("pr_c0", ctypes.c_double), ("pr_c1", ctypes.c_double)]
 
 
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -81,6 +83,10 @@ def lib():
             getattr(L, fn).restype = ctypes.c_int
         L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         L.oracle_set_num_threads.restype = None
+        L.oracle_eos.argtypes = [PP, ctypes.c_double, ctypes.c_double, _DP]
+        L.oracle_eos.restype = None
+        L.oracle_temperature.argtypes = [PP, ctypes.c_double, ctypes.c_double, _DP]
+        L.oracle_temperature.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -116,7 +122,7 @@ class Params:
     """Lattice and physical parameters (lattice units)."""
 
     def __init__(self, D, shape, bc=(0, 0, 0), a=3.0 / 49.0, b=2.0 / 21.0, R=1.0, cv=2.5,
-                 mu=0.05, eta=0.05, k=None, kappa=0.01, upwind_eps=UPWIND_EPS, sc=(0.0, 0.0, 0.0)):
+                 mu=0.05, eta=0.05, k=None, kappa=0.01, upwind_eps=UPWIND_EPS, sc=(0.0, 0.0, 0.0), pr=None):
         nx, ny = shape[0], shape[1]
         nz = shape[2] if D == 3 else 1
         self.D, self.nx, self.ny, self.nz = D, nx, ny, nz
@@ -128,6 +134,10 @@ class Params:
         self.upwind_eps = upwind_eps
         # shock-capturing coefficients (C_mu, C_eta, C_k) of Section 4.4; zeros: off
         self.sc = tuple(float(v) for v in sc)
+        # Peng-Robinson: dict(m, Tc, c0, c1) with a, b, R its constants; None: van der Waals
+        self.pr = dict(pr) if pr is not None else None
+        if self.pr is not None:
+            self.k = mu * (self.pr["c0"] + R) if k is None else k
 
     @property
     def N(self):
@@ -146,6 +156,9 @@ class Params:
         s.mu, s.eta, s.k, s.kappa = self.mu, self.eta, self.k, self.kappa
         s.upwind_eps = self.upwind_eps
         s.sc_cmu, s.sc_ceta, s.sc_ck = self.sc
+        if self.pr is not None:
+            s.eos = 1
+            s.pr_m, s.pr_Tc, s.pr_c0, s.pr_c1 = (float(self.pr[k]) for k in ("m", "Tc", "c0", "c1"))
         return s
 
 
@@ -237,6 +250,21 @@ def operator_moments(D, u, e, theta):
     uu = np.ascontiguousarray(u, dtype=np.float64)
     lib().oracle_operator_moments(D, _ptr(uu), float(e), float(theta), _ptr(out))
     return out[: 3 ** D]
+
+
+def eos(p: Params, rho: float, T: float) -> dict:
+    """The parameters' equation of state at (rho, T): P, e, c_v, c_s^2, (dP/dT)_rho."""
+    out = np.zeros(5)
+    lib().oracle_eos(ctypes.byref(p.c_struct()), float(rho), float(T), _ptr(out))
+    return dict(zip(("P", "e", "cv", "cs2", "dPdT"), out))
+
+
+def temperature(p: Params, rho: float, e: float):
+    """Caloric inversion T(rho, e) and the Newton iterations it took (0 when
+    explicit, -1 when not converged)."""
+    t = ctypes.c_double()
+    it = lib().oracle_temperature(ctypes.byref(p.c_struct()), float(rho), float(e), ctypes.byref(t))
+    return t.value, it
 
 
 def num_threads() -> int:

@@ -165,10 +165,91 @@ void oracle_geq(int D, double rho, const double *u, double e, double theta, doub
 }
 
 /* ---------------------------------------------------------------------- */
+/* Equation of state.  van der Waals (eq. Pvdw with the caloric relation of */
+/* eq. de_vdW, e = c_v T - a rho; its inversion is explicit, eq. lbm_temp), */
+/* or Peng-Robinson, the paper's example of an equation of state whose     */
+/* caloric relation must be inverted iteratively at every node (Section     */
+/* 3.2, after eq. lbm_temp), written from Peng & Robinson's published form: */
+/*   P = rho R T / (1 - b rho) - a alpha(T) rho^2 / (1 + 2 b rho - b^2 rho^2) */
+/*   alpha(T) = (1 + m (1 - s))^2,  s = sqrt(T / Tc),                       */
+/* with a temperature-dependent ideal-gas heat capacity c_v0 = c0 + c1 T.   */
+/* The energy follows from the thermodynamic identity                      */
+/*   (de/drho)_T = (P - T (dP/dT)_rho) / rho^2                              */
+/* integrated from the dilute limit:                                        */
+/*   e = c0 T + c1 T^2 / 2 - a (alpha - T alpha') L(rho),                   */
+/*   alpha - T alpha' = (1 + m)(1 + m (1 - s)),                             */
+/*   L(rho) = ln[(1 + (1 + sqrt2) b rho) / (1 + (1 - sqrt2) b rho)] / (2 sqrt2 b), */
+/* quartic in s, hence Newton's method.  The adiabatic sound speed is the   */
+/* general identity c_s^2 = (dP/drho)_T + T (dP/dT)_rho^2 / (rho^2 c_v)     */
+/* (eq. speed_of_sound).                                                    */
+/* ---------------------------------------------------------------------- */
+static double pr_L(double b, double rho) {
+    const double r2 = sqrt(2.0);
+    return log((1.0 + (1.0 + r2) * b * rho) / (1.0 + (1.0 - r2) * b * rho)) / (2.0 * r2 * b);
+}
+
+void oracle_eos(const oracle_params *p, double rho, double T, double *out) {
+    if (p->eos == 0) {
+        double omb = 1.0 - p->b * rho;
+        out[0] = rho * p->R * T / omb - p->a * rho * rho;                        /* eq. Pvdw */
+        out[1] = p->cv * T - p->a * rho;                                          /* eq. de_vdW */
+        out[2] = p->cv;
+        out[3] = p->R * T * (1.0 + p->R / p->cv) / (omb * omb) - 2.0 * p->a * rho; /* eq. vdW_speed_of_sound */
+        out[4] = rho * p->R / omb;
+        return;
+    }
+    const double a = p->a, b = p->b, R = p->R, m = p->pr_m;
+    const double s = sqrt(T / p->pr_Tc);
+    const double k = 1.0 + m * (1.0 - s);
+    const double alpha = k * k;
+    const double dalpha = -m * k / sqrt(T * p->pr_Tc);          /* d alpha / dT */
+    const double d2alpha = 0.5 * m * (1.0 + m) / (T * sqrt(T * p->pr_Tc)); /* d^2 alpha / dT^2 */
+    const double den = 1.0 + 2.0 * b * rho - b * b * rho * rho;
+    const double omb = 1.0 - b * rho;
+    const double L = pr_L(b, rho);
+    out[0] = rho * R * T / omb - a * alpha * rho * rho / den;
+    out[1] = p->pr_c0 * T + 0.5 * p->pr_c1 * T * T - a * (1.0 + m) * k * L;
+    out[2] = p->pr_c0 + p->pr_c1 * T + a * T * d2alpha * L;     /* c_v0 + a T alpha'' L */
+    out[4] = rho * R / omb - a * dalpha * rho * rho / den;
+    const double dPdrho = R * T / (omb * omb) - a * alpha * (2.0 * rho * den - rho * rho * (2.0 * b - 2.0 * b * b * rho)) / (den * den);
+    out[3] = dPdrho + T * out[4] * out[4] / (rho * rho * out[2]);
+}
+
+int oracle_temperature(const oracle_params *p, double rho, double e, double *T) {
+    if (p->eos == 0) {
+        *T = (e + p->a * rho) / p->cv;                               /* eq. lbm_temp */
+        return 0;
+    }
+    /* Newton's method on e(rho, T) - e = 0 from the dilute (ideal-gas)
+     * estimate c0 T = e, kept positive by halving a step that would not be */
+    double t = e / p->pr_c0;
+    if (!(t > 1e-3 * p->pr_Tc)) t = p->pr_Tc;
+    double q[5];
+    for (int it = 1; it <= 100; it++) {
+        oracle_eos(p, rho, t, q);
+        double dt = (q[1] - e) / q[2];
+        double tn = t - dt;
+        while (!(tn > 0.0)) {
+            dt *= 0.5;
+            tn = t - dt;
+        }
+        t = tn;
+        if (fabs(dt) <= 1e-15 * t) {
+            *T = t;
+            return it;
+        }
+    }
+    *T = t;
+    return -1;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Grid helpers                                                            */
 /* ---------------------------------------------------------------------- */
 static int check_params(const oracle_params *p) {
     if (!p) return -1;
+    if (p->eos != 0 && p->eos != 1) return -1;
+    if (p->eos == 1 && !(p->pr_Tc > 0 && p->pr_c0 > 0)) return -1;
     if (p->D != 2 && p->D != 3) return -1;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return -1;
     if (p->D == 2 && p->nz != 1) return -1;
@@ -209,6 +290,7 @@ typedef struct {
     double *Phi; /* diagonal Galilean correction of each cell, set by the collision */
     double *mu_num, *eta_num, *k_num; /* shock-capturing numerical transport */
     double *sc_a, *sc_b;              /* scratch of the shock-capturing passes */
+    double *cv, *dPdT;                /* c_v and (dP/dT)_rho of each cell */
 } work_fields;
 
 static void shock_capturing(const oracle_params *p, work_fields *w);
@@ -234,6 +316,8 @@ static void work_alloc(work_fields *w, long N, int D) {
     w->k_num = calloc(N, sizeof(double));
     w->sc_a = calloc(N, sizeof(double));
     w->sc_b = calloc(N, sizeof(double));
+    w->cv = calloc(N, sizeof(double));
+    w->dPdT = calloc(N, sizeof(double));
 }
 
 static void work_free(work_fields *w) {
@@ -241,6 +325,7 @@ static void work_free(work_fields *w) {
     free(w->E); free(w->T); free(w->P); free(w->theta); free(w->e); free(w->h);
     free(w->cs2); free(w->Lam); free(w->Phi);
     free(w->mu_num); free(w->eta_num); free(w->k_num); free(w->sc_a); free(w->sc_b);
+    free(w->cv); free(w->dPdT);
 }
 
 static void compute_fields(const oracle_params *p, const double *f, const double *g,
@@ -293,13 +378,16 @@ static void compute_fields(const oracle_params *p, const double *f, const double
             u2 += u[a] * u[a];
         }
         double E = (w->G[x] + 0.5 * uF) / rho;                  /* eq. def_E */
-        double T = (E - 0.5 * u2 + p->a * rho) / p->cv;         /* eq. lbm_temp */
-        double P = rho * p->R * T / (1.0 - p->b * rho) - p->a * rho * rho; /* eq. Pvdw */
-        double theta = P / rho;                                 /* eq. theta */
         double e = E - 0.5 * u2;                                /* eq. rhoE */
+        double T, q[5];
+        oracle_temperature(p, rho, e, &T);                      /* eq. lbm_temp, or Newton */
+        oracle_eos(p, rho, T, q);
+        double P = q[0];                                        /* eq. Pvdw (or Peng-Robinson) */
+        double theta = P / rho;                                 /* eq. theta */
         double h = e + P / rho;                                 /* eq. enthalpy */
-        double omb = 1.0 - p->b * rho;
-        double cs2 = p->R * T * (1.0 + p->R / p->cv) / (omb * omb) - 2.0 * p->a * rho; /* eq. vdW_speed_of_sound */
+        double cs2 = q[3];
+        w->cv[x] = q[2];
+        w->dPdT[x] = q[4];
         for (int a = 0; a < D; a++) {
             w->u[a * N + x] = u[a];
             /* Lambda_a = rho u_a^3 + 3 rho u_a (theta - varsigma^2) */
@@ -401,7 +489,10 @@ static void shock_capturing(const oracle_params *p, work_fields *w) {
         for (int a = 0; a < D; a++) {
             long xp = nbr_axis(p, x, a, 1), xm = nbr_axis(p, x, a, -1);
             double dT = 0.5 * (w->T[xp] - w->T[xm]), dr = 0.5 * (w->rho[xp] - w->rho[xm]);
-            double ds = p->cv / T * dT - p->R / (rho * (1.0 - p->b * rho)) * dr;
+            /* ds = (c_v / T) dT - (dP/dT)_rho / rho^2 drho; van der Waals:
+             * (dP/dT)_rho / rho^2 = R / (rho (1 - b rho)) */
+            double ds = p->eos == 0 ? p->cv / T * dT - p->R / (rho * (1.0 - p->b * rho)) * dr
+                                    : w->cv[x] / T * dT - w->dPdT[x] / (rho * rho) * dr;
             g2 += ds * ds;
         }
         w->sc_a[x] = sqrt(g2);
@@ -475,12 +566,25 @@ static void collide_all(const oracle_params *p, const double *f, const double *g
         double us[3] = {0, 0, 0}, FF = 0.0;
         for (int a = 0; a < D; a++) { us[a] = u[a] + F[a] / rho; FF += F[a] * F[a]; } /* eq. sh_vel_1 */
         double thetas = theta + alpha * theta * divu;                  /* eq. sh_temp_1 */
-        double Ts = T - FF / (2.0 * rho * rho * p->cv);                /* eq. sh_T_1 */
+        double Ts = T - FF / (2.0 * rho * rho * w->cv[x]);             /* eq. sh_T_1 */
         double qc[3] = {0, 0, 0};
         for (int a = 0; a < D; a++) qc[a] = P * (gh[a] - (kk / mu) * gT[a]); /* eq. qc_1 */
 
-        double e_eq = p->cv * T - p->a * rho;   /* caloric vdW EOS e(rho, T) (eq. de_vdW) */
-        double e_st = p->cv * Ts - p->a * rho;  /* e(rho, T*) */
+        double q[5];
+        oracle_eos(p, rho, T, q);
+        double e_eq = q[1];                     /* caloric EOS e(rho, T) (eq. de_vdW) */
+        /* e(rho, T*): van der Waals by its caloric relation at T*; for an
+         * energy non-linear in T the value the shift stands for,
+         * e - |F|^2 / (2 rho^2) (equal to e(rho, T*) to O(|F|^4), and exact
+         * for van der Waals), so that the collision changes sum_i g_i by
+         * exactly u . F */
+        double e_st;
+        if (p->eos == 0) {
+            oracle_eos(p, rho, Ts, q);
+            e_st = q[1];
+        } else {
+            e_st = e_eq - FF / (2.0 * rho * rho);
+        }
 
         double feq[27], fst[27], geq[27], gst[27];
         oracle_feq(D, rho, u, theta, feq);
@@ -521,11 +625,12 @@ int oracle_init(const oracle_params *p, const double *rho, const double *u,
     const long N = (long)p->nx * p->ny * p->nz;
 #pragma omp parallel for schedule(static)
     for (long x = 0; x < N; x++) {
-        double r = rho[x], t = T[x], uu[3] = {0, 0, 0};
+        double r = rho[x], t = T[x], uu[3] = {0, 0, 0}, q[5];
         for (int a = 0; a < D; a++) uu[a] = u[a * N + x];
-        double P = r * p->R * t / (1.0 - p->b * r) - p->a * r * r;
+        oracle_eos(p, r, t, q);
+        double P = q[0];
         double theta = P / r;
-        double e = p->cv * t - p->a * r;
+        double e = q[1];
         double feq[27], geq[27];
         oracle_feq(D, r, uu, theta, feq);
         oracle_geq(D, r, uu, e, theta, geq);

@@ -37,6 +37,10 @@ typedef struct {
     double sc_cmu, sc_ceta, sc_ck; /* coefficients C_mu, C_eta, C_k of the
                            shock-capturing numerical transport (Section 4.4);
                            all zero: off */
+    int eos;            /* 0: van der Waals (a, b, R, cv); 1: Peng-Robinson
+                           with a, b, R and the fields below (cv unused) */
+    double pr_m, pr_Tc; /* Peng-Robinson alpha(T) = (1 + m (1 - sqrt(T/Tc)))^2 */
+    double pr_c0, pr_c1; /* ideal-gas heat capacity c_v0(T) = c0 + c1 T */
 } oracle_params;
 
 /* Per-cell fields produced while evaluating one step (all length N or D*N). */
@@ -67,6 +71,15 @@ int oracle_stream(const oracle_params *p, const double *fpost,
 
 /* n full steps (collide + stream) in place on f, g. */
 int oracle_run(const oracle_params *p, double *f, double *g, int nsteps);
+
+/* Equation of state of the parameters at (rho, T): out[0] P, out[1] e,
+ * out[2] c_v = (de/dT)_rho, out[3] c_s^2, out[4] (dP/dT)_rho. */
+void oracle_eos(const oracle_params *p, double rho, double T, double *out);
+/* Caloric inversion: T with e(rho, T) = e (explicit for van der Waals,
+ * Newton iterations to convergence for Peng-Robinson).  Returns the number
+ * of Newton iterations taken (0 for the explicit inversion), or -1 when the
+ * iteration failed to converge. */
+int oracle_temperature(const oracle_params *p, double rho, double e, double *T);
 
 /* Equilibria of a single state (for moment tests). feq, geq: Q values.
  * e is the specific internal energy e(rho, T). */

@@ -63,6 +63,20 @@ def build():
                              rho0=rc, T0=Ttgv, U0=0.5 * cs, cs=cs, noise=0.01, seed=5,
                              mu=2 * MU, eta=2 * ETA, k=2 * MU * (CV + R),
                              mlp_box=dict(rho=[0.05 * rc, 2.5 * rc], T=[0.8 * Tc, 1.5 * Tc]))
+    # Peng-Robinson fluid for the iterative caloric inversion (Section 3.2,
+    # after eq. lbm_temp): Peng & Robinson's published coefficients
+    # a = 0.45724 R^2 Tc^2 / Pc, b = 0.07780 R Tc / Pc and
+    # m = 0.37464 + 1.54226 omega - 0.26992 omega^2, here with the van der
+    # Waals fluid's T_c, P_c = Z_c rho_c R T_c at Z_c = 0.3074 and rho_c = 3.5
+    # (so both fluids share the critical state), acentric factor omega = 0.2,
+    # and a temperature-dependent ideal-gas heat capacity c_v0 = c0 + c1 T
+    # with c0 = 2.0, c1 = 5.0 (readings: the paper names the equation of state
+    # only).
+    om = 0.2
+    Pc_pr = 0.3074 * rc * R * Tc
+    out["peng_robinson"] = dict(a=0.45724 * R * R * Tc * Tc / Pc_pr, b=0.07780 * R * Tc / Pc_pr, R=R,
+                                m=0.37464 + 1.54226 * om - 0.26992 * om * om, Tc=Tc, Pc=Pc_pr, rho_c=rc,
+                                c0=2.0, c1=5.0, omega=om, Zc=0.3074)
     return out
 
 
