@@ -67,6 +67,20 @@ extern "C" {
 #define LBM_EOS_VDW 0       /* explicit van der Waals caloric inversion, eq. lbm_temp */
 #define LBM_EOS_MLP 1       /* learned surrogate (rho, e) -> (T, P, c_s^2) with a
                                per-cell residual check and exact Newton fallback */
+/* Peng-Robinson (the paper's example of an equation of state whose caloric
+ * relation needs an iterative inversion, Section 3.2 after eq. lbm_temp):
+ *   P = rho R T / (1 - b rho) - a alpha(T) rho^2 / (1 + 2 b rho - b^2 rho^2),
+ *   alpha(T) = (1 + m (1 - sqrt(T / Tc)))^2,
+ *   e = c0 T + c1 T^2 / 2 - a (1 + m)(1 + m (1 - sqrt(T / Tc))) L(rho),
+ *   L = ln[(1 + (1 + sqrt2) b rho) / (1 + (1 - sqrt2) b rho)] / (2 sqrt2 b),
+ * with a, b, R of lbm_params and m, Tc, c0, c1 its pr_* fields (cv unused);
+ * T recovered per cell by FP64 Newton iterations to convergence.  These modes
+ * take the multi-kernel path. */
+#define LBM_EOS_PR 2        /* Newton from the dilute estimate e / c0 */
+#define LBM_EOS_PR_PREV 3   /* Newton from the cell's temperature of the previous step */
+#define LBM_EOS_PR_MLP 4    /* the surrogate's T, accepted when its caloric residual
+                               |e(rho, T_hat) - e| / (c_v T_hat) <= mlp_tol, else
+                               Newton from T_hat (not with FP64 storage) */
 
 /* ---- parameters --------------------------------------------------------- */
 typedef struct {
@@ -98,6 +112,20 @@ typedef struct {
                                check_every steps (non-finite cells, then the
                                admissible set of LBM_EUNSTABLE) and returns at
                                the first failing check; 0: no checks */
+    double pr_m, pr_Tc, pr_c0, pr_c1; /* Peng-Robinson modes: alpha(T) slope m,
+                               critical temperature, ideal-gas heat capacity
+                               c_v0 = c0 + c1 T */
+    double sc_cmu, sc_ceta, sc_ck; /* shock-capturing numerical transport
+                               (Section 4.4, eqs. shock_cap, shock_cap_k, r = 5):
+                               mu, eta, k of each cell gain rho C_mu fS,
+                               rho C_eta fS and rho c_s C_k fs, with fS, fs the
+                               Gaussian-filtered (radius 4, sigma 1.2 cells)
+                               |sum_a d^4/dx_a^4| of the strain-rate magnitude
+                               S = |grad u + grad u^T| / 2 and of the entropy
+                               gradient magnitude |grad s|.  All zero: off.
+                               Non-zero coefficients take the multi-kernel
+                               path (the extra passes need the fields of every
+                               cell through HBM). */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx; /* opaque, library-owned */
@@ -235,6 +263,13 @@ int lbm_mlp_set(lbm_ctx *ctx, const float *host_params, const float *host_norm);
 /* Fraction of cell evaluations since the last call that failed the residual
  * check and took the Newton fallback (blocking; resets the counters). */
 int lbm_mlp_stats(lbm_ctx *ctx, double *host_fallback_fraction);
+
+/* Statistics of the equation-of-state stage of the steps since the last call
+ * (blocking; resets the counters): the fraction of surrogate evaluations
+ * that failed the residual check (0 without the surrogate) and the mean
+ * number of Peng-Robinson Newton iterations per cell update (0 for van der
+ * Waals).  Either pointer may be NULL. */
+int lbm_eos_stats(lbm_ctx *ctx, double *host_fallback_fraction, double *host_mean_newton_iterations);
 
 /* Stand-alone surrogate forward pass: dev_x[2*B] raw (rho, e) pairs,
  * dev_y[3*B] de-normalised (T, P, c_s^2); dev_params[4547], dev_norm[10];

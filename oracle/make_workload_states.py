@@ -63,6 +63,24 @@ def build():
                              rho0=rc, T0=Ttgv, U0=0.5 * cs, cs=cs, noise=0.01, seed=5,
                              mu=2 * MU, eta=2 * ETA, k=2 * MU * (CV + R),
                              mlp_box=dict(rho=[0.05 * rc, 2.5 * rc], T=[0.8 * Tc, 1.5 * Tc]))
+    # The paper's non-ideal shock tubes I-III (Section 4.3.1, its table of
+    # cases): reduced states (P_r, rho_r) left / right of the mid-point and
+    # R / c_v per case, on this van der Waals fluid in lattice units; 1000
+    # cells along x (zero-gradient ends) as the paper's dx = L_x / 1000; run to
+    # the times of its figures, t = t_r L_x sqrt(rho_c / P_c) with t_r = 0.45,
+    # 0.2, 0.15 (readings: transport mu = eta = 0.05, k = mu (c_v + R),
+    # kappa = 0.01 in lattice units; the paper's own are not given).
+    cases = {"I": (0.0125, (1.09, 0.879), (0.885, 0.562), 0.45), "II": (0.329, (1.6077, 1.01), (0.8957, 0.594), 0.2),
+             "III": (0.0125, (3.00, 1.818), (0.575, 0.275), 0.15)}
+    for name, (rcv, (PLr, rLr), (PRr, rRr), tr) in cases.items():
+        rl, rr = rLr * rc, rRr * rc
+        TL = (PLr * Pc + A * rl * rl) * (1.0 - B * rl) / (rl * R)  # eq. Pvdw solved for T
+        TR = (PRr * Pc + A * rr * rr) * (1.0 - B * rr) / (rr * R)
+        cvc = R / rcv
+        out["shock_tube_" + name] = dict(lattice=2, shape=[1000, 4], bc=[1, 0, 0], R_over_cv=rcv, cv=cvc,
+                                         rho_left=rl, T_left=TL, rho_right=rr, T_right=TR, t_reduced=tr,
+                                         steps=int(round(tr * 1000 * math.sqrt(rc / Pc))), mu=MU, eta=ETA,
+                                         k=MU * (cvc + R))
     # Peng-Robinson fluid for the iterative caloric inversion (Section 3.2,
     # after eq. lbm_temp): Peng & Robinson's published coefficients
     # a = 0.45724 R^2 Tc^2 / Pc, b = 0.07780 R Tc / Pc and

@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(RED_BLOCK) k_check_inputs(long long N, Phys<do
         }
         acc[5] += bad ? 1.0 : 0.0;
         if (!bad) {
-            const double P = vdw_pressure(ph, r, t);
+            const double P = ph.pr ? pr_eos(ph, r, t).P : vdw_pressure(ph, r, t);
             acc[6] += admissible<D>(r, P / r, uu, ph.b) ? 0.0 : 1.0;
         }
     }
@@ -196,6 +196,14 @@ template <class C> static Phys<C> make_phys(const lbm_params &p) {
     ph.k_over_mu = (C)(p.k / p.mu);
     ph.eta_over_mu = (C)(p.eta / p.mu);
     ph.sgn_eps = (C)p.upwind_eps;
+    ph.sc_cmu = (C)p.sc_cmu;
+    ph.sc_ceta = (C)p.sc_ceta;
+    ph.sc_ck = (C)p.sc_ck;
+    ph.pr = lbm_eos_is_pr(p.eos) ? 1 : 0;
+    ph.pr_m = p.pr_m;
+    ph.pr_Tc = p.pr_Tc;
+    ph.pr_c0 = p.pr_c0;
+    ph.pr_c1 = p.pr_c1;
     return ph;
 }
 
@@ -245,6 +253,7 @@ using TileOf = typename std::conditional<std::is_same<S, StoreF64>::value, Tile<
 template <int D, class S> struct Impl {
     using C = typename S::C;
     using T = typename S::T;
+    // the fused step's surrogate form (van der Waals with the network)
     static bool mlp(const lbm_ctx *c) { return std::is_same<C, float>::value && c->p.eos == LBM_EOS_MLP; }
 
     // complete moments of the current state into the side channel; inbound
@@ -383,19 +392,49 @@ template <int D, class S> struct Impl {
         int rc = last_launch();
         return rc ? rc : fused_prepare(c);
     }
-    static int fields_pass(lbm_ctx *c) {
+    // count: add the Peng-Robinson Newton iterations to the context's
+    // counters (the step's passes; read-back passes do not count)
+    static int fields_pass(lbm_ctx *c, bool count = false) {
         Fields<C> fl = get_fields<C>(c);
         dim3 gr = cell_grid(c);
         hipLaunchKernelGGL((k_moments<D, S>), gr, dim3(BX), 0, c->stream, c->grid, c->ref, (const T *)c->f[c->cur],
                            (const T *)c->g[c->cur], fl, c->pulled);
         hipLaunchKernelGGL((k_lap<D, C>), gr, dim3(BX), 0, c->stream, c->grid, fl);
-        if (c->p.eos == LBM_EOS_MLP) {
-            int rc = launch_fields_mlp<D, C>(c, fl);
+        if (lbm_eos_uses_mlp(c->p.eos)) {
+            int rc = launch_fields_mlp<D, C>(c, fl, count);
             if (rc) return rc;
         } else {
-            hipLaunchKernelGGL((k_fields<D, C>), gr, dim3(BX), 0, c->stream, c->grid, make_phys<C>(c->p), fl);
+            hipLaunchKernelGGL((k_fields<D, C>), gr, dim3(BX), 0, c->stream, c->grid, make_phys<C>(c->p), fl,
+                               (c->p.eos == LBM_EOS_PR_PREV && c->T_valid) ? 1 : 0,
+                               count ? c->mlp_counters + 2 : (unsigned long long *)nullptr);
         }
+        c->T_valid = true;
         return last_launch();
+    }
+    // shock-capturing passes over the fields of the step; returns the filtered
+    // (|grad^4 S|, |grad^4 |grad s||) arrays, or nulls when the scheme is off
+    static void sc_passes(lbm_ctx *c, const C **fS, const C **fs) {
+        *fS = *fs = nullptr;
+        if (!c->sc) return;
+        Fields<C> fl = get_fields<C>(c);
+        dim3 gr = cell_grid(c);
+        hipLaunchKernelGGL((k_sc_grad<D, C>), gr, dim3(BX), 0, c->stream, c->grid, make_phys<C>(c->p), fl);
+        hipLaunchKernelGGL((k_sc_d4<D, C>), gr, dim3(BX), 0, c->stream, c->grid, fl.sc[0], fl.sc[1], fl.sc[2],
+                           fl.sc[3]);
+        // filter weights exp(-j^2 / (2 sigma^2)), |j| <= 4, sigma = 1.2, normalised
+        ScFilter<C> f;
+        double w[2 * SC_RADIUS + 1], ws = 0;
+        for (int j = -SC_RADIUS; j <= SC_RADIUS; j++) ws += (w[j + SC_RADIUS] = std::exp(-(double)(j * j) / 2.88));
+        for (int j = 0; j <= 2 * SC_RADIUS; j++) f.w[j] = (C)(w[j] / ws);
+        int src = 2;
+        for (int a = 0; a < D; a++) {
+            const int dst = 2 - src;
+            hipLaunchKernelGGL((k_sc_filter<D, C>), gr, dim3(BX), 0, c->stream, c->grid, a, f, fl.sc[src],
+                               fl.sc[src + 1], fl.sc[dst], fl.sc[dst + 1]);
+            src = dst;
+        }
+        *fS = fl.sc[src];
+        *fs = fl.sc[src + 1];
     }
     static int step(lbm_ctx *c, int n) {
         Fields<C> fl = get_fields<C>(c);
@@ -406,12 +445,14 @@ template <int D, class S> struct Impl {
                 fused_launch(c);
                 rc = last_launch();
             } else {
-                rc = fields_pass(c);
+                rc = fields_pass(c, true);
                 if (rc) return rc;
+                const C *fS, *fs;
+                sc_passes(c, &fS, &fs);
                 int nxt = 1 - c->cur;
                 hipLaunchKernelGGL((k_collide<D, S>), gr, dim3(BX), 0, c->stream, c->grid, make_phys<C>(c->p), c->ref,
                                    (const T *)c->f[c->cur], (const T *)c->g[c->cur], fl, (T *)c->f[nxt],
-                                   (T *)c->g[nxt]);
+                                   (T *)c->g[nxt], fS, fs);
                 rc = last_launch();
                 c->cur = nxt;
             }
@@ -469,12 +510,18 @@ template <int D, class S> struct Impl {
             (void)hipEventRecord(ev[1], c->stream);
             hipLaunchKernelGGL((k_lap<D, C>), gr, dim3(BX), 0, c->stream, c->grid, fl);
             (void)hipEventRecord(ev[2], c->stream);
-            if (c->p.eos == LBM_EOS_MLP) rc = launch_fields_mlp<D, C>(c, fl);
-            else hipLaunchKernelGGL((k_fields<D, C>), gr, dim3(BX), 0, c->stream, c->grid, make_phys<C>(c->p), fl);
+            if (lbm_eos_uses_mlp(c->p.eos)) rc = launch_fields_mlp<D, C>(c, fl, true);
+            else
+                hipLaunchKernelGGL((k_fields<D, C>), gr, dim3(BX), 0, c->stream, c->grid, make_phys<C>(c->p), fl,
+                                   (c->p.eos == LBM_EOS_PR_PREV && c->T_valid) ? 1 : 0, c->mlp_counters + 2);
+            c->T_valid = true;
+            const C *fS, *fs;
+            sc_passes(c, &fS, &fs);  // timed with the fields kind
             (void)hipEventRecord(ev[3], c->stream);
             int nxt = 1 - c->cur;
             hipLaunchKernelGGL((k_collide<D, S>), gr, dim3(BX), 0, c->stream, c->grid, make_phys<C>(c->p), c->ref,
-                               (const T *)c->f[c->cur], (const T *)c->g[c->cur], fl, (T *)c->f[nxt], (T *)c->g[nxt]);
+                               (const T *)c->f[c->cur], (const T *)c->g[c->cur], fl, (T *)c->f[nxt], (T *)c->g[nxt],
+                               fS, fs);
             (void)hipEventRecord(ev[4], c->stream);
             if (rc == LBM_OK) rc = last_launch();
             c->cur = nxt;
@@ -638,12 +685,18 @@ static int validate(const lbm_params *p) {
     for (int a = 0; a < 3; a++)
         if (p->bc[a] != LBM_BC_PERIODIC && p->bc[a] != LBM_BC_ZEROGRAD) return LBM_EINVAL;
     if (p->storage < LBM_STORE_F64 || p->storage > LBM_STORE_F16) return LBM_EINVAL;
-    if (p->eos != LBM_EOS_VDW && p->eos != LBM_EOS_MLP) return LBM_EINVAL;
-    if (p->eos == LBM_EOS_MLP && p->storage == LBM_STORE_F64) return LBM_EINVAL;
+    if (p->eos < LBM_EOS_VDW || p->eos > LBM_EOS_PR_MLP) return LBM_EINVAL;
+    if (lbm_eos_uses_mlp(p->eos) && p->storage == LBM_STORE_F64) return LBM_EINVAL;
+    if (lbm_eos_is_pr(p->eos) && !(p->pr_Tc > 0 && p->pr_c0 > 0 && p->pr_c1 >= 0 && std::isfinite(p->pr_m) &&
+                                   p->b > 0 && p->a >= 0))
+        return LBM_EINVAL;
     if (!(p->cv > 0) || !(p->mu > 0) || !(p->R > 0)) return LBM_EINVAL;
     if (!(p->upwind_eps >= 0)) return LBM_EINVAL;
     if (p->zsegments < 0 || p->zsegments > p->nz) return LBM_EINVAL;
     if (p->check_every < 0) return LBM_EINVAL;
+    if (!(p->sc_cmu >= 0 && p->sc_ceta >= 0 && p->sc_ck >= 0) || !std::isfinite(p->sc_cmu) ||
+        !std::isfinite(p->sc_ceta) || !std::isfinite(p->sc_ck))
+        return LBM_EINVAL;
     if ((long long)p->nx * p->ny > (1LL << 30)) return LBM_EINVAL;
     if ((p->storage == LBM_STORE_BF16 || p->storage == LBM_STORE_F16) && !(p->ref_rho > 0 && p->ref_T > 0))
         return LBM_EINVAL;
@@ -671,8 +724,10 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
     int cb = params->storage == LBM_STORE_F64 ? 8 : 4;
     make_ref(*params, c->D, c->ref);
     size_t pop_bytes = (size_t)c->Q * N * sb;
-    // field arrays: rho, J[D], G, lap, u[D], F[D], Lam[D], T, P, h, cs2
-    size_t nfield = (size_t)(8 + 4 * c->D);
+    // field arrays: rho, J[D], G, lap, u[D], F[D], Lam[D], T, P, h, cs2, and
+    // the four shock-capturing work arrays when that scheme is on
+    c->sc = params->sc_cmu > 0 || params->sc_ceta > 0 || params->sc_ck > 0;
+    size_t nfield = (size_t)(8 + 4 * c->D + (c->sc ? 4 : 0));
     size_t field_bytes = nfield * N * cb;
     c->red_blocks = 1024;
     // one buffer per ping-pong slot holds both sets, f_i and g_i side by side
@@ -681,7 +736,7 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
               hipMalloc(&c->work, field_bytes) == hipSuccess &&
               hipMalloc((void **)&c->red_partials, sizeof(double) * RED_VALS * c->red_blocks) == hipSuccess &&
               hipMalloc((void **)&c->red_out, sizeof(double) * RED_VALS) == hipSuccess &&
-              hipMalloc((void **)&c->mlp_counters, sizeof(unsigned long long) * 2) == hipSuccess &&
+              hipMalloc((void **)&c->mlp_counters, sizeof(unsigned long long) * 4) == hipSuccess &&
               hipMalloc((void **)&c->mlp_params, sizeof(float) * (LBM_MLP_NPARAMS + 64)) == hipSuccess &&
               hipMalloc((void **)&c->mlp_norm, sizeof(float) * 16) == hipSuccess &&
               hipMalloc((void **)&c->mlp_w2b, sizeof(uint16_t) * 64 * 64) == hipSuccess;
@@ -693,7 +748,8 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
         return LBM_ENOMEM;
     }
     // the single-pass step covers periodic z (and every D = 2 lattice)
-    c->fused = c->D == 2 || params->bc[2] == LBM_BC_PERIODIC;
+    // with the van der Waals equation of state, without shock capturing
+    c->fused = (c->D == 2 || params->bc[2] == LBM_BC_PERIODIC) && !c->sc && !lbm_eos_is_pr(params->eos);
     if (c->fused) {
         auto tiles = [&]() { DISPATCH_VOID(c, tiles(c)); };
         tiles();
@@ -714,7 +770,7 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
             return LBM_ENOMEM;
         }
     }
-    (void)hipMemsetAsync(c->mlp_counters, 0, sizeof(unsigned long long) * 2, c->stream);
+    (void)hipMemsetAsync(c->mlp_counters, 0, sizeof(unsigned long long) * 4, c->stream);
     c->cur = 0;
     c->initialized = false;
     c->mlp_ready = false;
@@ -724,13 +780,15 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
 
 void lbm_destroy(lbm_ctx *c) {
     if (!c) return;
-    if (c->stream) hipStreamSynchronize(c->stream);
-    else hipDeviceSynchronize();
+    // errors here have nowhere to go (the call returns nothing); the context
+    // is released regardless
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
     void *ptrs[] = {c->f[0], c->f[1], c->work, c->red_partials, c->red_out,
                     c->mlp_counters, c->mlp_params, c->mlp_norm, c->mlp_w2b, c->Mc[0], c->Mc[1], c->IN[0], c->IN[1],
                     c->Tsur};
     for (void *p : ptrs)
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
     delete c;
 }
 
@@ -745,6 +803,7 @@ int lbm_init(lbm_ctx *c, const double *rho, const double *u, const double *Tf) {
     const int rc = init_dispatch(c, rho, u, Tf);
     c->initialized = rc == LBM_OK;
     c->steps_done = 0;
+    c->T_valid = false;
     return rc;
 }
 
@@ -752,14 +811,14 @@ int lbm_step(lbm_ctx *c, int n) {
     if (!c) return LBM_EINVAL;
     if (!c->initialized) return LBM_ESTATE;
     if (n < 0) return LBM_EINVAL;
-    if (c->p.eos == LBM_EOS_MLP && !c->mlp_ready) return LBM_ESTATE;
+    if (lbm_eos_uses_mlp(c->p.eos) && !c->mlp_ready) return LBM_ESTATE;
     DISPATCH(c, step(c, n));
 }
 
 int lbm_moments(lbm_ctx *c, double *rho, double *u, double *Tf, double *P) {
     if (!c) return LBM_EINVAL;
     if (!c->initialized) return LBM_ESTATE;
-    if (c->p.eos == LBM_EOS_MLP && !c->mlp_ready) return LBM_ESTATE;
+    if (lbm_eos_uses_mlp(c->p.eos) && !c->mlp_ready) return LBM_ESTATE;
     DISPATCH(c, moments(c, rho, u, Tf, P));
 }
 
@@ -773,13 +832,14 @@ int lbm_set_populations(lbm_ctx *c, const double *f, const double *g) {
     if (!c || !f || !g) return LBM_EINVAL;
     c->initialized = true;
     c->steps_done = 0;
+    c->T_valid = false;
     DISPATCH(c, set_pops(c, f, g));
 }
 
 int lbm_conservation(lbm_ctx *c, double *host_out) {
     if (!c || !host_out) return LBM_EINVAL;
     if (!c->initialized) return LBM_ESTATE;
-    if (c->p.eos == LBM_EOS_MLP && !c->mlp_ready) return LBM_ESTATE;
+    if (lbm_eos_uses_mlp(c->p.eos) && !c->mlp_ready) return LBM_ESTATE;
     DISPATCH(c, conservation(c, host_out));
 }
 
@@ -791,7 +851,7 @@ int lbm_synchronize(lbm_ctx *c) {
 int lbm_step_timed(lbm_ctx *c, int n, double *host_ms, int nslots) {
     if (!c || !host_ms || n < 0) return LBM_EINVAL;
     if (!c->initialized) return LBM_ESTATE;
-    if (c->p.eos == LBM_EOS_MLP && !c->mlp_ready) return LBM_ESTATE;
+    if (lbm_eos_uses_mlp(c->p.eos) && !c->mlp_ready) return LBM_ESTATE;
     if (nslots < LBM_NUM_KERNELS) return LBM_EINVAL;
     DISPATCH(c, step_timed(c, n, host_ms));
 }

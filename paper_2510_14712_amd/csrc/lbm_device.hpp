@@ -32,7 +32,71 @@ template <class C> struct Phys {
     C a, b, R, cv, mu, eta, k, kappa;
     C inv_cv, k_over_mu, eta_over_mu;
     C sgn_eps;  // dead zone of the upwind switch
+    C sc_cmu, sc_ceta, sc_ck;  // shock-capturing coefficients (zero: off)
+    int pr;                    // 1: Peng-Robinson (a, b, R and the fields below); 0: van der Waals
+    double pr_m, pr_Tc, pr_c0, pr_c1;
 };
+
+// ---------------------------------------------------------------------------
+// Peng-Robinson equation of state (the paper's example of a fluid whose
+// temperature needs a node-wise non-linear solve, Section 3.2 after eq.
+// lbm_temp), in FP64:
+//   P = rho R T / (1 - b rho) - a alpha(T) rho^2 / (1 + 2 b rho - b^2 rho^2),
+//   alpha = (1 + m (1 - s))^2, s = sqrt(T / Tc),
+//   e = c0 T + c1 T^2 / 2 - a (1 + m)(1 + m (1 - s)) L(rho)   (c_v0 = c0 + c1 T),
+//   L = ln[(1 + (1 + sqrt2) b rho) / (1 + (1 - sqrt2) b rho)] / (2 sqrt2 b),
+// the energy departure being the integral of (P - T dP/dT)/rho^2 over
+// density; c_v = c_v0 + a T alpha'' L; c_s^2 = (dP/drho)_T + T (dP/dT)^2 /
+// (rho^2 c_v) (eq. speed_of_sound).
+// ---------------------------------------------------------------------------
+struct EosPoint {
+    double P, e, cv, cs2, dPdT;
+};
+template <class C> __device__ __forceinline__ EosPoint pr_eos(const Phys<C> &ph, double rho, double T) {
+    const double a = (double)ph.a, b = (double)ph.b, R = (double)ph.R, m = ph.pr_m;
+    const double sq = sqrt(T * ph.pr_Tc);
+    const double k = 1.0 + m * (1.0 - sqrt(T / ph.pr_Tc));
+    const double alpha = k * k;
+    const double dalpha = -m * k / sq;
+    const double d2alpha = 0.5 * m * (1.0 + m) / (T * sq);
+    const double den = 1.0 + 2.0 * b * rho - b * b * rho * rho;
+    const double omb = 1.0 - b * rho;
+    const double r2 = 1.4142135623730951;
+    const double L = log((1.0 + (1.0 + r2) * b * rho) / (1.0 + (1.0 - r2) * b * rho)) / (2.0 * r2 * b);
+    EosPoint o;
+    o.P = rho * R * T / omb - a * alpha * rho * rho / den;
+    o.e = ph.pr_c0 * T + 0.5 * ph.pr_c1 * T * T - a * (1.0 + m) * k * L;
+    o.cv = ph.pr_c0 + ph.pr_c1 * T + a * T * d2alpha * L;
+    o.dPdT = rho * R / omb - a * dalpha * rho * rho / den;
+    const double dPdrho = R * T / (omb * omb) - a * alpha * (2.0 * rho * den - rho * rho * (2.0 * b - 2.0 * b * b * rho)) /
+                                                    (den * den);
+    o.cs2 = dPdrho + T * o.dPdT * o.dPdT / (rho * rho * o.cv);
+    return o;
+}
+// Newton's method on e(rho, T) = e from T0 (a non-positive or non-finite
+// start is replaced by the dilute estimate e / c0, else T_c), a step that
+// would leave T > 0 halved; converged when the step is below 1e-15 T.
+// `iters` receives the iterations taken (50 at most).
+template <class C>
+__device__ __forceinline__ double pr_temperature(const Phys<C> &ph, double rho, double e, double T0, int &iters) {
+    double t = T0;
+    if (!(t > 1e-3 * ph.pr_Tc)) t = e / ph.pr_c0;
+    if (!(t > 1e-3 * ph.pr_Tc)) t = ph.pr_Tc;
+    iters = 0;
+    for (int it = 1; it <= 50; it++) {
+        const EosPoint q = pr_eos(ph, rho, t);
+        double dt = (q.e - e) / q.cv;
+        double tn = t - dt;
+        while (!(tn > 0.0) && fabs(dt) > 1e-300) {
+            dt *= 0.5;
+            tn = t - dt;
+        }
+        t = tn;
+        iters = it;
+        if (!(fabs(dt) > 1e-15 * t)) break;
+    }
+    return t;
+}
 
 // van der Waals pressure (eq. Pvdw)
 template <class C> __device__ __forceinline__ C vdw_pressure(const Phys<C> &p, C rho, C T) {

@@ -18,12 +18,14 @@ struct lbm_ctx {
     lbm::RefPops ref;
     hipStream_t stream = nullptr;
     bool initialized = false;
+    bool sc = false;                  // shock-capturing numerical transport on
     long long steps_done = 0;         // steps since the last init / set_populations (check interval)
+    bool T_valid = false;             // the field array T holds the current state's temperature
     bool mlp_ready = false;
     int red_blocks = 0;
     double *red_partials = nullptr;
     double *red_out = nullptr;
-    unsigned long long *mlp_counters = nullptr;  // [0] fallbacks, [1] evaluations
+    unsigned long long *mlp_counters = nullptr;  // [0] fallbacks, [1] evaluations, [2] Newton iterations, [3] cells
     float *mlp_params = nullptr;                 // 4547 FP32 + BF16 copy of W2
     float *mlp_norm = nullptr;
     uint16_t *mlp_w2b = nullptr;      // BF16 copy of the hidden 64x64 weights
@@ -54,11 +56,20 @@ template <class C> static inline lbm::Fields<C> get_fields(lbm_ctx *c) {
     fl.P = w; w += N;
     fl.h = w; w += N;
     fl.cs2 = w; w += N;
+    for (int k = 0; k < 4; k++) {
+        fl.sc[k] = c->sc ? w : nullptr;
+        if (c->sc) w += N;
+    }
     return fl;
 }
 
 // Record a failed HIP call's message for lbm_last_error(); returns the status.
 int lbm_note(hipError_t e);
 
-// surrogate-EOS variant of the per-cell fields pass (defined with the MLP code)
-template <int D, class C> int launch_fields_mlp(lbm_ctx *c, lbm::Fields<C> fl);
+// surrogate-EOS variant of the per-cell fields pass (defined with the MLP
+// code); count: add Newton iterations to the context's counters
+template <int D, class C> int launch_fields_mlp(lbm_ctx *c, lbm::Fields<C> fl, bool count);
+
+// equation-of-state modes
+inline bool lbm_eos_is_pr(int eos) { return eos == LBM_EOS_PR || eos == LBM_EOS_PR_PREV || eos == LBM_EOS_PR_MLP; }
+inline bool lbm_eos_uses_mlp(int eos) { return eos == LBM_EOS_MLP || eos == LBM_EOS_PR_MLP; }

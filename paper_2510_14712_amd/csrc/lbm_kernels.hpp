@@ -25,6 +25,7 @@ template <class C> struct Fields {
     C *lap;              // Laplacian of rho
     C *u, *F, *Lam;      // D components each
     C *T, *P, *h, *cs2;  // scalars
+    C *sc[4];            // shock-capturing work arrays (null when off)
 };
 
 template <int D> __device__ __forceinline__ long long cell_index(const Grid &g, int x, int y, int z) {
@@ -91,9 +92,16 @@ __global__ void __launch_bounds__(BX) k_init(Grid g, Phys<double> ph, RefPops re
     if (x >= g.nx) return;
     long long c = cell_index<D>(g, x, y, z);
     double r = rho[c], t = T[c];
-    double P = vdw_pressure(ph, r, t);
+    double P, e;
+    if (ph.pr) {
+        const EosPoint q = pr_eos(ph, r, t);
+        P = q.P;
+        e = q.e;
+    } else {
+        P = vdw_pressure(ph, r, t);
+        e = ph.cv * t - ph.a * r;
+    }
     double theta = P / r;
-    double e = ph.cv * t - ph.a * r;
     double eps = e - 0.5 * D * theta;
     AxisEq<double> ax[3];
     for (int a = 0; a < D; a++) ax[a] = axis_eq(u[a * g.N + c], theta);
@@ -154,12 +162,28 @@ __global__ void __launch_bounds__(BX) k_lap(Grid g, Fields<C> fl) {
     fl.lap[c] = s;
 }
 
-// per-cell thermodynamic fields from the moments, the exact van der Waals
-// caloric inversion T = (E - u^2/2 + a rho)/c_v (eq. lbm_temp)
+// sum over a wavefront of a per-lane count, added once per wavefront
+__device__ __forceinline__ void wave_count(unsigned long long *dst, unsigned v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, (unsigned long long)v);
+}
+
+// per-cell thermodynamic fields from the moments: the exact van der Waals
+// caloric inversion T = (E - u^2/2 + a rho)/c_v (eq. lbm_temp), or for
+// Peng-Robinson Newton's method in FP64 from the dilute estimate (warm = 0)
+// or from the cell's temperature of the previous step (warm = 1);
+// newton[0] counts the iterations, newton[1] the cells (may be null)
 template <int D, class C>
-__global__ void __launch_bounds__(BX) k_fields(Grid g, Phys<C> ph, Fields<C> fl) {
+__global__ void __launch_bounds__(BX) k_fields(Grid g, Phys<C> ph, Fields<C> fl, int warm,
+                                               unsigned long long *newton) {
     int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
-    if (x >= g.nx) return;
+    const bool active = x < g.nx;
+    if (ph.pr && newton) {
+        // the wavefront's lanes all take part in the count below
+        if (!active) x = g.nx - 1;
+    } else if (!active) {
+        return;
+    }
     long long c = cell_index<D>(g, x, y, z);
     C rho = fl.rho[c];
     C inv_rho = C(1) / rho;
@@ -173,8 +197,24 @@ __global__ void __launch_bounds__(BX) k_fields(Grid g, Phys<C> ph, Fields<C> fl)
     }
     C E = (fl.G[c] + C(0.5) * uF) * inv_rho;                  // eq. def_E
     C e = E - C(0.5) * u2;
-    C T = (e + ph.a * rho) * ph.inv_cv;                        // eq. lbm_temp
-    C P = vdw_pressure(ph, rho, T);                            // eq. Pvdw
+    C T, P, cs2;
+    if (ph.pr) {
+        int it = 0;
+        const double Td = pr_temperature(ph, (double)rho, (double)e, warm ? (double)fl.T[c] : 0.0, it);
+        const EosPoint q = pr_eos(ph, (double)rho, Td);
+        T = (C)Td;
+        P = (C)q.P;
+        cs2 = (C)q.cs2;
+        if (newton) {
+            wave_count(&newton[0], active ? (unsigned)it : 0u);
+            wave_count(&newton[1], active ? 1u : 0u);
+        }
+        if (!active) return;
+    } else {
+        T = (e + ph.a * rho) * ph.inv_cv;                      // eq. lbm_temp
+        P = vdw_pressure(ph, rho, T);                          // eq. Pvdw
+        cs2 = vdw_cs2(ph, rho, T);                             // eq. vdW_speed_of_sound
+    }
     C theta = P * inv_rho;
     for (int a = 0; a < D; a++) {
         fl.u[a * g.N + c] = u[a];
@@ -185,15 +225,109 @@ __global__ void __launch_bounds__(BX) k_fields(Grid g, Phys<C> ph, Fields<C> fl)
     fl.T[c] = T;
     fl.P[c] = P;
     fl.h[c] = e + theta;                                       // eq. enthalpy
-    fl.cs2[c] = vdw_cs2(ph, rho, T);
+    fl.cs2[c] = cs2;
 }
 
 // ---------------------------------------------------------------------------
+// Shock-capturing numerical transport (Section 4.4, eqs. shock_cap and
+// shock_cap_k, r = 5, dx = 1), three passes over the fields of the step:
+//   k_sc_grad    S = |grad u + grad u^T| / 2 and |grad s|, grad s = (c_v/T) grad T
+//                - R/(rho (1 - b rho)) grad rho (eq. ds_vdW), central differences
+//   k_sc_d4      |sum_a d^4/dx_a^4| of both (central fourth differences)
+//   k_sc_filter  the truncated Gaussian filter along one axis (launched per axis)
+// k_collide then adds rho C_mu fS, rho C_eta fS and rho c_s C_k fs to mu, eta,
+// k of the cell.  Indices beyond a zero-gradient wall clamp, periodic ones wrap.
+__device__ __forceinline__ int wrap_any(int v, int n, int clamp) {
+    if (clamp) return v < 0 ? 0 : (v >= n ? n - 1 : v);
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+template <int D> __device__ __forceinline__ long long nb_axis_n(const Grid &g, int x, int y, int z, int a, int s) {
+    if (a == 0) x = wrap_any(x + s, g.nx, g.clampx);
+    else if (a == 1) y = wrap_any(y + s, g.ny, g.clampy);
+    else z = wrap_any(z + s, g.nz, g.clampz);
+    return cell_index<D>(g, x, y, z);
+}
+
+constexpr int SC_RADIUS = 4;  // filter taps -4 .. 4
+template <class C> struct ScFilter {
+    C w[2 * SC_RADIUS + 1];
+};
+
+template <int D, class C>
+__global__ void __launch_bounds__(BX) k_sc_grad(Grid g, Phys<C> ph, Fields<C> fl) {
+    int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    const long long N = g.N, c = cell_index<D>(g, x, y, z);
+    C G[3][3];  // G[a][b] = d u_a / d x_b
+    const C rho = fl.rho[c], T = fl.T[c];
+    // ds = (c_v / T) dT - (dP/dT)_rho / rho^2 drho; van der Waals: the second
+    // coefficient is R / (rho (1 - b rho))
+    C cT, cr;
+    if (ph.pr) {
+        const EosPoint q = pr_eos(ph, (double)rho, (double)T);
+        cT = (C)(q.cv / (double)T);
+        cr = (C)(q.dPdT / ((double)rho * (double)rho));
+    }
+    C g2 = 0;
+    for (int b = 0; b < D; b++) {
+        const long long cp = nb_axis<D>(g, x, y, z, b, 1), cm = nb_axis<D>(g, x, y, z, b, -1);
+        for (int a = 0; a < D; a++) G[a][b] = C(0.5) * (fl.u[a * N + cp] - fl.u[a * N + cm]);
+        const C dT = C(0.5) * (fl.T[cp] - fl.T[cm]), dr = C(0.5) * (fl.rho[cp] - fl.rho[cm]);
+        const C ds = ph.pr ? cT * dT - cr * dr : ph.cv / T * dT - ph.R / (rho * (C(1) - ph.b * rho)) * dr;
+        g2 += ds * ds;
+    }
+    C ss = 0;
+    for (int a = 0; a < D; a++)
+        for (int b = 0; b < D; b++) ss += (G[a][b] + G[b][a]) * (G[a][b] + G[b][a]);
+    fl.sc[0][c] = C(0.5) * sqrt(ss);
+    fl.sc[1][c] = sqrt(g2);
+}
+
+template <int D, class C>
+__global__ void __launch_bounds__(BX) k_sc_d4(Grid g, const C *__restrict__ a_in, const C *__restrict__ b_in,
+                                              C *__restrict__ a_out, C *__restrict__ b_out) {
+    int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    const long long c = cell_index<D>(g, x, y, z);
+    C sa = 0, sb = 0;
+    for (int a = 0; a < D; a++) {
+        const long long p1 = nb_axis_n<D>(g, x, y, z, a, 1), p2 = nb_axis_n<D>(g, x, y, z, a, 2);
+        const long long m1 = nb_axis_n<D>(g, x, y, z, a, -1), m2 = nb_axis_n<D>(g, x, y, z, a, -2);
+        sa += a_in[p2] - C(4) * a_in[p1] + C(6) * a_in[c] - C(4) * a_in[m1] + a_in[m2];
+        sb += b_in[p2] - C(4) * b_in[p1] + C(6) * b_in[c] - C(4) * b_in[m1] + b_in[m2];
+    }
+    a_out[c] = fabs(sa);
+    b_out[c] = fabs(sb);
+}
+
+template <int D, class C>
+__global__ void __launch_bounds__(BX) k_sc_filter(Grid g, int axis, ScFilter<C> f, const C *__restrict__ a_in,
+                                                  const C *__restrict__ b_in, C *__restrict__ a_out,
+                                                  C *__restrict__ b_out) {
+    int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    const long long c = cell_index<D>(g, x, y, z);
+    C sa = 0, sb = 0;
+    for (int j = -SC_RADIUS; j <= SC_RADIUS; j++) {
+        const long long n = nb_axis_n<D>(g, x, y, z, axis, j);
+        sa += f.w[j + SC_RADIUS] * a_in[n];
+        sb += f.w[j + SC_RADIUS] * b_in[n];
+    }
+    a_out[c] = sa;
+    b_out[c] = sb;
+}
+
+// ---------------------------------------------------------------------------
+// fS, fs: filtered |grad^4 S| and |grad^4 |grad s|| of the shock-capturing
+// passes, or null without shock capturing
 template <int D, class S>
 __global__ void __launch_bounds__(BX) k_collide(Grid g, Phys<typename S::C> ph, RefPops ref,
                                                 const typename S::T *__restrict__ fi,
                                                 const typename S::T *__restrict__ gi, Fields<typename S::C> fl,
-                                                typename S::T *__restrict__ fo, typename S::T *__restrict__ go) {
+                                                typename S::T *__restrict__ fo, typename S::T *__restrict__ go,
+                                                const typename S::C *__restrict__ fS,
+                                                const typename S::C *__restrict__ fs) {
     using C = typename S::C;
     constexpr int Q = Lattice<D>::Q;
     int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
@@ -201,6 +335,17 @@ __global__ void __launch_bounds__(BX) k_collide(Grid g, Phys<typename S::C> ph, 
     const long long N = g.N;
     long long c = cell_index<D>(g, x, y, z);
     C rho = fl.rho[c], P = fl.P[c], T = fl.T[c];
+    // transport coefficients of the cell: the constants plus the numerical
+    // contributions of the shock-capturing scheme (Section 4.4)
+    C mu = ph.mu, eta_over_mu = ph.eta_over_mu, k_over_mu = ph.k_over_mu;
+    if (fS) {
+        const C cs = sqrt(fl.cs2[c] > C(0) ? fl.cs2[c] : C(0));
+        mu = ph.mu + rho * ph.sc_cmu * fS[c];
+        const C eta = ph.eta + rho * ph.sc_ceta * fS[c];
+        const C kk = ph.k + rho * cs * ph.sc_ck * fs[c];
+        eta_over_mu = eta / mu;
+        k_over_mu = kk / mu;
+    }
     C inv_rho = C(1) / rho;
     C theta = P * inv_rho;
     C u[3], F[3], divu = 0, qc[3], Phi[3], FF = 0;
@@ -212,7 +357,7 @@ __global__ void __launch_bounds__(BX) k_collide(Grid g, Phys<typename S::C> ph, 
         divu += C(0.5) * (fl.u[a * N + cp] - fl.u[a * N + cm]);
         C dh = C(0.5) * (fl.h[cp] - fl.h[cm]);
         C dT = C(0.5) * (fl.T[cp] - fl.T[cm]);
-        qc[a] = P * (dh - ph.k_over_mu * dT);                  // eq. qc_1
+        qc[a] = P * (dh - k_over_mu * dT);                     // eq. qc_1
         // upwind-biased d_a Lambda_a by sgn(u_a); |u_a| <= eps gives the average
         C L0 = fl.Lam[a * N + c];
         C dL;
@@ -221,12 +366,21 @@ __global__ void __launch_bounds__(BX) k_collide(Grid g, Phys<typename S::C> ph, 
         else dL = C(0.5) * (fl.Lam[a * N + cp] - fl.Lam[a * N + cm]);
         Phi[a] = -dL * inv_rho;                                // eq. correction
     }
-    C beta = P / (P + C(2) * ph.mu);                           // eq. beta_main with tau = mu / P
-    C alpha = C(D + 2) / C(D) - rho * fl.cs2[c] / P - ph.eta_over_mu;  // eq. corr_bulk
+    C beta = P / (P + C(2) * mu);                              // eq. beta_main with tau = mu / P
+    C alpha = C(D + 2) / C(D) - rho * fl.cs2[c] / P - eta_over_mu;  // eq. corr_bulk
     C thetas = theta + alpha * theta * divu;                   // eq. sh_temp_1
-    C Ts = T - FF * inv_rho * inv_rho * C(0.5) * ph.inv_cv;    // eq. sh_T_1
-    C e = ph.cv * T - ph.a * rho;                              // e(rho, T), eq. de_vdW
-    C es = ph.cv * Ts - ph.a * rho;                            // e(rho, T*)
+    C e, es;
+    if (ph.pr) {
+        // e(rho, T) by the caloric relation; e(rho, T*) as the energy the
+        // shift of eq. sh_T_1 stands for, e - |F|^2 / (2 rho^2) (exact for an
+        // energy linear in T, and keeps the collision's energy change u . F)
+        e = (C)pr_eos(ph, (double)rho, (double)T).e;
+        es = e - FF * inv_rho * inv_rho * C(0.5);
+    } else {
+        C Ts = T - FF * inv_rho * inv_rho * C(0.5) * ph.inv_cv;  // eq. sh_T_1
+        e = ph.cv * T - ph.a * rho;                            // e(rho, T), eq. de_vdW
+        es = ph.cv * Ts - ph.a * rho;                          // e(rho, T*)
+    }
     C eps_eq = e - C(0.5 * D) * theta;
     C eps_st = es - C(0.5 * D) * thetas;
 

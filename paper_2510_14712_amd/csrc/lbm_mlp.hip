@@ -143,6 +143,9 @@ __global__ void __launch_bounds__(64) k_forward_l1mfma(const float *P, const flo
 // whose e is linear in T -- and the closed forms for P and c_s^2.
 constexpr int MLP_BLOCK = 128;  // two waves: 2 x 16.6 KB of LDS per workgroup
 
+// With the Peng-Robinson equation of state the residual is taken with
+// e(rho, T_hat) and c_v(rho, T_hat) in FP64, and a failing cell runs Newton's
+// method from T_hat to convergence (counters[2], [3]: iterations, cells).
 template <int D>
 __global__ void __launch_bounds__(MLP_BLOCK) k_fields_mlp(Grid g, Phys<float> ph, Fields<float> fl, const float *P,
                                                          const uint16_t *W2b, const float *norm, float tol,
@@ -172,9 +175,27 @@ __global__ void __launch_bounds__(MLP_BLOCK) k_fields_mlp(Grid g, Phys<float> ph
     // (explicit once T is known); the network's P and c_s^2 outputs are
     // trained and reported but not used here.
     float T = yh[0] * norm[5] + norm[4];
-    float r = fabsf(ph.cv * T - ph.a * rho - e) / (ph.cv * fabsf(T));
-    const bool fb = !(r <= tol);
     float Pr, c2;
+    bool fb;
+    if (ph.pr) {
+        const double rd = (double)rho, ed = (double)e;
+        EosPoint q = pr_eos(ph, rd, (double)T);
+        fb = !(fabs(q.e - ed) <= (double)tol * q.cv * fabs((double)T));
+        int it = 0;
+        if (fb) {
+            const double Td = pr_temperature(ph, rd, ed, (double)T, it);
+            q = pr_eos(ph, rd, Td);
+            T = (float)Td;
+        }
+        Pr = (float)q.P;
+        c2 = (float)q.cs2;
+        if (counters) {
+            wave_count(&counters[2], active ? (unsigned)it : 0u);
+            wave_count(&counters[3], active ? 1u : 0u);
+        }
+    } else {
+    float r = fabsf(ph.cv * T - ph.a * rho - e) / (ph.cv * fabsf(T));
+    fb = !(r <= tol);
     if (fb) {
         double Td = (double)T, rd = (double)rho, cv = (double)ph.cv, a = (double)ph.a;
         Td = Td - (cv * Td - a * rd - (double)e) / cv;  // Newton on e(rho, T) - e = 0
@@ -186,9 +207,10 @@ __global__ void __launch_bounds__(MLP_BLOCK) k_fields_mlp(Grid g, Phys<float> ph
         Pr = vdw_pressure(ph, rho, T);
         c2 = vdw_cs2(ph, rho, T);
     }
+    }
     unsigned long long nfb = __popcll(__ballot(fb && active));
     unsigned long long nact = __popcll(__ballot(active));
-    if ((tid & 63) == 0) {
+    if ((tid & 63) == 0 && counters) {
         atomicAdd(&counters[0], nfb);
         atomicAdd(&counters[1], nact);
     }
@@ -342,6 +364,15 @@ __global__ void k_make_samples(int n, unsigned long long seed, Phys<double> ph, 
     if (i >= n) return;
     double rho = r0 + (r1 - r0) * uniform01(seed, 2ull * i);
     double T = T0 + (T1 - T0) * uniform01(seed, 2ull * i + 1);
+    if (ph.pr) {  // Peng-Robinson targets
+        const EosPoint q = pr_eos(ph, rho, T);
+        x[2 * i] = (float)rho;
+        x[2 * i + 1] = (float)q.e;
+        t[3 * i] = T;
+        t[3 * i + 1] = q.P;
+        t[3 * i + 2] = q.cs2;
+        return;
+    }
     double e = ph.cv * T - ph.a * rho;
     double omb = 1.0 - ph.b * rho;
     x[2 * i] = (float)rho;
@@ -398,10 +429,11 @@ __global__ void k_normalise_samples(int n, const float *x, const double *t, cons
 }  // namespace lbm
 
 // ---------------------------------------------------------------------------
-template <int D, class C> int launch_fields_mlp(lbm_ctx *c, Fields<C> fl) {
+template <int D, class C> int launch_fields_mlp(lbm_ctx *c, Fields<C> fl, bool count) {
     if constexpr (!std::is_same<C, float>::value) {
         (void)c;
         (void)fl;
+        (void)count;
         return LBM_EINVAL;
     } else {
         Phys<float> ph;
@@ -410,16 +442,20 @@ template <int D, class C> int launch_fields_mlp(lbm_ctx *c, Fields<C> fl) {
         ph.mu = (float)p.mu; ph.eta = (float)p.eta; ph.k = (float)p.k; ph.kappa = (float)p.kappa;
         ph.inv_cv = (float)(1.0 / p.cv); ph.k_over_mu = (float)(p.k / p.mu); ph.eta_over_mu = (float)(p.eta / p.mu);
         ph.sgn_eps = (float)p.upwind_eps;
+        ph.sc_cmu = (float)p.sc_cmu; ph.sc_ceta = (float)p.sc_ceta; ph.sc_ck = (float)p.sc_ck;
+        ph.pr = lbm_eos_is_pr(p.eos) ? 1 : 0;
+        ph.pr_m = p.pr_m; ph.pr_Tc = p.pr_Tc; ph.pr_c0 = p.pr_c0; ph.pr_c1 = p.pr_c1;
         dim3 gr((unsigned)((p.nx + mlp::MLP_BLOCK - 1) / mlp::MLP_BLOCK), (unsigned)p.ny, (unsigned)p.nz);
         hipLaunchKernelGGL((mlp::k_fields_mlp<D>), gr, dim3(mlp::MLP_BLOCK), 0, c->stream, c->grid, ph, fl, c->mlp_params,
-                           c->mlp_w2b, c->mlp_norm, (float)p.mlp_tol, c->mlp_counters);
+                           c->mlp_w2b, c->mlp_norm, (float)p.mlp_tol,
+                           count ? c->mlp_counters : (unsigned long long *)nullptr);
         return lbm_note(hipGetLastError());
     }
 }
-template int launch_fields_mlp<2, float>(lbm_ctx *, Fields<float>);
-template int launch_fields_mlp<3, float>(lbm_ctx *, Fields<float>);
-template int launch_fields_mlp<2, double>(lbm_ctx *, Fields<double>);
-template int launch_fields_mlp<3, double>(lbm_ctx *, Fields<double>);
+template int launch_fields_mlp<2, float>(lbm_ctx *, Fields<float>, bool);
+template int launch_fields_mlp<3, float>(lbm_ctx *, Fields<float>, bool);
+template int launch_fields_mlp<2, double>(lbm_ctx *, Fields<double>, bool);
+template int launch_fields_mlp<3, double>(lbm_ctx *, Fields<double>, bool);
 
 // ---------------------------------------------------------------------------
 namespace {
@@ -484,6 +520,14 @@ int lbm_mlp_loss_grad(const float *params, const float *xn, const float *tn, int
     return rc;
 }
 
+// Peng-Robinson specific energy e(rho, T) on the host (the same relation the
+// kernels evaluate), for the input range of the training box
+static double host_pr_energy(const lbm_params &p, double rho, double T) {
+    const double r2 = std::sqrt(2.0);
+    const double L = std::log((1.0 + (1.0 + r2) * p.b * rho) / (1.0 + (1.0 - r2) * p.b * rho)) / (2.0 * r2 * p.b);
+    return p.pr_c0 * T + 0.5 * p.pr_c1 * T * T - p.a * (1.0 + p.pr_m) * (1.0 + p.pr_m * (1.0 - std::sqrt(T / p.pr_Tc))) * L;
+}
+
 int lbm_mlp_train(const lbm_params *prm, const double *box, int n, uint64_t seed, int epochs, int batch, float lr,
                   int precision, float *host_params, float *host_norm, double *host_loss) {
     if (!prm || !box || !host_params || !host_norm) return LBM_EINVAL;
@@ -491,6 +535,7 @@ int lbm_mlp_train(const lbm_params *prm, const double *box, int n, uint64_t seed
     if (precision != LBM_MLP_BF16 && precision != LBM_MLP_F32) return LBM_EINVAL;
     if (!(box[1] > box[0] && box[3] > box[2] && box[0] > 0 && box[2] > 0)) return LBM_EINVAL;
     if (!(prm->cv > 0) || !(prm->b * box[1] < 1.0)) return LBM_EINVAL;
+    if (lbm_eos_is_pr(prm->eos) && !(prm->pr_Tc > 0 && prm->pr_c0 > 0 && prm->b > 0)) return LBM_EINVAL;
     hipStream_t s = nullptr;
     const int nbat = n / batch;
     DevBuf x, t, xn, tn, P, m, v, grad, loss, gpart, lpart, stats, norm, lacc;
@@ -505,18 +550,28 @@ int lbm_mlp_train(const lbm_params *prm, const double *box, int n, uint64_t seed
     Phys<double> ph;
     ph.a = prm->a; ph.b = prm->b; ph.R = prm->R; ph.cv = prm->cv;
     ph.mu = ph.eta = ph.k = ph.kappa = 0; ph.inv_cv = 1.0 / prm->cv; ph.k_over_mu = ph.eta_over_mu = 0; ph.sgn_eps = 0;
+    ph.sc_cmu = ph.sc_ceta = ph.sc_ck = 0;
+    ph.pr = lbm_eos_is_pr(prm->eos) ? 1 : 0;
+    ph.pr_m = prm->pr_m; ph.pr_Tc = prm->pr_Tc; ph.pr_c0 = prm->pr_c0; ph.pr_c1 = prm->pr_c1;
     hipLaunchKernelGGL(mlp::k_make_samples, dim3((n + 255) / 256), dim3(256), 0, s, n, (unsigned long long)seed, ph,
                        box[0], box[1], box[2], box[3], x.as<float>(), t.as<double>());
     hipLaunchKernelGGL(mlp::k_target_stats, dim3(1), dim3(256), 0, s, n, t.as<double>(), stats.as<double>());
     double st[6];
     if (hipMemcpy(st, stats.p, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return LBM_EDEVICE;
-    // input ranges of the box: rho in [r0, r1]; e = c_v T - a rho in
-    // [c_v T0 - a r1, c_v T1 - a r0]
+    // input ranges of the box: rho in [r0, r1]; e rises with T and falls
+    // with rho (van der Waals e = c_v T - a rho: [c_v T0 - a r1, c_v T1 - a r0];
+    // Peng-Robinson likewise, its departure term being negative and growing
+    // with density)
     float nh[16] = {0};
     nh[0] = (float)box[0];
     nh[1] = (float)box[1];
-    nh[2] = (float)(prm->cv * box[2] - prm->a * box[1]);
-    nh[3] = (float)(prm->cv * box[3] - prm->a * box[0]);
+    if (ph.pr) {
+        nh[2] = (float)host_pr_energy(*prm, box[1], box[2]);
+        nh[3] = (float)host_pr_energy(*prm, box[0], box[3]);
+    } else {
+        nh[2] = (float)(prm->cv * box[2] - prm->a * box[1]);
+        nh[3] = (float)(prm->cv * box[3] - prm->a * box[0]);
+    }
     for (int k = 0; k < 3; k++) {
         nh[4 + 2 * k] = (float)st[2 * k];
         nh[5 + 2 * k] = (float)(st[2 * k + 1] > 0 ? st[2 * k + 1] : 1.0);
@@ -566,7 +621,7 @@ static uint16_t host_bf16(float v) {
 
 int lbm_mlp_set(lbm_ctx *c, const float *host_params, const float *host_norm) {
     if (!c || !host_params || !host_norm) return LBM_EINVAL;
-    if (c->p.eos != LBM_EOS_MLP) return LBM_EINVAL;
+    if (!lbm_eos_uses_mlp(c->p.eos)) return LBM_EINVAL;
     for (int i = 0; i < mlp::H * mlp::H; i++) c->mlp_w2b_host[i] = host_bf16(host_params[mlp::OFF_W2 + i]);
     if (hipMemcpyAsync(c->mlp_params, host_params, sizeof(float) * LBM_MLP_NPARAMS, hipMemcpyHostToDevice,
                        c->stream) != hipSuccess ||
@@ -580,15 +635,21 @@ int lbm_mlp_set(lbm_ctx *c, const float *host_params, const float *host_norm) {
     return LBM_OK;
 }
 
-int lbm_mlp_stats(lbm_ctx *c, double *frac) {
-    if (!c || !frac) return LBM_EINVAL;
-    unsigned long long h[2];
+int lbm_eos_stats(lbm_ctx *c, double *frac, double *iters) {
+    if (!c) return LBM_EINVAL;
+    unsigned long long h[4];
     if (hipMemcpyAsync(h, c->mlp_counters, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
         return LBM_EDEVICE;
-    *frac = h[1] ? (double)h[0] / (double)h[1] : 0.0;
+    if (frac) *frac = h[1] ? (double)h[0] / (double)h[1] : 0.0;
+    if (iters) *iters = h[3] ? (double)h[2] / (double)h[3] : 0.0;
     if (hipMemsetAsync(c->mlp_counters, 0, sizeof(h), c->stream) != hipSuccess) return LBM_EDEVICE;
     return LBM_OK;
+}
+
+int lbm_mlp_stats(lbm_ctx *c, double *frac) {
+    if (!c || !frac) return LBM_EINVAL;
+    return lbm_eos_stats(c, frac, nullptr);
 }
 
 }  // extern "C"

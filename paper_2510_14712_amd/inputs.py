@@ -32,7 +32,7 @@ def physics(st: dict, workload: str | None = None) -> dict:
     gives in place of the shared ones."""
     kw = {k: st["constants"][k] for k in ("a", "b", "R", "cv", "mu", "eta", "k", "kappa")}
     if workload is not None:
-        for k in ("mu", "eta", "k"):
+        for k in ("cv", "mu", "eta", "k"):
             if k in st[workload]:
                 kw[k] = st[workload][k]
     return kw
@@ -78,14 +78,16 @@ def random_state(D, shape, seed, rho0, T0, drho=0.02, du=0.05, dT=0.02, white=0.
     return rho, u, T
 
 
-def shock_tube(shape, rho_left, rho_right, T, x_split=None):
-    """Piecewise-constant Riemann data at rest: rho = rho_left for x < x_split."""
+def shock_tube(shape, rho_left, rho_right, T, x_split=None, T_right=None):
+    """Piecewise-constant Riemann data at rest: rho = rho_left (and T) for
+    x < x_split, rho_right (and T_right, default T) beyond."""
     coords = grid(shape)
     x = coords[0]
     xs = shape[0] // 2 if x_split is None else x_split
     rho = np.where(x < xs, rho_left, rho_right).astype(np.float64)
     u = np.zeros(len(shape) * x.size)
-    return rho, u, np.full(x.size, float(T))
+    Tf = np.where(x < xs, float(T), float(T if T_right is None else T_right)).astype(np.float64)
+    return rho, u, Tf
 
 
 def shock_drop(shape, centre, radius, width, rho_liquid, rho_vapour, T1,

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm_hip.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ENAN, LBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 STORAGE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
-EOS = {"vdw": 0, "mlp": 1}
+EOS = {"vdw": 0, "mlp": 1, "pr": 2, "pr_prev": 3, "pr_mlp": 4}
 MLP_BF16, MLP_F32, MLP_BF16_L1 = 0, 1, 2
 MLP_NPARAMS, MLP_NNORM = 4547, 10
 # dead zone of the upwind switch: |u| at or below takes the central average
@@ -39,7 +39,10 @@ class _Params(ctypes.Structure):
                 ("kappa", ctypes.c_double),
                 ("storage", ctypes.c_int), ("eos", ctypes.c_int), ("mlp_tol", ctypes.c_double),
                 ("ref_rho", ctypes.c_double), ("ref_T", ctypes.c_double), ("stream", ctypes.c_void_p),
-                ("upwind_eps", ctypes.c_double), ("zsegments", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("upwind_eps", ctypes.c_double), ("zsegments", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("pr_m", ctypes.c_double), ("pr_Tc", ctypes.c_double), ("pr_c0", ctypes.c_double),
+                ("pr_c1", ctypes.c_double),
+                ("sc_cmu", ctypes.c_double), ("sc_ceta", ctypes.c_double), ("sc_ck", ctypes.c_double)]
 
 
 _lib = None
@@ -80,6 +83,7 @@ def load():
                            ctypes.c_int, _FP, _FP, _DP], ctypes.c_int),
         "lbm_mlp_set": ([_VP, _FP, _FP], ctypes.c_int),
         "lbm_mlp_stats": ([_VP, _DP], ctypes.c_int),
+        "lbm_eos_stats": ([_VP, _DP, _DP], ctypes.c_int),
         "lbm_mlp_forward": ([_VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP], ctypes.c_int),
         "lbm_mlp_loss_grad": ([_VP, _VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
         "lbm_mlp_adam": ([_VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_float, _VP], ctypes.c_int),
@@ -135,7 +139,7 @@ class Lattice:
 
     def __init__(self, lattice, shape, bc=(0, 0, 0), a=3.0 / 49.0, b=2.0 / 21.0, R=1.0, cv=2.5, mu=0.05,
                  eta=0.05, k=None, kappa=0.01, storage="f32", eos="vdw", mlp_tol=1e-6, ref_rho=0.0, ref_T=0.0,
-                 stream=None, upwind_eps=UPWIND_EPS, zsegments=0, check_every=0):
+                 stream=None, upwind_eps=UPWIND_EPS, zsegments=0, check_every=0, sc=(0.0, 0.0, 0.0), pr=None):
         L = load()
         self.D = int(lattice)
         nx, ny = int(shape[0]), int(shape[1])
@@ -158,6 +162,9 @@ class Lattice:
         p.upwind_eps = upwind_eps
         p.zsegments = int(zsegments)
         p.check_every = int(check_every)
+        p.sc_cmu, p.sc_ceta, p.sc_ck = (float(v) for v in sc)  # shock capturing (C_mu, C_eta, C_k)
+        if pr is not None:  # Peng-Robinson constants dict(m, Tc, c0, c1); a, b, R above
+            p.pr_m, p.pr_Tc, p.pr_c0, p.pr_c1 = (float(pr[k]) for k in ("m", "Tc", "c0", "c1"))
         self._stream = stream
         p.stream = _stream_ptr(stream).value if _torch().cuda.is_available() else None
         self.params = p
@@ -257,14 +264,25 @@ class Lattice:
         _check(load().lbm_mlp_stats(self._h, ctypes.byref(v)), "lbm_mlp_stats")
         return v.value
 
+    def eos_stats(self):
+        """(fallback fraction, mean Newton iterations per cell) since the last call."""
+        fb, it = ctypes.c_double(), ctypes.c_double()
+        _check(load().lbm_eos_stats(self._h, ctypes.byref(fb), ctypes.byref(it)), "lbm_eos_stats")
+        return fb.value, it.value
+
 
 def mlp_train(box, n_samples, seed, epochs, batch, lr, params0, precision=MLP_BF16, a=3.0 / 49.0, b=2.0 / 21.0,
-              R=1.0, cv=2.5):
-    """lbm_mlp_train: returns (params[4547], norm[10], final_loss)."""
+              R=1.0, cv=2.5, pr=None):
+    """lbm_mlp_train: returns (params[4547], norm[10], final_loss).  pr:
+    Peng-Robinson constants dict(m, Tc, c0, c1) to train on that equation of
+    state (a, b, R then its constants), else van der Waals."""
     p = _Params()
     p.lattice, p.nx, p.ny, p.nz = 2, 1, 1, 1
     p.a, p.b, p.R, p.cv = a, b, R, cv
     p.mu = 1.0
+    if pr is not None:
+        p.eos = EOS["pr_mlp"]
+        p.pr_m, p.pr_Tc, p.pr_c0, p.pr_c1 = (float(pr[k]) for k in ("m", "Tc", "c0", "c1"))
     bx = np.ascontiguousarray(box, dtype=np.float64)
     prm = np.ascontiguousarray(params0, dtype=np.float32).copy()
     norm = np.zeros(MLP_NNORM, dtype=np.float32)
