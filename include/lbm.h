@@ -295,6 +295,22 @@ int lbm_mlp_adam(float *dev_params, const float *dev_grad, float *dev_m, float *
 int lbm_mlp_loss_grad(const float *dev_params, const float *dev_xn, const float *dev_tn,
                       int B, float *dev_grad, float *dev_loss, int precision, void *stream);
 
+/* lbm_mlp_loss_grad without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving or training loops,
+ * harnesses that forbid hipMalloc.  Same arguments, kernels and results as
+ * lbm_mlp_loss_grad (bit for bit), with B a positive multiple of 64 of at
+ * most LBM_MLP_NOALLOC_MAX_BATCH.  The per-block partial sums live in a
+ * library-owned static device array (2.3 MB on every GPU the library is
+ * called on, kept until the process ends); each call overwrites the part it
+ * uses before reading it.  Calls that overlap on one GPU (different streams
+ * or threads) share that array and race: serialise them.  Asynchronous on
+ * `stream` (no synchronisation).  The first call on a device looks up the
+ * array's address there.  Errors: LBM_EINVAL (B out of range, precision,
+ * NULL pointer), LBM_EDEVICE. */
+#define LBM_MLP_NOALLOC_MAX_BATCH 8192
+int lbm_mlp_loss_grad_noalloc(const float *dev_params, const float *dev_xn, const float *dev_tn, int B,
+                              float *dev_grad, float *dev_loss, int precision, void *stream);
+
 /* ---- precision codec ---------------------------------------------------- */
 /* dev_out[n] = 16-bit code of dev_x[n] - dev_ref[n] (FP32 subtraction,
  * round-to-nearest-even; kind LBM_STORE_BF16 or LBM_STORE_F16); the decode

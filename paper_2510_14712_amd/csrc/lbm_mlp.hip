@@ -13,6 +13,8 @@
 //   row 32 mt + 8 (v / 4) + 4 (l / 32) + v % 4, column 32 nt + l % 32.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <cmath>
 #include <cstring>
 #include <type_traits>
@@ -458,6 +460,40 @@ template int launch_fields_mlp<2, double>(lbm_ctx *, Fields<double>, bool);
 template int launch_fields_mlp<3, double>(lbm_ctx *, Fields<double>, bool);
 
 // ---------------------------------------------------------------------------
+// Scratch of lbm_mlp_loss_grad_noalloc: the per-block gradient partials (NP
+// values per 64 samples) and squared-error partials of a batch of at most
+// LBM_MLP_NOALLOC_MAX_BATCH samples, 2.3 MB on every GPU the library runs on,
+// held until the process ends.  Host code never passes `scratch` itself to a
+// kernel (in host code the name is a stand-in, not a device address): it
+// takes the address of each device's copy with hipGetSymbolAddress, once per
+// device, and passes that.
+namespace {
+constexpr int NOALLOC_BLOCKS = LBM_MLP_NOALLOC_MAX_BATCH / 64;
+constexpr int NOALLOC_FLOATS = NOALLOC_BLOCKS * mlp::NP + NOALLOC_BLOCKS;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+__device__ __align__(256) float scratch[NOALLOC_FLOATS];
+
+std::mutex g_scratch_mutex;
+float *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// device address of the current device's scratch array (looked up on the
+// first call on that device)
+int scratch_address(float **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return lbm_note(hipGetLastError());
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return LBM_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return lbm_note(e != hipSuccess ? e : hipErrorInvalidSymbol);
+        g_scratch_ptr[dev] = (float *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+}  // namespace
+
 namespace {
 struct DevBuf {
     void *p = nullptr;
@@ -518,6 +554,20 @@ int lbm_mlp_loss_grad(const float *params, const float *xn, const float *tn, int
     // the scratch buffers are released when this call returns
     if (hipStreamSynchronize(s) != hipSuccess) return LBM_EDEVICE;
     return rc;
+}
+
+int lbm_mlp_loss_grad_noalloc(const float *params, const float *xn, const float *tn, int B, float *grad,
+                              float *loss, int precision, void *stream) {
+    if (B <= 0 || B % 64 || B > LBM_MLP_NOALLOC_MAX_BATCH || (precision != LBM_MLP_BF16 && precision != LBM_MLP_F32))
+        return LBM_EINVAL;
+    if (!params || !xn || !tn || !grad || !loss) return LBM_EINVAL;
+    float *sp = nullptr;
+    const int rc = scratch_address(&sp);
+    if (rc) return rc;
+    // every partial of the B / 64 blocks is written before it is summed, so
+    // nothing of a previous call's contents is read
+    return loss_grad_impl(params, xn, tn, B, grad, loss, precision, (hipStream_t)stream, sp,
+                          sp + (size_t)NOALLOC_BLOCKS * mlp::NP);
 }
 
 // Peng-Robinson specific energy e(rho, T) on the host (the same relation the

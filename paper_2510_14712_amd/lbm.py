@@ -86,6 +86,7 @@ def load():
         "lbm_eos_stats": ([_VP, _DP, _DP], ctypes.c_int),
         "lbm_mlp_forward": ([_VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP], ctypes.c_int),
         "lbm_mlp_loss_grad": ([_VP, _VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
+        "lbm_mlp_loss_grad_noalloc": ([_VP, _VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
         "lbm_mlp_adam": ([_VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_float, _VP], ctypes.c_int),
         "lbm_codec_encode": ([ctypes.c_int, _VP, _VP, _VP, ctypes.c_int64, _VP], ctypes.c_int),
         "lbm_codec_decode": ([ctypes.c_int, _VP, _VP, _VP, ctypes.c_int64, _VP], ctypes.c_int),
@@ -315,6 +316,23 @@ def mlp_loss_grad(params, xn, tn, precision=MLP_BF16, stream=None):
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
     _check(load().lbm_mlp_loss_grad(_ptr(pt), _ptr(xt), _ptr(tt), B, _ptr(grad), _ptr(loss), int(precision),
                                     _stream_ptr(stream)), "lbm_mlp_loss_grad")
+    return loss, grad
+
+
+def mlp_loss_grad_noalloc(params, xn, tn, precision=MLP_BF16, stream=None, out=None):
+    """lbm_mlp_loss_grad_noalloc: the library allocates nothing; `out` =
+    (loss[1], grad[4547]) float32 CUDA tensors to fill, else new ones."""
+    torch = _torch()
+    pt = _dev(params, torch.float32, MLP_NPARAMS)
+    xt = _dev(xn, torch.float32)
+    tt = _dev(tn, torch.float32)
+    B = xt.numel() // 2
+    if out is None:
+        out = (torch.empty(1, dtype=torch.float32, device="cuda"),
+               torch.empty(MLP_NPARAMS, dtype=torch.float32, device="cuda"))
+    loss, grad = out
+    _check(load().lbm_mlp_loss_grad_noalloc(_ptr(pt), _ptr(xt), _ptr(tt), B, _ptr(grad), _ptr(loss), int(precision),
+                                            _stream_ptr(stream)), "lbm_mlp_loss_grad_noalloc")
     return loss, grad
 
 
