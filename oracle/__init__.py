@@ -44,7 +44,8 @@ class _Params(ctypes.Structure):
                 ("k", ctypes.c_double), ("kappa", ctypes.c_double), ("upwind_eps", ctypes.c_double),
                 ("sc_cmu", ctypes.c_double), ("sc_ceta", ctypes.c_double), ("sc_ck", ctypes.c_double),
                 ("eos", ctypes.c_int), ("pr_m", ctypes.c_double), ("pr_Tc", ctypes.c_double),
-                ("pr_c0", ctypes.c_double), ("pr_c1", ctypes.c_double)]
+                ("pr_c0", ctypes.c_double), ("pr_c1", ctypes.c_double),
+                ("wall_u", (ctypes.c_double * 3) * 2), ("wall_T", ctypes.c_double * 2)]
 
 
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -122,7 +123,8 @@ class Params:
     """Lattice and physical parameters (lattice units)."""
 
     def __init__(self, D, shape, bc=(0, 0, 0), a=3.0 / 49.0, b=2.0 / 21.0, R=1.0, cv=2.5,
-                 mu=0.05, eta=0.05, k=None, kappa=0.01, upwind_eps=UPWIND_EPS, sc=(0.0, 0.0, 0.0), pr=None):
+                 mu=0.05, eta=0.05, k=None, kappa=0.01, upwind_eps=UPWIND_EPS, sc=(0.0, 0.0, 0.0), pr=None,
+                 walls=None):
         nx, ny = shape[0], shape[1]
         nz = shape[2] if D == 3 else 1
         self.D, self.nx, self.ny, self.nz = D, nx, ny, nz
@@ -134,6 +136,8 @@ class Params:
         self.upwind_eps = upwind_eps
         # shock-capturing coefficients (C_mu, C_eta, C_k) of Section 4.4; zeros: off
         self.sc = tuple(float(v) for v in sc)
+        # walls (bc 2 on x): ((u_lo, T_lo), (u_hi, T_hi)) with u a D-vector
+        self.walls = walls
         # Peng-Robinson: dict(m, Tc, c0, c1) with a, b, R its constants; None: van der Waals
         self.pr = dict(pr) if pr is not None else None
         if self.pr is not None:
@@ -156,6 +160,11 @@ class Params:
         s.mu, s.eta, s.k, s.kappa = self.mu, self.eta, self.k, self.kappa
         s.upwind_eps = self.upwind_eps
         s.sc_cmu, s.sc_ceta, s.sc_ck = self.sc
+        if self.walls is not None:
+            for side, (uw, Tw) in enumerate(self.walls):
+                for a, v in enumerate(uw):
+                    s.wall_u[side][a] = float(v)
+                s.wall_T[side] = float(Tw)
         if self.pr is not None:
             s.eos = 1
             s.pr_m, s.pr_Tc, s.pr_c0, s.pr_c1 = (float(self.pr[k]) for k in ("m", "Tc", "c0", "c1"))

@@ -254,14 +254,15 @@ static int check_params(const oracle_params *p) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return -1;
     if (p->D == 2 && p->nz != 1) return -1;
     for (int a = 0; a < 3; a++)
-        if (p->bc[a] != 0 && p->bc[a] != 1) return -1;
+        if (p->bc[a] != 0 && p->bc[a] != 1 && !(p->bc[a] == 2 && a == 0)) return -1;
+    if (p->bc[0] == 2 && (p->bc[1] != 0 || p->bc[2] != 0)) return -1; /* walls: periodic y, z */
     return 0;
 }
 
 static int coord(int x, int n, int bc) {
     if (x >= 0 && x < n) return x;
     if (bc == 0) return ((x % n) + n) % n; /* periodic */
-    return x < 0 ? 0 : n - 1;               /* zero-gradient: clamp */
+    return x < 0 ? 0 : n - 1;               /* zero-gradient (and wall): clamp */
 }
 
 /* index of the cell at (x, y, z) + (dx, dy, dz) under the boundary rules */
@@ -279,6 +280,41 @@ static long nbr_axis(const oracle_params *p, long idx, int a, int s) {
     int d[3] = {0, 0, 0};
     d[a] = s;
     return nbr(p, idx, d[0], d[1], d[2]);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Walls (bc 2 on the x axis), for the thermal Couette flow of Section 4.1, */
+/* whose wall treatment the paper does not state.  Reading: diffuse         */
+/* reflection.  Each ghost cell beyond a wall (x = -1, x = nx) absorbs the  */
+/* populations that leave the domain into it and re-emits equilibria of the */
+/* wall state -- velocity u_w, temperature T_w, and the thermodynamic state */
+/* of the boundary cell next to it (theta_w = P(rho_b, T_w)/rho_b, e_w =    */
+/* e(rho_b, T_w)) -- scaled so that the ghost emits the mass it absorbed    */
+/* (no mass crosses the wall).  The central differences of u, T, h and      */
+/* Lambda at the boundary cell take the ghost's values (with rho_b); rho    */
+/* and its Laplacian, and the shock-capturing stencils, stay zero-gradient. */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    double u[3], T, theta, e, h;
+} ghost_state;
+
+static ghost_state wall_ghost(const oracle_params *p, int side, double rho_g) {
+    ghost_state gs;
+    double q[5];
+    for (int a = 0; a < 3; a++) gs.u[a] = p->wall_u[side][a];
+    gs.T = p->wall_T[side];
+    oracle_eos(p, rho_g, gs.T, q);
+    gs.theta = q[0] / rho_g;
+    gs.e = q[1];
+    gs.h = gs.e + gs.theta;
+    return gs;
+}
+
+/* side of the wall the neighbour x + s e_a lies beyond (0 low, 1 high), or -1 */
+static int beyond_wall(const oracle_params *p, long idx, int a, int s) {
+    if (a != 0 || p->bc[0] != 2) return -1;
+    int x = (int)(idx % p->nx) + s;
+    return x < 0 ? 0 : (x >= p->nx ? 1 : -1);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -544,14 +580,28 @@ static void collide_all(const oracle_params *p, const double *f, const double *g
         double divu = 0.0, gh[3] = {0, 0, 0}, gT[3] = {0, 0, 0}, Phi[3] = {0, 0, 0};
         for (int a = 0; a < D; a++) {
             long xp = nbr_axis(p, x, a, +1), xm = nbr_axis(p, x, a, -1);
-            divu += 0.5 * (w->u[a * N + xp] - w->u[a * N + xm]);
-            gh[a] = 0.5 * (w->h[xp] - w->h[xm]);
-            gT[a] = 0.5 * (w->T[xp] - w->T[xm]);
+            /* u_a, h, T, Lambda_a at x - e_a (index 0) and x + e_a (1): the
+             * neighbours', or a wall ghost's */
+            double nu[2] = {w->u[a * N + xm], w->u[a * N + xp]};
+            double nh[2] = {w->h[xm], w->h[xp]}, nT[2] = {w->T[xm], w->T[xp]};
+            double nL[2] = {w->Lam[a * N + xm], w->Lam[a * N + xp]};
+            for (int k = 0; k < 2; k++) {
+                int side = beyond_wall(p, x, a, k ? 1 : -1);
+                if (side < 0) continue;
+                ghost_state gs = wall_ghost(p, side, rho);
+                nu[k] = gs.u[a];
+                nh[k] = gs.h;
+                nT[k] = gs.T;
+                nL[k] = rho * gs.u[a] * gs.u[a] * gs.u[a] + 3.0 * rho * gs.u[a] * (gs.theta - LATTICE_SOUND_SPEED_SQ);
+            }
+            divu += 0.5 * (nu[1] - nu[0]);
+            gh[a] = 0.5 * (nh[1] - nh[0]);
+            gT[a] = 0.5 * (nT[1] - nT[0]);
             /* upwind-biased derivative of Lambda_a by the sign of u_a at x,
              * then Phi_aa = -(1/rho) d_a Lambda_a (eq. correction) */
             double s = sgn(u[a], p->upwind_eps);
-            double dL = 0.5 * (1.0 + s) * (w->Lam[a * N + x] - w->Lam[a * N + xm])
-                      + 0.5 * (1.0 - s) * (w->Lam[a * N + xp] - w->Lam[a * N + x]);
+            double dL = 0.5 * (1.0 + s) * (w->Lam[a * N + x] - nL[0])
+                      + 0.5 * (1.0 - s) * (nL[1] - w->Lam[a * N + x]);
             Phi[a] = -dL / rho;
             w->Phi[a * N + x] = Phi[a];
         }
@@ -664,9 +714,64 @@ int oracle_collide(const oracle_params *p, const double *f, const double *g,
     return 0;
 }
 
+/* the populations a wall ghost emits replace what the clamped pull read:
+ * f_i(x) for x - c_i beyond the wall comes from the ghost at x - c_i.  That
+ * ghost absorbed the post-collision populations f'_j (pointing out through
+ * the wall) of the boundary cells x_g - c_j (x_g: the ghost's position) and
+ * emits m / s times the equilibria of the wall state at the boundary cell
+ * next to it, where m is the absorbed mass and s the sum of the emitted
+ * equilibria per unit density */
+static void wall_inflow(const oracle_params *p, const work_fields *w, const double *fpost, double *f, double *g) {
+    const int D = p->D, Q = num_vel(D);
+    const long N = (long)p->nx * p->ny * p->nz;
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < N; x++) {
+        for (int i = 0; i < Q; i++) {
+            int c[3];
+            vel(D, i, c);
+            int side = beyond_wall(p, x, 0, -c[0]);
+            if (side < 0) continue;
+            /* the ghost sits at x - c_i; the boundary cell next to it is the
+             * same position with x clamped into the domain */
+            long adj = nbr(p, x, -c[0], -c[1], -c[2]);
+            double rho_b = w->rho[adj];
+            ghost_state gs = wall_ghost(p, side, rho_b);
+            /* absorbed mass: populations j with c_jx pointing through this
+             * wall, from the boundary cells adj - (c_jy, c_jz) */
+            double m = 0.0;
+            for (int j = 0; j < Q; j++) {
+                int cj[3];
+                vel(D, j, cj);
+                if (cj[0] != -c[0]) continue;
+                long src = nbr(p, adj, 0, -cj[1], -cj[2]);
+                m += fpost[j * N + src];
+            }
+            double feq[27], geq[27], sm = 0.0;
+            oracle_feq(D, 1.0, gs.u, gs.theta, feq);
+            for (int j = 0; j < Q; j++) {
+                int cj[3];
+                vel(D, j, cj);
+                if (cj[0] == c[0]) sm += feq[j];
+            }
+            double rho_g = m / sm;
+            oracle_feq(D, rho_g, gs.u, gs.theta, feq);
+            oracle_geq(D, rho_g, gs.u, gs.e, gs.theta, geq);
+            f[i * N + x] = feq[i];
+            g[i * N + x] = geq[i];
+        }
+    }
+}
+
+static int stream_pull(const oracle_params *p, const double *fpost, const double *gpost, double *f, double *g);
+
 int oracle_stream(const oracle_params *p, const double *fpost, const double *gpost,
                   double *f, double *g) {
-    if (check_params(p)) return -1;
+    if (check_params(p) || p->bc[0] == 2) return -1;
+    return stream_pull(p, fpost, gpost, f, g);
+}
+
+static int stream_pull(const oracle_params *p, const double *fpost, const double *gpost,
+                       double *f, double *g) {
     const int D = p->D, Q = num_vel(D);
     const long N = (long)p->nx * p->ny * p->nz;
     /* f_i(x + c_i, t + 1) = f'_i(x, t), written as a pull from x - c_i */
@@ -695,7 +800,8 @@ int oracle_run(const oracle_params *p, double *f, double *g, int nsteps) {
     for (int s = 0; s < nsteps; s++) {
         compute_fields(p, f, g, &w);
         collide_all(p, f, g, &w, fp, gp);
-        oracle_stream(p, fp, gp, f, g);
+        stream_pull(p, fp, gp, f, g);
+        if (p->bc[0] == 2) wall_inflow(p, &w, fp, f, g);
     }
     work_free(&w);
     free(fp);

@@ -28,7 +28,8 @@ extern "C" {
 typedef struct {
     int D;              /* 2 or 3 */
     int nx, ny, nz;     /* nz must be 1 for D = 2 */
-    int bc[3];          /* per axis: 0 periodic, 1 zero-gradient */
+    int bc[3];          /* per axis: 0 periodic, 1 zero-gradient, 2 wall
+                           (x axis only; see wall_u, wall_T) */
     double a, b, R, cv; /* van der Waals constants and isochoric heat */
     double mu, eta, k;  /* shear, bulk viscosity, thermal conductivity */
     double kappa;       /* capillarity coefficient */
@@ -41,6 +42,8 @@ typedef struct {
                            with a, b, R and the fields below (cv unused) */
     double pr_m, pr_Tc; /* Peng-Robinson alpha(T) = (1 + m (1 - sqrt(T/Tc)))^2 */
     double pr_c0, pr_c1; /* ideal-gas heat capacity c_v0(T) = c0 + c1 T */
+    double wall_u[2][3]; /* wall velocities at x = -1 ([0]) and x = nx ([1]) */
+    double wall_T[2];    /* wall temperatures there */
 } oracle_params;
 
 /* Per-cell fields produced while evaluating one step (all length N or D*N). */
@@ -65,7 +68,9 @@ int oracle_fields_eval(const oracle_params *p, const double *f, const double *g,
 int oracle_collide(const oracle_params *p, const double *f, const double *g,
                    double *fpost, double *gpost, oracle_fields *out);
 
-/* Pull streaming of post-collision populations into the state arrays. */
+/* Pull streaming of post-collision populations into the state arrays
+ * (periodic and zero-gradient axes; a wall axis needs the fields of the step
+ * and is streamed by oracle_run: returns -1). */
 int oracle_stream(const oracle_params *p, const double *fpost,
                   const double *gpost, double *f, double *g);
 
