@@ -53,6 +53,16 @@ extern "C" {
 /* ---- enumerations ------------------------------------------------------ */
 #define LBM_BC_PERIODIC 0
 #define LBM_BC_ZEROGRAD 1
+/* Walls at x = -1 and x = nx (x axis only, y and z periodic): diffuse
+ * reflection -- each ghost cell beyond a wall absorbs the populations that
+ * leave the domain into it and re-emits the equilibria of the wall state
+ * (wall_u, wall_T, and the boundary cell's density for the thermodynamics),
+ * scaled to the absorbed mass, so no mass crosses the wall; central
+ * differences of u, T, h, Lambda at a boundary cell take the ghost's values,
+ * those of rho stay zero-gradient.  The wall treatment of the paper's thermal
+ * Couette flow (Section 4.1) is not stated; this is the reading taken.
+ * Takes the multi-kernel path. */
+#define LBM_BC_WALL 2
 
 /* population storage; arithmetic is FP64 for LBM_STORE_F64 and FP32 for the
  * others.  The two 16-bit forms store f_i - f_i^ref (and g_i - g_i^ref) with
@@ -115,6 +125,8 @@ typedef struct {
     double pr_m, pr_Tc, pr_c0, pr_c1; /* Peng-Robinson modes: alpha(T) slope m,
                                critical temperature, ideal-gas heat capacity
                                c_v0 = c0 + c1 T */
+    double wall_u[2][3];    /* LBM_BC_WALL: wall velocities at x = -1 ([0]) and x = nx ([1]) */
+    double wall_T[2];       /* LBM_BC_WALL: wall temperatures */
     double sc_cmu, sc_ceta, sc_ck; /* shock-capturing numerical transport
                                (Section 4.4, eqs. shock_cap, shock_cap_k, r = 5):
                                mu, eta, k of each cell gain rho C_mu fS,

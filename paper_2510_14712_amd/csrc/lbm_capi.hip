@@ -436,6 +436,22 @@ template <int D, class S> struct Impl {
         *fS = fl.sc[src];
         *fs = fl.sc[src + 1];
     }
+    // collide and stream into buffer nxt (multi-kernel path), then what the
+    // wall ghosts emit
+    static void collide_launch(lbm_ctx *c, Fields<C> fl, const C *fS, const C *fs, int nxt) {
+        Walls w;
+        for (int s = 0; s < 2; s++) {
+            for (int a = 0; a < 3; a++) w.u[s][a] = c->p.wall_u[s][a];
+            w.T[s] = c->p.wall_T[s];
+        }
+        hipLaunchKernelGGL((k_collide<D, S>), cell_grid(c), dim3(BX), 0, c->stream, c->grid, make_phys<C>(c->p),
+                           c->ref, (const T *)c->f[c->cur], (const T *)c->g[c->cur], fl, (T *)c->f[nxt],
+                           (T *)c->g[nxt], fS, fs, w, (C *)c->ghost);
+        if (c->grid.wallx)
+            hipLaunchKernelGGL((k_wall_emit<D, S>), dim3((unsigned)((c->p.ny + 63) / 64), (unsigned)c->p.nz, 2u),
+                               dim3(64), 0, c->stream, c->grid, make_phys<C>(c->p), c->ref, w, fl,
+                               (const C *)c->ghost, (T *)c->f[nxt], (T *)c->g[nxt]);
+    }
     static int step(lbm_ctx *c, int n) {
         Fields<C> fl = get_fields<C>(c);
         dim3 gr = cell_grid(c);
@@ -450,9 +466,7 @@ template <int D, class S> struct Impl {
                 const C *fS, *fs;
                 sc_passes(c, &fS, &fs);
                 int nxt = 1 - c->cur;
-                hipLaunchKernelGGL((k_collide<D, S>), gr, dim3(BX), 0, c->stream, c->grid, make_phys<C>(c->p), c->ref,
-                                   (const T *)c->f[c->cur], (const T *)c->g[c->cur], fl, (T *)c->f[nxt],
-                                   (T *)c->g[nxt], fS, fs);
+                collide_launch(c, fl, fS, fs, nxt);
                 rc = last_launch();
                 c->cur = nxt;
             }
@@ -519,9 +533,7 @@ template <int D, class S> struct Impl {
             sc_passes(c, &fS, &fs);  // timed with the fields kind
             (void)hipEventRecord(ev[3], c->stream);
             int nxt = 1 - c->cur;
-            hipLaunchKernelGGL((k_collide<D, S>), gr, dim3(BX), 0, c->stream, c->grid, make_phys<C>(c->p), c->ref,
-                               (const T *)c->f[c->cur], (const T *)c->g[c->cur], fl, (T *)c->f[nxt], (T *)c->g[nxt],
-                               fS, fs);
+            collide_launch(c, fl, fS, fs, nxt);
             (void)hipEventRecord(ev[4], c->stream);
             if (rc == LBM_OK) rc = last_launch();
             c->cur = nxt;
@@ -683,7 +695,15 @@ static int validate(const lbm_params *p) {
     if (p->lattice == 2 && p->nz != 1) return LBM_EINVAL;
     if (p->ny > 65535 || p->nz > 65535) return LBM_EINVAL;
     for (int a = 0; a < 3; a++)
-        if (p->bc[a] != LBM_BC_PERIODIC && p->bc[a] != LBM_BC_ZEROGRAD) return LBM_EINVAL;
+        if (p->bc[a] != LBM_BC_PERIODIC && p->bc[a] != LBM_BC_ZEROGRAD && !(a == 0 && p->bc[a] == LBM_BC_WALL))
+            return LBM_EINVAL;
+    if (p->bc[0] == LBM_BC_WALL) {
+        if (p->bc[1] != LBM_BC_PERIODIC || p->bc[2] != LBM_BC_PERIODIC) return LBM_EINVAL;
+        for (int s = 0; s < 2; s++)
+            if (!(p->wall_T[s] > 0) || !std::isfinite(p->wall_u[s][0]) || !std::isfinite(p->wall_u[s][1]) ||
+                !std::isfinite(p->wall_u[s][2]))
+                return LBM_EINVAL;
+    }
     if (p->storage < LBM_STORE_F64 || p->storage > LBM_STORE_F16) return LBM_EINVAL;
     if (p->eos < LBM_EOS_VDW || p->eos > LBM_EOS_PR_MLP) return LBM_EINVAL;
     if (lbm_eos_uses_mlp(p->eos) && p->storage == LBM_STORE_F64) return LBM_EINVAL;
@@ -716,7 +736,8 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
     c->Q = c->D == 2 ? 9 : 27;
     c->stream = (hipStream_t)params->stream;
     c->grid.nx = params->nx; c->grid.ny = params->ny; c->grid.nz = params->nz;
-    c->grid.clampx = params->bc[0]; c->grid.clampy = params->bc[1]; c->grid.clampz = params->bc[2];
+    c->grid.clampx = params->bc[0] != LBM_BC_PERIODIC; c->grid.clampy = params->bc[1]; c->grid.clampz = params->bc[2];
+    c->grid.wallx = params->bc[0] == LBM_BC_WALL;
     c->grid.N = (long long)params->nx * params->ny * params->nz;
     const long long N = c->grid.N;
     int sb = params->storage == LBM_STORE_F64 ? 8 : (params->storage == LBM_STORE_F32 ? 4 : 2);
@@ -749,7 +770,15 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
     }
     // the single-pass step covers periodic z (and every D = 2 lattice)
     // with the van der Waals equation of state, without shock capturing
-    c->fused = (c->D == 2 || params->bc[2] == LBM_BC_PERIODIC) && !c->sc && !lbm_eos_is_pr(params->eos);
+    c->fused = (c->D == 2 || params->bc[2] == LBM_BC_PERIODIC) && !c->sc && !lbm_eos_is_pr(params->eos) &&
+               params->bc[0] != LBM_BC_WALL;
+    if (ok && c->grid.wallx)
+        ok = hipMalloc(&c->ghost, (size_t)2 * params->ny * params->nz * c->Q * cb) == hipSuccess;
+    if (!ok) {
+        lbm_note(hipGetLastError());
+        lbm_destroy(c);
+        return LBM_ENOMEM;
+    }
     if (c->fused) {
         auto tiles = [&]() { DISPATCH_VOID(c, tiles(c)); };
         tiles();
@@ -786,7 +815,7 @@ void lbm_destroy(lbm_ctx *c) {
     else (void)hipDeviceSynchronize();
     void *ptrs[] = {c->f[0], c->f[1], c->work, c->red_partials, c->red_out,
                     c->mlp_counters, c->mlp_params, c->mlp_norm, c->mlp_w2b, c->Mc[0], c->Mc[1], c->IN[0], c->IN[1],
-                    c->Tsur};
+                    c->Tsur, c->ghost};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;

@@ -140,6 +140,13 @@ struct Grid {
     int nx, ny, nz;
     int clampx, clampy, clampz;
     long long N;
+    int wallx;  // 1: diffuse-reflection walls at x = -1 and x = nx (clampx is then 1 too)
+};
+
+// wall states of the x walls: [0] at x = -1, [1] at x = nx
+struct Walls {
+    double u[2][3];
+    double T[2];
 };
 
 // Internal population layout: plane-major, with f_i and g_i of a cell side by

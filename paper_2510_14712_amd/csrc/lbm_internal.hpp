@@ -19,6 +19,7 @@ struct lbm_ctx {
     hipStream_t stream = nullptr;
     bool initialized = false;
     bool sc = false;                  // shock-capturing numerical transport on
+    void *ghost = nullptr;            // LBM_BC_WALL: populations leaving through the walls [2][ny nz][Q]
     long long steps_done = 0;         // steps since the last init / set_populations (check interval)
     bool T_valid = false;             // the field array T holds the current state's temperature
     bool mlp_ready = false;

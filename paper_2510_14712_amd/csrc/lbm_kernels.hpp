@@ -319,15 +319,97 @@ __global__ void __launch_bounds__(BX) k_sc_filter(Grid g, int axis, ScFilter<C> 
 }
 
 // ---------------------------------------------------------------------------
+// Diffuse-reflection walls at x = -1 and x = nx (the thermal Couette flow of
+// Section 4.1; the paper does not state its wall treatment).  Each ghost cell
+// beyond a wall absorbs the populations leaving the domain into it and
+// re-emits equilibria of the wall state -- u_w, T_w, and the thermodynamics of
+// the boundary cell next to it (theta_w = P(rho_b, T_w)/rho_b, e_w = e(rho_b,
+// T_w)) -- scaled to the absorbed mass, so no mass crosses the wall.  The
+// central differences of u, T, h and Lambda at a boundary cell take the
+// ghost's values; rho, its Laplacian and the shock-capturing stencils stay
+// zero-gradient.  k_collide writes the leaving post-collision populations to
+// the ghost buffer gb[side][(z ny + y) Q + i]; k_wall_emit then writes what
+// each ghost emits.
+template <class C> struct WallGhost {
+    C u[3], T, theta, e, h;
+};
+template <class C> __device__ __forceinline__ WallGhost<C> wall_ghost(const Phys<C> &ph, const Walls &w, int side,
+                                                                      C rho_b) {
+    WallGhost<C> gs;
+    for (int a = 0; a < 3; a++) gs.u[a] = (C)w.u[side][a];
+    gs.T = (C)w.T[side];
+    C P, e;
+    if (ph.pr) {
+        const EosPoint q = pr_eos(ph, (double)rho_b, (double)gs.T);
+        P = (C)q.P;
+        e = (C)q.e;
+    } else {
+        P = vdw_pressure(ph, rho_b, gs.T);
+        e = ph.cv * gs.T - ph.a * rho_b;
+    }
+    gs.theta = P / rho_b;
+    gs.e = e;
+    gs.h = e + gs.theta;
+    return gs;
+}
+
+template <int D, class S>
+__global__ void __launch_bounds__(64) k_wall_emit(Grid g, Phys<typename S::C> ph, RefPops ref, Walls w,
+                                                  Fields<typename S::C> fl, const typename S::C *__restrict__ gb,
+                                                  typename S::T *__restrict__ fo, typename S::T *__restrict__ go) {
+    using C = typename S::C;
+    constexpr int Q = Lattice<D>::Q;
+    const int yg = blockIdx.x * 64 + threadIdx.x, zg = blockIdx.y, side = blockIdx.z;
+    if (yg >= g.ny) return;
+    const int xb = side ? g.nx - 1 : 0;
+    const int cin = side ? -1 : 1;  // x component of the emitted directions
+    const C rho_b = fl.rho[cell_index<D>(g, xb, yg, zg)];
+    const WallGhost<C> gs = wall_ghost(ph, w, side, rho_b);
+    const C *src = gb + ((size_t)side * g.ny * g.nz + (size_t)zg * g.ny + yg) * Q;
+    C m = 0;
+    for (int j = 0; j < Q; j++)
+        if (cx_of(j) == -cin) m += src[j];
+    AxisEq<C> ax[3];
+    for (int a = 0; a < D; a++) ax[a] = axis_eq(gs.u[a], gs.theta);
+    auto pz_of = [&](int i) { return D == 3 ? pick(ax[2].p, cz_of(i)) : C(1); };
+    C sm = 0;
+    for (int j = 0; j < Q; j++)
+        if (cx_of(j) == cin) sm += pick(ax[0].p, cx_of(j)) * pick(ax[1].p, cy_of(j)) * pz_of(j);
+    const C rg = m / sm;
+    const C eps = gs.e - C(0.5 * D) * gs.theta;
+    for (int i = 0; i < Q; i++) {
+        if (cx_of(i) != cin) continue;
+        const C px = pick(ax[0].p, cx_of(i)), py = pick(ax[1].p, cy_of(i));
+        const C qx = pick(ax[0].q, cx_of(i)), qy = pick(ax[1].q, cy_of(i));
+        C feq, gsum;
+        if (D == 2) {
+            feq = rg * px * py;
+            gsum = qx * py + px * qy;
+        } else {
+            const C pz = pick(ax[2].p, cz_of(i)), qz = pick(ax[2].q, cz_of(i));
+            feq = rg * px * py * pz;
+            gsum = (qx * py + px * qy) * pz + px * py * qz;
+        }
+        const C geq = feq * eps + C(0.5) * rg * gsum;
+        const int yd = wrap1(yg + cy_of(i), g.ny, 0), zd = D == 3 ? wrap1(zg + cz_of(i), g.nz, 0) : 0;
+        const long long d = pop_index<Q>(g, i, zd, xb + (long long)g.nx * yd);
+        fo[d] = S::enc(feq, (C)ref.f[i]);
+        go[d] = S::enc(geq, (C)ref.g[i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // fS, fs: filtered |grad^4 S| and |grad^4 |grad s|| of the shock-capturing
-// passes, or null without shock capturing
+// passes, or null without shock capturing; w, gb: wall states and ghost
+// buffer (used when g.wallx)
 template <int D, class S>
 __global__ void __launch_bounds__(BX) k_collide(Grid g, Phys<typename S::C> ph, RefPops ref,
                                                 const typename S::T *__restrict__ fi,
                                                 const typename S::T *__restrict__ gi, Fields<typename S::C> fl,
                                                 typename S::T *__restrict__ fo, typename S::T *__restrict__ go,
                                                 const typename S::C *__restrict__ fS,
-                                                const typename S::C *__restrict__ fs) {
+                                                const typename S::C *__restrict__ fs, Walls w,
+                                                typename S::C *__restrict__ gb) {
     using C = typename S::C;
     constexpr int Q = Lattice<D>::Q;
     int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
@@ -354,16 +436,30 @@ __global__ void __launch_bounds__(BX) k_collide(Grid g, Phys<typename S::C> ph, 
         u[a] = fl.u[a * N + c];
         F[a] = fl.F[a * N + c];
         FF += F[a] * F[a];
-        divu += C(0.5) * (fl.u[a * N + cp] - fl.u[a * N + cm]);
-        C dh = C(0.5) * (fl.h[cp] - fl.h[cm]);
-        C dT = C(0.5) * (fl.T[cp] - fl.T[cm]);
+        // u_a, h, T, Lambda_a at x - e_a ([0]) and x + e_a ([1]): the
+        // neighbours', or a wall ghost's
+        C nu[2] = {fl.u[a * N + cm], fl.u[a * N + cp]}, nh[2] = {fl.h[cm], fl.h[cp]};
+        C nT[2] = {fl.T[cm], fl.T[cp]}, nL[2] = {fl.Lam[a * N + cm], fl.Lam[a * N + cp]};
+        if (a == 0 && g.wallx) {
+            for (int k = 0; k < 2; k++) {
+                if (!(k == 0 ? x == 0 : x == g.nx - 1)) continue;
+                const WallGhost<C> gs = wall_ghost(ph, w, k, rho);
+                nu[k] = gs.u[0];
+                nh[k] = gs.h;
+                nT[k] = gs.T;
+                nL[k] = rho * gs.u[0] * gs.u[0] * gs.u[0] + C(3) * rho * gs.u[0] * (gs.theta - C(1.0 / 3.0));
+            }
+        }
+        divu += C(0.5) * (nu[1] - nu[0]);
+        C dh = C(0.5) * (nh[1] - nh[0]);
+        C dT = C(0.5) * (nT[1] - nT[0]);
         qc[a] = P * (dh - k_over_mu * dT);                     // eq. qc_1
         // upwind-biased d_a Lambda_a by sgn(u_a); |u_a| <= eps gives the average
         C L0 = fl.Lam[a * N + c];
         C dL;
-        if (u[a] > ph.sgn_eps) dL = L0 - fl.Lam[a * N + cm];
-        else if (u[a] < -ph.sgn_eps) dL = fl.Lam[a * N + cp] - L0;
-        else dL = C(0.5) * (fl.Lam[a * N + cp] - fl.Lam[a * N + cm]);
+        if (u[a] > ph.sgn_eps) dL = L0 - nL[0];
+        else if (u[a] < -ph.sgn_eps) dL = nL[1] - L0;
+        else dL = C(0.5) * (nL[1] - nL[0]);
         Phi[a] = -dL * inv_rho;                                // eq. correction
     }
     C beta = P / (P + C(2) * mu);                              // eq. beta_main with tau = mu / P
@@ -430,7 +526,19 @@ __global__ void __launch_bounds__(BX) k_collide(Grid g, Phys<typename S::C> ph, 
         C gn = w_keep * gg + w_eq * geq + w_st * gst;
         typename S::T fe = S::enc(fn, (C)ref.f[i]), ge = S::enc(gn, (C)ref.g[i]);
         int dx[2], dy[2], dz[2] = {0, 0};
-        int nxd = push_axis(x, ix, g.nx, g.clampx, dx);
+        int nxd;
+        if (g.wallx) {
+            // walls: a population leaving through one goes to its ghost
+            const int xd = x + ix;
+            nxd = (xd >= 0 && xd < g.nx) ? 1 : 0;
+            dx[0] = xd;
+            if (!nxd) {
+                const int yg = wrap1(y + iy, g.ny, 0), zg = D == 3 ? wrap1(z + iz, g.nz, 0) : 0;
+                gb[((size_t)(xd < 0 ? 0 : 1) * g.ny * g.nz + (size_t)zg * g.ny + yg) * Q + i] = fn;
+            }
+        } else {
+            nxd = push_axis(x, ix, g.nx, g.clampx, dx);
+        }
         int nyd = push_axis(y, iy, g.ny, g.clampy, dy);
         int nzd = D == 3 ? push_axis(z, iz, g.nz, g.clampz, dz) : 1;
         for (int a = 0; a < nxd; a++)

@@ -42,6 +42,7 @@ class _Params(ctypes.Structure):
                 ("upwind_eps", ctypes.c_double), ("zsegments", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("pr_m", ctypes.c_double), ("pr_Tc", ctypes.c_double), ("pr_c0", ctypes.c_double),
                 ("pr_c1", ctypes.c_double),
+                ("wall_u", (ctypes.c_double * 3) * 2), ("wall_T", ctypes.c_double * 2),
                 ("sc_cmu", ctypes.c_double), ("sc_ceta", ctypes.c_double), ("sc_ck", ctypes.c_double)]
 
 
@@ -140,7 +141,8 @@ class Lattice:
 
     def __init__(self, lattice, shape, bc=(0, 0, 0), a=3.0 / 49.0, b=2.0 / 21.0, R=1.0, cv=2.5, mu=0.05,
                  eta=0.05, k=None, kappa=0.01, storage="f32", eos="vdw", mlp_tol=1e-6, ref_rho=0.0, ref_T=0.0,
-                 stream=None, upwind_eps=UPWIND_EPS, zsegments=0, check_every=0, sc=(0.0, 0.0, 0.0), pr=None):
+                 stream=None, upwind_eps=UPWIND_EPS, zsegments=0, check_every=0, sc=(0.0, 0.0, 0.0), pr=None,
+                 walls=None):
         L = load()
         self.D = int(lattice)
         nx, ny = int(shape[0]), int(shape[1])
@@ -164,6 +166,11 @@ class Lattice:
         p.zsegments = int(zsegments)
         p.check_every = int(check_every)
         p.sc_cmu, p.sc_ceta, p.sc_ck = (float(v) for v in sc)  # shock capturing (C_mu, C_eta, C_k)
+        if walls is not None:  # bc[0] = 2: ((u_lo, T_lo), (u_hi, T_hi)) of the x walls
+            for side, (uw, Tw) in enumerate(walls):
+                for a, v in enumerate(uw):
+                    p.wall_u[side][a] = float(v)
+                p.wall_T[side] = float(Tw)
         if pr is not None:  # Peng-Robinson constants dict(m, Tc, c0, c1); a, b, R above
             p.pr_m, p.pr_Tc, p.pr_c0, p.pr_c1 = (float(pr[k]) for k in ("m", "Tc", "c0", "c1"))
         self._stream = stream
