@@ -161,6 +161,35 @@ def cpu_baseline(st, seconds_target=12.0):
             "single_thread": {"value": round(st1, 4), "unit": "MLUPS", "cores": 1}}
 
 
+def hbm_probe(lbm, torch):
+    """Ceiling of the access pattern-free HBM streams on this GPU: GB/s of the
+    library's read / write / copy probes (16-byte accesses, non-temporal
+    hint) per workgroups-per-CU setting, and of the runtime's device copy."""
+    nbytes = 4 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    out = {"bytes": nbytes, "probes": {}}
+    for kind, name, moved in ((0, "read", 1), (1, "write", 1), (2, "copy", 2)):
+        row = {}
+        for bpc in (1, 2, 4, 8, 16, 32):
+            ms = lbm.hbm_probe(kind, src, dst, bpc, iters=10)
+            row[bpc] = round(moved * nbytes / (ms * 1e-3) / 1e9, 1)
+        out["probes"][name] = row
+        _p(f"{name}: GB/s by workgroups per CU {row}")
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    dst.copy_(src)
+    t0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    out["runtime_copy_gbs"] = round(2 * nbytes / (t0.elapsed_time(t1) / 10 * 1e-3) / 1e9, 1)
+    out["peak_gbs"] = HBM_PEAK_GBS
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +200,9 @@ def main():
     ap.add_argument("--forms", default="plain,bf16vdw,surrogate", help="comma list of forms to time")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--hbm-probe", action="store_true",
+                    help="only measure the HBM ceiling: read, write and copy probes over 4 GiB, "
+                         "workgroups per compute unit swept, beside the runtime's copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1",
@@ -190,6 +222,9 @@ def main():
     from paper_2510_14712_amd import inputs, lbm
     lbm.load()
     torch.cuda.set_device(0)
+    if args.hbm_probe:
+        hbm_probe(lbm, torch)
+        return
     st = inputs.states()
     wl = {"tgv512": "tgv_3d_512", "tgv256": "tgv_3d_256", "drop3d": "shock_drop_3d"}[args.workload]
     kw = inputs.physics(st, wl)
@@ -197,7 +232,18 @@ def main():
     N = int(np.prod(shape))
 
     forms = args.forms.split(",")
-    plain = bvdw = None
+    plain = bvdw = surr = None
+    # the value form first, on a device whose memory no earlier form has
+    # fragmented (a form timed after others' large allocations and frees ran
+    # its fused kernel up to 6 % slower)
+    if "surrogate" in forms:
+        _p("training the surrogate EOS on the GPU")
+        params, norm, loss, t_train = train_surrogate(st, lbm)
+        _p(f"  loss {loss:.3e} in {t_train:.1f} s")
+        _p("surrogate + BF16 deviation form")
+        surr = time_form(lbm, torch, shape, bc, fields, ref, kw, "bf16", "mlp", args.steps, args.warmup,
+                         mlp=(params, norm))
+        _p(f"  {surr['mlups']:.0f} MLUPS, kernels {surr['kernel_ms']}, fallback {surr['fallback_fraction']}")
     if "plain" in forms:
         _p(f"plain FP32 form on {shape}")
         plain = time_form(lbm, torch, shape, bc, fields, ref, kw, "f32", "vdw", args.steps, args.warmup)
@@ -206,18 +252,8 @@ def main():
         _p("BF16 deviation form, explicit van der Waals EOS")
         bvdw = time_form(lbm, torch, shape, bc, fields, ref, kw, "bf16", "vdw", args.steps, args.warmup)
         _p(f"  {bvdw['mlups']:.0f} MLUPS, kernels {bvdw['kernel_ms']}")
-    if "surrogate" not in forms:
-        print(json.dumps({"forms": {"plain_fp32": plain, "bf16_vdw": bvdw}}), flush=True)
-        return
-    _p("training the surrogate EOS on the GPU")
-    params, norm, loss, t_train = train_surrogate(st, lbm)
-    _p(f"  loss {loss:.3e} in {t_train:.1f} s")
-    _p("surrogate + BF16 deviation form")
-    surr = time_form(lbm, torch, shape, bc, fields, ref, kw, "bf16", "mlp", args.steps, args.warmup,
-                     mlp=(params, norm))
-    _p(f"  {surr['mlups']:.0f} MLUPS, kernels {surr['kernel_ms']}, fallback {surr['fallback_fraction']}")
-    if plain is None:
-        print(json.dumps({"forms": {"surrogate_bf16": surr, "bf16_vdw": bvdw}}), flush=True)
+    if surr is None or plain is None:
+        print(json.dumps({"forms": {"plain_fp32": plain, "bf16_vdw": bvdw, "surrogate_bf16": surr}}), flush=True)
         return
 
     def roof(form, name):

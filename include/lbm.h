@@ -323,6 +323,18 @@ int lbm_mlp_loss_grad(const float *dev_params, const float *dev_xn, const float 
 int lbm_mlp_loss_grad_noalloc(const float *dev_params, const float *dev_xn, const float *dev_tn, int B,
                               float *dev_grad, float *dev_loss, int precision, void *stream);
 
+/* ---- HBM ceiling probe -------------------------------------------------- */
+/* The practical bandwidth ceiling the step's kernels are measured against:
+ * kind 0 reads `bytes` of dev_src, 1 writes `bytes` of dev_dst, 2 copies
+ * dev_src to dev_dst; 16-byte accesses per lane with the non-temporal hint,
+ * blocks_per_cu (1..64) workgroups of 256 threads per compute unit striding
+ * over the buffer.  host_ms receives the average duration of `iters`
+ * launches after one warm-up launch (HIP events; blocking).  Buffers are
+ * caller-owned, `bytes` a multiple of 16 (dev_dst needs 16 bytes for kind 0).
+ * Errors: LBM_EINVAL, LBM_EDEVICE. */
+int lbm_hbm_probe(int kind, const void *dev_src, void *dev_dst, int64_t bytes, int blocks_per_cu, int iters,
+                  void *stream, double *host_ms);
+
 /* ---- precision codec ---------------------------------------------------- */
 /* dev_out[n] = 16-bit code of dev_x[n] - dev_ref[n] (FP32 subtraction,
  * round-to-nearest-even; kind LBM_STORE_BF16 or LBM_STORE_F16); the decode

@@ -167,6 +167,30 @@ __global__ void k_codec_decode(int kind, const uint16_t *code, const float *ref,
     if (i >= n) return;
     out[i] = ref[i] + (kind == LBM_STORE_BF16 ? bf16_to_f32(code[i]) : f16_to_f32(code[i]));
 }
+// HBM bandwidth probes (the practical ceiling the step's kernels are
+// measured against): 16-byte accesses per lane, grid-stride loops, stores
+// and loads with the non-temporal hint.  The read probe folds its loads into
+// one value that is stored only if it equals an arbitrary constant, so the
+// loads cannot be dropped.
+__global__ void __launch_bounds__(256) k_probe_read(const u32x4 *__restrict__ src, long long n,
+                                                    u32x4 *__restrict__ sink) {
+    u32x4 acc = {0u, 0u, 0u, 0u};
+    for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        acc ^= __builtin_nontemporal_load(&src[i]);
+    const unsigned a = acc.x, b = acc.y, c = acc.z, d = acc.w;
+    if ((a ^ b ^ c ^ d) == 0x9e3779b9u) sink[0] = acc;
+}
+__global__ void __launch_bounds__(256) k_probe_write(u32x4 *__restrict__ dst, long long n) {
+    for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const unsigned k = (unsigned)i;
+        __builtin_nontemporal_store((u32x4){k, k + 1u, k + 2u, k + 3u}, &dst[i]);
+    }
+}
+__global__ void __launch_bounds__(256) k_probe_copy(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
+                                                    long long n) {
+    for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(&src[i]), &dst[i]);
+}
 }  // namespace lbm
 
 // ---------------------------------------------------------------------------
@@ -900,6 +924,42 @@ int lbm_is_fused(const lbm_ctx *c) { return c && c->fused ? 1 : 0; }
 double lbm_bytes_per_cell(const lbm_ctx *c) {
     if (!c) return 0.0;
     return 2.0 * 2.0 * c->Q * c->store_bytes;
+}
+
+int lbm_hbm_probe(int kind, const void *src, void *dst, int64_t bytes, int blocks_per_cu, int iters, void *stream,
+                  double *host_ms) {
+    if (kind < 0 || kind > 2 || bytes <= 0 || bytes % 16 || blocks_per_cu < 1 || blocks_per_cu > 64 || iters < 1 ||
+        !host_ms || !dst || (kind != 1 && !src))
+        return LBM_EINVAL;
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+        return lbm_note(hipGetLastError());
+    hipStream_t s = (hipStream_t)stream;
+    const long long n = bytes / 16;
+    const dim3 grid((unsigned)(ncu * blocks_per_cu));
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return lbm_note(hipGetLastError());
+    auto launch = [&]() {
+        if (kind == 0)
+            hipLaunchKernelGGL(k_probe_read, grid, dim3(256), 0, s, (const u32x4 *)src, n, (u32x4 *)dst);
+        else if (kind == 1)
+            hipLaunchKernelGGL(k_probe_write, grid, dim3(256), 0, s, (u32x4 *)dst, n);
+        else
+            hipLaunchKernelGGL(k_probe_copy, grid, dim3(256), 0, s, (const u32x4 *)src, (u32x4 *)dst, n);
+    };
+    launch();  // warm-up
+    (void)hipEventRecord(e0, s);
+    for (int k = 0; k < iters; k++) launch();
+    (void)hipEventRecord(e1, s);
+    int rc = last_launch();
+    float ms = 0;
+    if (rc == LBM_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = lbm_note(hipGetLastError());
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *host_ms = (double)ms / iters;
+    return rc;
 }
 
 int lbm_codec_encode(int kind, const float *x, const float *ref, uint16_t *out, int64_t n, void *stream) {

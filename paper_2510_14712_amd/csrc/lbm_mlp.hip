@@ -321,17 +321,27 @@ __global__ void __launch_bounds__(64) k_train_partial(const float *__restrict__ 
     }
 }
 
-__global__ void k_sum_partials(const float *gpart, const float *lpart, int nblk, int B, float *grad, float *loss) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < NP) {
-        float s = 0.0f;
-        for (int k = 0; k < nblk; k++) s += gpart[(long long)k * NP + p];
-        grad[p] = s;
-    }
-    if (p == 0 && loss) {
-        double s = 0.0;
-        for (int k = 0; k < nblk; k++) s += (double)lpart[k];
-        loss[0] = (float)(s / (3.0 * (double)B));
+// Sum of the per-block partial gradients, in a fixed order: a workgroup
+// takes 64 parameters; its four wavefronts each sum a contiguous quarter of
+// the blocks for those parameters (a lane per parameter, loads coalesced
+// across the lanes), and lane p of the first wavefront adds the four quarter
+// sums in order.  The loss: FP64 sum of the block losses by one lane.
+__global__ void __launch_bounds__(256) k_sum_partials(const float *gpart, const float *lpart, int nblk, int B,
+                                                      float *grad, float *loss) {
+    __shared__ float part[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + lane;
+    const int k0 = (int)(((long long)w * nblk) / 4), k1 = (int)(((long long)(w + 1) * nblk) / 4);
+    float s = 0.0f;
+    if (p < NP)
+        for (int k = k0; k < k1; k++) s += gpart[(long long)k * NP + p];
+    part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && p < NP) grad[p] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && loss) {
+        double t = 0.0;
+        for (int k = 0; k < nblk; k++) t += (double)lpart[k];
+        loss[0] = (float)(t / (3.0 * (double)B));
     }
 }
 
@@ -537,7 +547,7 @@ static int loss_grad_impl(const float *params, const float *xn, const float *tn,
         hipLaunchKernelGGL(mlp::k_train_partial<true>, dim3(nblk), dim3(64), 0, s, params, xn, tn, B, gpart, lpart);
     else
         hipLaunchKernelGGL(mlp::k_train_partial<false>, dim3(nblk), dim3(64), 0, s, params, xn, tn, B, gpart, lpart);
-    hipLaunchKernelGGL(mlp::k_sum_partials, dim3((mlp::NP + 255) / 256), dim3(256), 0, s, gpart, lpart, nblk, B,
+    hipLaunchKernelGGL(mlp::k_sum_partials, dim3((mlp::NP + 63) / 64), dim3(256), 0, s, gpart, lpart, nblk, B,
                        grad, loss);
     return lbm_note(hipGetLastError());
 }

@@ -89,6 +89,8 @@ def load():
         "lbm_mlp_loss_grad": ([_VP, _VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
         "lbm_mlp_loss_grad_noalloc": ([_VP, _VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
         "lbm_mlp_adam": ([_VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_float, _VP], ctypes.c_int),
+        "lbm_hbm_probe": ([ctypes.c_int, _VP, _VP, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _VP, _DP],
+                          ctypes.c_int),
         "lbm_codec_encode": ([ctypes.c_int, _VP, _VP, _VP, ctypes.c_int64, _VP], ctypes.c_int),
         "lbm_codec_decode": ([ctypes.c_int, _VP, _VP, _VP, ctypes.c_int64, _VP], ctypes.c_int),
     }
@@ -349,6 +351,16 @@ def mlp_adam(params, grad, m, v, t, lr, stream=None):
         assert a.is_cuda and a.dtype == _torch().float32 and a.is_contiguous() and a.numel() == MLP_NPARAMS
     _check(load().lbm_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(t), float(lr), _stream_ptr(stream)),
            "lbm_mlp_adam")
+
+
+def hbm_probe(kind, src, dst, blocks_per_cu, iters=10, stream=None):
+    """lbm_hbm_probe on CUDA tensors: average ms per launch of the read (0),
+    write (1) or copy (2) probe over dst's bytes."""
+    ms = ctypes.c_double()
+    nbytes = dst.numel() * dst.element_size()
+    _check(load().lbm_hbm_probe(int(kind), _ptr(src), _ptr(dst), nbytes, int(blocks_per_cu), int(iters),
+                                _stream_ptr(stream), ctypes.byref(ms)), "lbm_hbm_probe")
+    return ms.value
 
 
 def codec_encode(kind, x, ref, stream=None):

@@ -430,8 +430,10 @@ def test_fast_instance_16bit_step_by_step(storage):
         _step_by_step_16bit(lat, 3, shape, (0, 0, 0), storage, 6)
 
 
-# per-field rel-L2 bars after the workload's 2000 steps
-BARS_16BIT_2000 = {"bf16": dict(rho=1e-3, u=3e-2, T=2e-3), "f16": dict(rho=3e-4, u=5e-3, T=3e-4)}
+# per-field rel-L2 bars after the workload's 2000 steps (measured: BF16 rho
+# 2.0e-4, u 1.6e-2, T 6.9e-5; FP16 rho 1.6e-5, u 1.5e-3, T 2.7e-6; u decays
+# to a third of U0 over the run, so its relative error is the largest)
+BARS_16BIT_2000 = {"bf16": dict(rho=1e-3, u=3e-2, T=5e-4), "f16": dict(rho=1e-4, u=5e-3, T=3e-5)}
 
 
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
@@ -441,8 +443,8 @@ def test_tgv64_2000_steps_error_vs_oracle(storage):
     with the surrogate EOS (threshold 1e-6, FP64 Newton fallback), FP32
     collide, against the FP64 oracle's fields stored by
     oracle/make_tgv64_reference.py (tests/golden/tgv64_mu0.1_2000.npz).
-    Per-field rel-L2 bars: BF16 rho 1e-3, u 3e-2, T 2e-3; FP16 rho 3e-4,
-    u 5e-3, T 3e-4."""
+    Per-field rel-L2 bars: BF16 rho 1e-3, u 3e-2, T 5e-4; FP16 rho 1e-4,
+    u 5e-3, T 3e-5."""
     import os
     lbm = _lbm()
     gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "tgv64_mu0.1_2000.npz"))
