@@ -353,8 +353,12 @@ template <class C> struct CenterF {
 // Newton step on e(rho, T) = e where it fails (exact for van der Waals).
 // Writes T of every cell; the fused step reads it in place of the explicit
 // inversion.  A workgroup takes a 64 x 4 block of (x, y) columns (one row per
-// wavefront) and marches through `zchunk` planes, keeping the Laplacian of
-// its own column for planes z-1, z, z+1 in registers.
+// wavefront) and marches through `zchunk` planes.  The rho of a 68 x 8 region
+// (the block and two cells around it) is staged in LDS for four planes, the
+// Laplacian of the 66 x 6 region in LDS for three, so that a plane costs one
+// coalesced load of the region per thread-share instead of a load per stencil
+// point; the region loads and the cell's j, G run two planes ahead of their use,
+// so that their latency overlaps the network of the planes between.
 template <int D>
 __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph, const float *__restrict__ Mc,
                                                        float *__restrict__ Tout, const float *__restrict__ P,
@@ -362,8 +366,16 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
                                                        const float *__restrict__ norm, float tol,
                                                        unsigned long long *count, int zchunk) {
     constexpr int W2LD = 72;  // padded BF16 rows: conflict-free 16-byte A-operand reads
+    constexpr int RW = 68, RN = RW * 8;   // rho region: x0 - 2 .. x0 + 65, y0 - 2 .. y0 + 5
+    constexpr int LW = 66, LN = LW * 6;   // Laplacian region: x0 - 1 .. x0 + 64, y0 - 1 .. y0 + 4
+    constexpr int KR = (RN + 255) / 256;  // region entries per thread
+    constexpr int KL = (LN + 255) / 256;
+    constexpr int NRP = D == 3 ? 4 : 1;   // planes held
+    constexpr int NLP = D == 3 ? 3 : 1;
     __shared__ float sNet[mlp::OFF_W2 + 2 * mlp::H + 2];
     __shared__ __attribute__((aligned(16))) uint16_t sW2[mlp::H * W2LD];
+    __shared__ float sRho[NRP][RN];
+    __shared__ float sLap[NLP][LN];
     const int tid = threadIdx.x, lane = tid & 63;
     for (int r = tid; r < mlp::OFF_W2; r += 256) sNet[r] = P[r];
     for (int r = tid; r < 2 * mlp::H; r += 256) sNet[mlp::OFF_W2 + r] = P[mlp::OFF_B2 + r];  // b2, w3 row of T
@@ -374,54 +386,86 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
         const int m = r / mlp::H, k = r % mlp::H;
         sW2[m * W2LD + k] = W2b[m * mlp::H + mlp::w2_perm_col(k)];
     }
-    __syncthreads();
     const mlp::Net net{sNet + mlp::OFF_W1, sNet + mlp::OFF_B1, sW2, nullptr, sNet + mlp::OFF_W2,
                        sNet + mlp::OFF_W2 + mlp::H, sNet + mlp::OFF_W2 + 2 * mlp::H, W2LD};
-    const mlp::L1Ops l1 = mlp::l1_operands(sNet + mlp::OFF_W1, sNet + mlp::OFF_B1);
 
     const int nx = g.nx, ny = g.ny, nz = D == 3 ? g.nz : 1;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
-    // lattice coordinate of a stencil point: wrapped (periodic) or clamped
+    // lattice coordinate of any point near the block: wrapped (periodic) or
+    // clamped (zero-gradient)
     auto ax = [](int v, int n, int clamp) {
-        return clamp ? (v < 0 ? 0 : (v >= n ? n - 1 : v)) : (v < 0 ? v + n : (v >= n ? v - n : v));
+        if (clamp) return v < 0 ? 0 : (v >= n ? n - 1 : v);
+        v %= n;
+        return v < 0 ? v + n : v;
     };
-    const int x = blockIdx.x * 64 + lane, y = blockIdx.y * 4 + (tid >> 6);
+    const int x0 = blockIdx.x * 64, y0 = blockIdx.y * 4;
+    const int x = x0 + lane, y = y0 + (tid >> 6);
     const bool act = x < nx && y < ny;  // other lanes evaluate a clamped cell and write nothing
     const int xc = min(x, nx - 1), yc = min(y, ny - 1);
-    // x and y coordinates of the column, of its neighbours and of theirs (a
-    // ghost point is the clamped cell: its Laplacian is that cell's)
-    const int xm = ax(xc - 1, nx, g.clampx), xp = ax(xc + 1, nx, g.clampx);
-    const int xmm = ax(xm - 1, nx, g.clampx), xmp = ax(xm + 1, nx, g.clampx);
-    const int xpm = ax(xp - 1, nx, g.clampx), xpp = ax(xp + 1, nx, g.clampx);
-    const int ym = ax(yc - 1, ny, g.clampy), yp = ax(yc + 1, ny, g.clampy);
-    const int ymm = ax(ym - 1, ny, g.clampy), ymp = ax(ym + 1, ny, g.clampy);
-    const int ypm = ax(yp - 1, ny, g.clampy), ypp = ax(yp + 1, ny, g.clampy);
     const unsigned oc = xc + nx * yc;
+    // the thread's rho-region entries: lattice offsets in a plane
+    unsigned roff[KR];
+#pragma unroll
+    for (int k = 0; k < KR; k++) {
+        const int r = min(tid + 256 * k, RN - 1);
+        roff[k] = (unsigned)(ax(x0 - 2 + r % RW, nx, g.clampx) + nx * ax(y0 - 2 + r / RW, ny, g.clampy));
+    }
+    // the thread's Laplacian-region entries: rho-region index of the point the
+    // Laplacian is evaluated at (on a zero-gradient axis a ghost point is the
+    // clamped cell, whose Laplacian it takes; on a periodic one the point itself)
+    int lsrc[KL];
+#pragma unroll
+    for (int k = 0; k < KL; k++) {
+        const int r = min(tid + 256 * k, LN - 1);
+        const int lx = r % LW - 1, ly = r / LW - 1;
+        const int ex = g.clampx ? ax(x0 + lx, nx, 1) - x0 : lx, ey = g.clampy ? ax(y0 + ly, ny, 1) - y0 : ly;
+        lsrc[k] = (ey + 2) * RW + ex + 2;
+    }
+    const int ol = (yc - y0 + 1) * LW + (xc - x0 + 1);  // the cell in the Laplacian region
+    const int orr = (yc - y0 + 2) * RW + (xc - x0 + 2);  // and in the rho region
+
+    // periodic plane index of q in [z0 - 2, z1 + 4) (conditional adds, no division)
+    auto zw = [&](int q) {
+        if (D != 3) return 0;
+        while (q < 0) q += nz;
+        while (q >= nz) q -= nz;
+        return q;
+    };
+    auto rs = [](int q) { return D == 3 ? q & 3 : 0; };
+    auto ls = [](int q) { return D == 3 ? (int)((unsigned)(q + 3 * 4096) % 3u) : 0; };  // q > -3 * 4096
     // One buffer resource per layer of the side channel (its 5 moments, the
-    // moment picked by a uniform offset) and per plane of T; the lane offsets
-    // of the stencil points do not change along the march, so a load needs
-    // no address arithmetic.  The host keeps 5 nx ny values below 2^31 bytes.
-    const unsigned mc_bytes = 5u * plane * (unsigned)sizeof(float);
-    auto mcr = [&](int layer) { return make_rsrc(Mc + (size_t)layer * 5 * plane, mc_bytes); };
-    // rho of a layer at cell offset o
-    auto rho = [&](Rsrc r, unsigned o) -> float {
-        float v;
-        buf_ld(r, o * (unsigned)sizeof(float), 0u, v);
-        return v;
+    // moment picked by a uniform offset); the host keeps 5 nx ny values below
+    // 2^31 bytes.
+    const unsigned mc_bytes = 5u * plane * (unsigned)sizeof(float), ko = plane * (unsigned)sizeof(float);
+    auto mcr = [&](int q) { return make_rsrc(Mc + (size_t)zw(q) * 5 * plane, mc_bytes); };
+    auto load_rho = [&](int q, float *v) {
+        const Rsrc r = mcr(q);
+#pragma unroll
+        for (int k = 0; k < KR; k++) buf_ld(r, roff[k] * (unsigned)sizeof(float), 0u, v[k]);
     };
-    // Laplacian at the lattice point (xs, ys) of the plane of r (expression
-    // order as in the fused step); rm, rp: the planes below and above; xsm ..
-    // ysp are the point's neighbours' coordinates
-    auto lap = [&](Rsrc r, Rsrc rm, Rsrc rp, int xs, int xsm, int xsp, int ys, int ysm, int ysp) -> float {
-        const unsigned o = xs + nx * ys;
-        const float r0 = rho(r, o);
-        float s = rho(r, xsp + nx * ys) + rho(r, xsm + nx * ys) - 2.0f * r0 + rho(r, xs + nx * ysp) +
-                  rho(r, xs + nx * ysm) - 2.0f * r0;
-        if (D == 3) s += rho(rp, o) + rho(rm, o) - 2.0f * r0;
-        return s;
+    auto put_rho = [&](int q, const float *v) {
+#pragma unroll
+        for (int k = 0; k < KR; k++)
+            if (tid + 256 * k < RN) sRho[rs(q)][tid + 256 * k] = v[k];
     };
-    auto zw = [&](int z) { return D == 3 ? ax(z, nz, 0) : 0; };
-    auto lap_col = [&](int z) { return lap(mcr(zw(z)), mcr(zw(z - 1)), mcr(zw(z + 1)), xc, xm, xp, yc, ym, yp); };
+    auto load_jg = [&](int q, float *v) {
+        const Rsrc r = mcr(q);
+#pragma unroll
+        for (int k = 0; k < 4; k++) buf_ld(r, oc * (unsigned)sizeof(float), (unsigned)(k + 1) * ko, v[k]);
+    };
+    // Laplacian of plane q over the region (expression order as in the fused step)
+    auto make_lap = [&](int q) {
+        const float *rc = sRho[rs(q)], *rm = sRho[rs(q - 1)], *rp = sRho[rs(q + 1)];
+#pragma unroll
+        for (int k = 0; k < KL; k++) {
+            if (tid + 256 * k >= LN) continue;
+            const int c = lsrc[k];
+            const float r0 = rc[c];
+            float s = rc[c + 1] + rc[c - 1] - 2.0f * r0 + rc[c + RW] + rc[c - RW] - 2.0f * r0;
+            if (D == 3) s += rp[c] + rm[c] - 2.0f * r0;
+            sLap[ls(q)][tid + 256 * k] = s;
+        }
+    };
 
     const int z0 = D == 3 ? blockIdx.z * zchunk : 0;
     const int z1 = D == 3 ? min(nz, z0 + zchunk) : 1;
@@ -431,34 +475,56 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     const float s0 = 2.0f / (norm[1] - norm[0]), s1 = 2.0f / (norm[3] - norm[2]);
     const float tol_cv = tol * ph.cv;
     const double inv_cv = 1.0 / (double)ph.cv;
-    float Lm = D == 3 ? lap_col(z0 - 1) : 0.0f, L0 = lap_col(z0);
-    for (int z = z0; z < z1; z++) {
-        const float Lp = D == 3 ? lap_col(z + 1) : 0.0f;
-        const int zz = zw(z);
-        const Rsrc rz = mcr(zz), rzm = mcr(zw(z - 1)), rzp = mcr(zw(z + 1));
-        const unsigned vo = oc * (unsigned)sizeof(float), ko = plane * (unsigned)sizeof(float);
-        float r, j0, j1, j2, G;
-        buf_ld(rz, vo, 0u, r);
-        buf_ld(rz, vo, ko, j0);
-        buf_ld(rz, vo, 2u * ko, j1);
-        buf_ld(rz, vo, 3u * ko, j2);
-        buf_ld(rz, vo, 4u * ko, G);
+    // prologue: rho of planes z0 - 2 .. z0 + 1 in LDS, the Laplacian of z0 - 1
+    // and z0; rho of z0 + 2, z0 + 3 and j, G of z0, z0 + 1 in flight
+    float va[KR], vb[KR], ja[4], jb[4];
+    {
+        float v[NRP][KR];
+#pragma unroll
+        for (int q = 0; q < NRP; q++) load_rho(z0 - (D == 3 ? 2 : 0) + q, v[q]);
+#pragma unroll
+        for (int q = 0; q < NRP; q++) put_rho(z0 - (D == 3 ? 2 : 0) + q, v[q]);
+    }
+    if (D == 3) {
+        load_rho(z0 + 2, va);
+        load_rho(z0 + 3, vb);
+    }
+    load_jg(z0, ja);
+    if (D == 3) load_jg(z0 + 1, jb);
+    __syncthreads();
+    if (D == 3) make_lap(z0 - 1);
+    make_lap(z0);
+    __syncthreads();
+    const mlp::L1Ops l1 = mlp::l1_operands(sNet + mlp::OFF_W1, sNet + mlp::OFF_B1);
+    // plane z; vr: rho of plane z + 2 (then loaded with z + 4), jg: j, G of
+    // plane z (then loaded with z + 2).  Two register sets take turns, so no
+    // register with a load in flight is ever copied.
+    auto plane_step = [&](int z, float (&vr)[KR], float (&jg)[4]) {
+        if (D == 3) {
+            // rho of plane z + 2 into the slot of plane z - 2 (last read before
+            // the previous plane's first barrier), the Laplacian of z + 1
+            put_rho(z + 2, vr);
+            load_rho(z + 4, vr);  // also past the chunk (unused there): the loads' wait counts stay exact
+            __syncthreads();
+            make_lap(z + 1);
+            __syncthreads();
+        }
+        const float r = sRho[rs(z)][orr];
         const float inv_rho = __builtin_amdgcn_rcpf(r);  // 1 ulp; feeds the network input and the residual
+        const float *lc = sLap[ls(z)];
         float F[3];
-        F[0] = ph.kappa * r * 0.5f *
-               (lap(rz, rzm, rzp, xp, xpm, xpp, yc, ym, yp) - lap(rz, rzm, rzp, xm, xmm, xmp, yc, ym, yp));
-        F[1] = ph.kappa * r * 0.5f *
-               (lap(rz, rzm, rzp, xc, xm, xp, yp, ypm, ypp) - lap(rz, rzm, rzp, xc, xm, xp, ym, ymm, ymp));
-        F[2] = D == 3 ? ph.kappa * r * 0.5f * (Lp - Lm) : 0.0f;
-        const float jv[3] = {j0, j1, j2};
+        F[0] = ph.kappa * r * 0.5f * (lc[ol + 1] - lc[ol - 1]);
+        F[1] = ph.kappa * r * 0.5f * (lc[ol + LW] - lc[ol - LW]);
+        F[2] = D == 3 ? ph.kappa * r * 0.5f * (sLap[ls(z + 1)][ol] - sLap[ls(z - 1)][ol]) : 0.0f;
         float uF = 0.0f, u2 = 0.0f;
         for (int d = 0; d < 3; d++) {
-            const float u = d < D ? (jv[d] + 0.5f * F[d]) * inv_rho : 0.0f;
+            const float u = d < D ? (jg[d] + 0.5f * F[d]) * inv_rho : 0.0f;
             uF += u * F[d];
             u2 += u * u;
         }
-        const float E = (G + 0.5f * uF) * inv_rho;
+        const float E = (jg[3] + 0.5f * uF) * inv_rho;
         const float e = E - 0.5f * u2;
+        if (D == 3) load_jg(z + 2, jg);
         float yh[1];
         const float x0n = (r - norm[0]) * s0 - 1.0f, x1n = (e - norm[2]) * s1 - 1.0f;
         mlp::forward_wave_l1mfma<1>(x0n, x1n, net, l1, yh);
@@ -471,13 +537,17 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
             Td = Td - ((double)ph.cv * Td - (double)ph.a * (double)r - (double)e) * inv_cv;
             Th = (float)Td;
         }
-        if (act) buf_st(make_rsrc(Tout + (size_t)zz * plane, ko), vo, 0u, Th);
+        // every lane stores: a lane beyond the lattice evaluated the clamped
+        // cell from the same inputs, so it writes the same value to it (no
+        // branch around the store, which keeps the loads' wait counts exact)
+        buf_st(make_rsrc(Tout + (size_t)zw(z) * plane, ko), oc * (unsigned)sizeof(float), 0u, Th);
         n_fb += __popcll(__ballot(fb && act));
         n_eval += __popcll(__ballot(act));
-        Lm = L0;
-        L0 = Lp;
+    };
+    for (int z = z0; z < z1; z += 2) {
+        plane_step(z, va, ja);
+        if (z + 1 < z1) plane_step(z + 1, vb, jb);
     }
-    (void)L0;
     if (lane == 0 && n_eval) {
         atomicAdd(&count[0], n_fb);
         atomicAdd(&count[1], n_eval);
