@@ -197,7 +197,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="tgv512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,bf16vdw,surrogate", help="comma list of forms to time")
+    ap.add_argument("--forms", default="plain,bf16vdw,surrogate,f16surrogate", help="comma list of forms to time")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--hbm-probe", action="store_true",
@@ -232,7 +232,7 @@ def main():
     N = int(np.prod(shape))
 
     forms = args.forms.split(",")
-    plain = bvdw = surr = None
+    plain = bvdw = surr = f16s = None
     # the value form first, on a device whose memory no earlier form has
     # fragmented (a form timed after others' large allocations and frees ran
     # its fused kernel up to 6 % slower)
@@ -244,6 +244,11 @@ def main():
         surr = time_form(lbm, torch, shape, bc, fields, ref, kw, "bf16", "mlp", args.steps, args.warmup,
                          mlp=(params, norm))
         _p(f"  {surr['mlups']:.0f} MLUPS, kernels {surr['kernel_ms']}, fallback {surr['fallback_fraction']}")
+    if "f16surrogate" in forms and surr is not None:
+        _p("surrogate + FP16 deviation form")
+        f16s = time_form(lbm, torch, shape, bc, fields, ref, kw, "f16", "mlp", args.steps, args.warmup,
+                         mlp=(params, norm))
+        _p(f"  {f16s['mlups']:.0f} MLUPS, kernels {f16s['kernel_ms']}, fallback {f16s['fallback_fraction']}")
     if "plain" in forms:
         _p(f"plain FP32 form on {shape}")
         plain = time_form(lbm, torch, shape, bc, fields, ref, kw, "f32", "vdw", args.steps, args.warmup)
@@ -296,6 +301,11 @@ def main():
             "mlups": round(bvdw["mlups"], 1), "ms_per_step": round(bvdw["ms_per_step"], 4),
             "step_hbm_frac": round(bvdw["bytes_per_cell"] * bvdw["mlups"] * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
             "kernel_ms": bvdw["kernel_ms"], "finite": bvdw["finite"], "roofline": roof(bvdw, "bf16_vdw")[1]}
+    if f16s is not None:
+        line["forms"]["surrogate_f16"] = {
+            "mlups": round(f16s["mlups"], 1), "ms_per_step": round(f16s["ms_per_step"], 4),
+            "kernel_ms": f16s["kernel_ms"], "finite": f16s["finite"], "fallback_fraction": f16s["fallback_fraction"],
+            "admissible": f16s["admissible"]}
     if not args.no_cpu_baseline:
         _p("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(st)

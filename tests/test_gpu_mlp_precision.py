@@ -170,7 +170,9 @@ def test_step_with_surrogate_and_fallback():
     fr, gr = oracle.run(p, *oracle.init(p, rho, u, T), 50)
     ref = oracle.fields(p, fr, gr)
     _say(f"  fallback fraction {frac:.4f}")
-    assert 0.0 <= frac <= 1.0
+    # 1e-6 is beyond the BF16 network's accuracy (its T error is ~1e-3): the
+    # parity below is that of the exact fallback, taken almost everywhere
+    assert 0.9 <= frac <= 1.0
     for k in ("rho", "u", "T"):
         e = rel_l2(mom[k], ref[k])
         _say(f"  {k} rel-L2 {e:.2e}")
@@ -210,6 +212,9 @@ def test_step_surrogate_accepted_where_residual_allows():
 
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
 def test_deviation_storage_error_per_field(storage):
+    """BF16 / FP16 deviation storage with the explicit EOS, Taylor-Green
+    40x32x24, 200 steps, against the FP64 oracle: rho within 1e-3, u within
+    1.5e-2, T within 3e-4 per field (relative L2)."""
     lbm = _lbm()
     c = ST["tgv_3d_256"]
     shape = (40, 32, 24)
@@ -225,13 +230,16 @@ def test_deviation_storage_error_per_field(storage):
     errs = {k: rel_l2(mom[k], ref[k]) for k in ("rho", "u", "T")}
     _say(f"  per-field rel-L2 {errs}")
     assert errs["rho"] <= 1e-3
+    assert errs["u"] <= 1.5e-2
+    assert errs["T"] <= 3e-4
 
 
 def test_surrogate_bf16_form_density_error():
     """The form the throughput comparison runs: BF16 deviation storage, the
     surrogate EOS (threshold 1e-6) with FP64 fallback, FP32 collision, on the
     Taylor-Green recipe for 200 steps: density within 1e-3 of the FP64
-    oracle; u and T errors reported beside it."""
+    oracle, u within 1.5e-2 and T within 3e-4 (measured 2.2e-4, 4.9e-3,
+    7.9e-5)."""
     lbm = _lbm()
     params, norm, _ = _train()
     c = ST["tgv_3d_256"]
@@ -251,7 +259,8 @@ def test_surrogate_bf16_form_density_error():
     errs = {k: rel_l2(mom[k], ref[k]) for k in ("rho", "u", "T")}
     _say(f"  fallback fraction {frac:.4f}, per-field rel-L2 {errs}")
     assert errs["rho"] <= 1e-3
-    assert errs["T"] <= 1e-2
+    assert errs["u"] <= 1.5e-2
+    assert errs["T"] <= 3e-4
 
 
 def test_surrogate_pass_2d_walls_partial_tiles():
