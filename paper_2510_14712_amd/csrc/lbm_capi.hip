@@ -297,7 +297,8 @@ template <int D, class S> struct Impl {
         hipLaunchKernelGGL((k_fused_moments<D, S, TL>), cell_grid(c), dim3(BX), 0, c->stream, c->grid, c->ref, rs[0],
                            rs[1], rs[2], rs[3],
                            c->ntx, c->nty, c->nseg, c->nlay, (const T *)c->f[c->cur], (const T *)c->g[c->cur],
-                           (C *)c->Mc[c->cur], c->pulled);
+                           (C *)c->Mc[c->mcc], c->pulled);
+        c->mc_pending = false;
         return last_launch();
     }
     // sums of the reference populations in the compute type as hi + lo
@@ -338,9 +339,9 @@ template <int D, class S> struct Impl {
         const int nxt = 1 - c->cur;
         a.fi = (const T *)c->f[c->cur];
         a.fo = (T *)c->f[nxt];
-        a.Mci = (const C *)c->Mc[c->cur];
-        a.Mco = (C *)c->Mc[nxt];
-        a.INo = (C *)c->IN[nxt];
+        a.Mci = (const C *)c->Mc[c->mcc];
+        a.Mco = (C *)c->Mc[1 - c->mcc];
+        a.INo = (C *)c->IN[1 - c->mcc];
         a.Tin = (const C *)c->Tsur;
         const dim3 grid((unsigned)(c->ntx * c->nty * c->nseg));
         // full tiles and periodic x, y: the specialisation without wall and
@@ -354,12 +355,21 @@ template <int D, class S> struct Impl {
             if (fast) hipLaunchKernelGGL((k_fused<D, S, TL, false, true>), grid, dim3(TL::NT), 0, c->stream, a);
             else hipLaunchKernelGGL((k_fused<D, S, TL, false, false>), grid, dim3(TL::NT), 0, c->stream, a);
         }
+        c->cur = nxt;
+        c->pulled = 1;
+        c->mc_pending = true;
+    }
+    // the surrogate pass completes the side channel itself (the fix-up's
+    // work): the surrogate form on 64 x 4 tiles, every tile at least 2 x 2
+    static bool fold(const lbm_ctx *c) {
+        return mlp(c) && c->p.nx >= 2 && c->p.ny >= 2 && c->p.nx % 64 != 1 && c->p.ny % 4 != 1;
     }
     // completes the output moments (kind 1 of step_timed) and flips the state
     static void fused_fixup(lbm_ctx *c) { mlp(c) ? fused_fixup_t<true>(c) : fused_fixup_t<false>(c); }
     template <bool M> static void fused_fixup_t(lbm_ctx *c) {
         using TL = TileOf<S, M>;
-        const int nxt = 1 - c->cur;
+        if (!c->mc_pending || fold(c)) return;
+        const int nxt = 1 - c->mcc;
         const long long per = (long long)c->ntx * c->nty * TL::PMAX;
         hipLaunchKernelGGL((k_fused_fixup<D, TL, C>), dim3((unsigned)((per + BX - 1) / BX), c->p.nz), dim3(BX), 0,
                            c->stream, c->grid, c->ntx, c->nty, c->nseg, 0, (C *)c->Mc[nxt],
@@ -370,8 +380,8 @@ template <int D, class S> struct Impl {
                                dim3(BX), 0, c->stream, c->grid, c->ntx, c->nty, c->nseg, 1,
                                (C *)c->Mc[nxt], (const C *)c->IN[nxt]);
         }
-        c->cur = nxt;
-        c->pulled = 1;
+        c->mcc = nxt;
+        c->mc_pending = false;
     }
     // surrogate form: T of every cell by the network pass (kind 2 of
     // step_timed), ahead of the fused step that reads it
@@ -382,9 +392,23 @@ template <int D, class S> struct Impl {
             const int zchunk = D == 3 ? 32 : 1;
             const dim3 grid((unsigned)((c->p.nx + 63) / 64), (unsigned)((c->p.ny + 3) / 4),
                             (unsigned)((c->p.nz + zchunk - 1) / zchunk));
-            hipLaunchKernelGGL(k_eos_surrogate<D>, grid, dim3(256), 0, c->stream, c->grid, make_phys<float>(c->p),
-                               (const float *)c->Mc[c->cur], (float *)c->Tsur, c->mlp_params, c->mlp_w2b,
-                               c->mlp_norm, (float)c->p.mlp_tol, c->mlp_counters, zchunk);
+            FoldArgs fa{nullptr, nullptr, c->ntx, c->nty, c->nseg};
+            if (fold(c) && c->mc_pending) {
+                // partial sums and slots of the last fused step in, complete
+                // moments out to the buffer that step read
+                fa.IN = (const float *)c->IN[1 - c->mcc];
+                fa.Mco = (float *)c->Mc[c->mcc];
+                hipLaunchKernelGGL((k_eos_surrogate<D, true>), grid, dim3(256), 0, c->stream, c->grid,
+                                   make_phys<float>(c->p), (const float *)c->Mc[1 - c->mcc], (float *)c->Tsur,
+                                   c->mlp_params, c->mlp_w2b, c->mlp_norm, (float)c->p.mlp_tol, c->mlp_counters,
+                                   zchunk, fa);
+                c->mc_pending = false;
+            } else {
+                hipLaunchKernelGGL((k_eos_surrogate<D, false>), grid, dim3(256), 0, c->stream, c->grid,
+                                   make_phys<float>(c->p), (const float *)c->Mc[c->mcc], (float *)c->Tsur,
+                                   c->mlp_params, c->mlp_w2b, c->mlp_norm, (float)c->p.mlp_tol, c->mlp_counters,
+                                   zchunk, fa);
+            }
         }
     }
     static void fused_launch(lbm_ctx *c) {
@@ -825,6 +849,8 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
     }
     (void)hipMemsetAsync(c->mlp_counters, 0, sizeof(unsigned long long) * 4, c->stream);
     c->cur = 0;
+    c->mcc = 0;
+    c->mc_pending = false;
     c->initialized = false;
     c->mlp_ready = false;
     *out = c;
@@ -852,6 +878,8 @@ static int init_dispatch(lbm_ctx *c, const double *rho, const double *u, const d
 int lbm_init(lbm_ctx *c, const double *rho, const double *u, const double *Tf) {
     if (!c || !rho || !u || !Tf) return LBM_EINVAL;
     c->cur = 0;
+    c->mcc = 0;
+    c->mc_pending = false;
     c->initialized = false;
     const int rc = init_dispatch(c, rho, u, Tf);
     c->initialized = rc == LBM_OK;

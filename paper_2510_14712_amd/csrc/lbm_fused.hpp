@@ -359,12 +359,27 @@ template <class C> struct CenterF {
 // coalesced load of the region per thread-share instead of a load per stencil
 // point; the region loads and the cell's j, G run two planes ahead of their use,
 // so that their latency overlaps the network of the planes between.
-template <int D>
+//
+// FOLD: the pass also completes the side channel, doing k_fused_fixup's work.
+// Mc then holds the previous fused step's partial sums, IN its inbound slots
+// and spill layers; every value the pass uses is completed on load with the
+// fix-up's terms, order and rounding (a perimeter cell adds its slots, every
+// cell of a segment's end plane its slots and the spill layers), and the five
+// complete moments of every cell go to Mco, which the next fused step reads.
+// The fused step's tiles are the pass's 64 x 4 blocks; tiles of at least 2 x 2
+// cells (the host falls back to the separate fix-up otherwise).
+struct FoldArgs {
+    const float *IN;  // inbound slots [nlay][tiles][5][NR]
+    float *Mco;       // complete moments out, plane layers [nz][5][ny][nx]
+    int ntx, nty, nseg;
+};
+template <int D, bool FOLD>
 __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph, const float *__restrict__ Mc,
                                                        float *__restrict__ Tout, const float *__restrict__ P,
                                                        const uint16_t *__restrict__ W2b,
                                                        const float *__restrict__ norm, float tol,
-                                                       unsigned long long *count, int zchunk) {
+                                                       unsigned long long *count, int zchunk, FoldArgs fa) {
+    using TL = Tile<64, 4>;
     constexpr int W2LD = 72;  // padded BF16 rows: conflict-free 16-byte A-operand reads
     constexpr int RW = 68, RN = RW * 8;   // rho region: x0 - 2 .. x0 + 65, y0 - 2 .. y0 + 5
     constexpr int LW = 66, LN = LW * 6;   // Laplacian region: x0 - 1 .. x0 + 64, y0 - 1 .. y0 + 4
@@ -391,6 +406,9 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
 
     const int nx = g.nx, ny = g.ny, nz = D == 3 ? g.nz : 1;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
+    // the block's chunk of planes
+    const int z0_blk = D == 3 ? blockIdx.z * zchunk : 0;
+    const int z1_blk = D == 3 ? min(nz, z0_blk + zchunk) : 1;
     // lattice coordinate of any point near the block: wrapped (periodic) or
     // clamped (zero-gradient)
     auto ax = [](int v, int n, int clamp) {
@@ -424,34 +442,174 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     const int ol = (yc - y0 + 1) * LW + (xc - x0 + 1);  // the cell in the Laplacian region
     const int orr = (yc - y0 + 2) * RW + (xc - x0 + 2);  // and in the rho region
 
+    // FOLD: inbound-slot byte offsets (moment 0, within a layer) of a lattice cell:
+    // its side, bottom/top and corner slot in its tile's array, and whether it
+    // lies on the tile's left/right and bottom/top edge (as in inbound_sum)
+    struct Slots {
+        unsigned sh, sv, sc;
+        bool hs, vs;
+    };
+    auto slots_of = [&](int xe, int ye) {
+        const int tx = xe / TL::TX, ty = ye / TL::TY, lx = xe - tx * TL::TX, ly = ye - ty * TL::TY;
+        const int w = min(TL::TX, g.nx - tx * TL::TX), h = min(TL::TY, g.ny - ty * TL::TY);
+        const bool l = lx == 0, r = lx == w - 1, b = ly == 0, t = ly == h - 1;
+        const unsigned base = (unsigned)(ty * fa.ntx + tx) * 5u * TL::NR;
+        Slots o;  // byte offsets
+        o.sh = (base + (unsigned)((l ? TL::FROM_L : TL::FROM_R) + ly)) * (unsigned)sizeof(float);
+        o.sv = (base + (unsigned)((b ? TL::FROM_B : TL::FROM_T) + lx)) * (unsigned)sizeof(float);
+        o.sc = (base + (unsigned)(TL::FROM_BL + (r ? 1 : 0) + (t ? 2 : 0))) * (unsigned)sizeof(float);
+        o.hs = l || r;
+        o.vs = b || t;
+        return o;
+    };
+    Slots rsl[KR], osl;
+    if (FOLD) {
+#pragma unroll
+        for (int k = 0; k < KR; k++) {
+            const int r = min(tid + 256 * k, RN - 1);
+            rsl[k] = slots_of(ax(x0 - 2 + r % RW, nx, g.clampx), ax(y0 - 2 + r / RW, ny, g.clampy));
+        }
+        osl = slots_of(xc, yc);
+    }
+    // the cell's row is a bottom or top row of its tile: uniform over the
+    // wavefront (one row of the block, which is the tile)
+    const bool row_perim = FOLD && __builtin_amdgcn_readfirstlane(osl.vs ? 1 : 0) != 0;
+    const unsigned in_layer = (unsigned)(fa.ntx * fa.nty) * 5u * TL::NR;  // floats per IN layer
+
     // periodic plane index of q in [z0 - 2, z1 + 4) (conditional adds, no division)
+    // periodic plane index of q in [z0 - 2, z1 + 4) (conditional adds, no
+    // division; set-up only: the march keeps wrapped plane counters, advanced
+    // by inc, a compare and select)
     auto zw = [&](int q) {
         if (D != 3) return 0;
         while (q < 0) q += nz;
         while (q >= nz) q -= nz;
         return q;
     };
+    auto inc = [&](int wq) { return D == 3 ? (wq + 1 == nz ? 0 : wq + 1) : 0; };
     auto rs = [](int q) { return D == 3 ? q & 3 : 0; };
     auto ls = [](int q) { return D == 3 ? (int)((unsigned)(q + 3 * 4096) % 3u) : 0; };  // q > -3 * 4096
     // One buffer resource per layer of the side channel (its 5 moments, the
-    // moment picked by a uniform offset); the host keeps 5 nx ny values below
-    // 2^31 bytes.
+    // moment picked by a uniform offset) and per layer of the inbound slots;
+    // the host keeps 5 nx ny values below 2^31 bytes.  wq, lay: layer indices.
     const unsigned mc_bytes = 5u * plane * (unsigned)sizeof(float), ko = plane * (unsigned)sizeof(float);
-    auto mcr = [&](int q) { return make_rsrc(Mc + (size_t)zw(q) * 5 * plane, mc_bytes); };
-    auto load_rho = [&](int q, float *v) {
-        const Rsrc r = mcr(q);
-#pragma unroll
-        for (int k = 0; k < KR; k++) buf_ld(r, roff[k] * (unsigned)sizeof(float), 0u, v[k]);
+    auto mcr = [&](int lay) { return make_rsrc(Mc + (size_t)lay * 5 * plane, mc_bytes); };
+    auto inr = [&](int lay) { return make_rsrc(fa.IN + (size_t)lay * in_layer, in_layer * (unsigned)sizeof(float)); };
+    // values loaded for a plane: the side channel's sums and (FOLD) the three
+    // inbound slots of each
+    constexpr int NS = FOLD ? 1 : 0;
+    struct RhoIn {
+        float m[KR];
+        float s[NS ? KR : 1][3];
     };
-    auto put_rho = [&](int q, const float *v) {
+    struct JgIn {
+        float m[4];
+        float s[NS ? 4 : 1][3];
+    };
+    // the moment's slot block is a uniform offset (no per-lane address arithmetic)
+    auto load_slots = [&](Rsrc ri, const Slots &sl, int m, float (&v)[3]) {
+        const unsigned mo = (unsigned)m * TL::NR * (unsigned)sizeof(float);
+        buf_ld(ri, sl.sh, mo, v[0]);
+        buf_ld(ri, sl.sv, mo, v[1]);
+        buf_ld(ri, sl.sc, mo, v[2]);
+    };
+    // the segment structure of plane wq (D = 3, FOLD): an end plane of its z
+    // segment also takes the spill layers (lay_hi on its first plane, from the
+    // segment below; lay_lo on its last, from the segment above)
+    struct EndInfo {
+        bool lo, hi;
+        int wq;
+    };
+    // bit i: plane z0 - 2 + i (i < 64; a chunk spans at most zchunk + 6 planes)
+    // is a segment's first (lo_m) / last (hi_m) plane, set up once per block
+    unsigned long long lo_m = 0, hi_m = 0;
+    if (D == 3 && FOLD) {
+        for (int i = 0; i < 64 && z0_blk - 2 + i < z1_blk + 4; i++) {
+            const int wq = zw(z0_blk - 2 + i), sg = seg_of(wq, nz, fa.nseg);
+            if (wq == seg_lo(sg, nz, fa.nseg)) lo_m |= 1ull << i;
+            if (wq == seg_lo(sg + 1, nz, fa.nseg) - 1) hi_m |= 1ull << i;
+        }
+    }
+    // q: the plane (unwrapped), wq: its layer
+    auto end_info = [&](int q, int wq) {
+        EndInfo ei{false, false, wq};
+        if (D == 3 && FOLD) {
+            const int i = q - (z0_blk - 2);
+            ei.lo = (lo_m >> i) & 1ull;
+            ei.hi = (hi_m >> i) & 1ull;
+        }
+        return ei;
+    };
+    // complete moment m of a cell (lane offset `cell` in a plane) of layer wq
+    // from its partial sum mc and slots sv: on an ordinary plane a perimeter
+    // cell adds its slots (inbound_sum_2x2), on an end plane every cell adds
+    // them (inbound_sum) and then the spill layers with their slots -- the
+    // terms, order and rounding of k_fused_fixup's two modes
+    auto complete = [&](float mc, const float (&sv)[3], const Slots &sl, unsigned cell, int m, const EndInfo &ei) {
+        if (!(ei.lo || ei.hi)) {
+            const float sum = ((sl.hs ? sv[0] : 0.0f) + (sl.vs ? sv[1] : 0.0f)) + ((sl.hs && sl.vs) ? sv[2] : 0.0f);
+            return (sl.hs || sl.vs) ? mc + sum : mc;
+        }
+        auto gen = [&](const float (&t)[3]) {
+            float v = 0.0f;
+            if (sl.hs) v += t[0];
+            if (sl.vs) v += t[1];
+            if (sl.hs && sl.vs) v += t[2];
+            return v;
+        };
+        float v = mc + gen(sv);
+        const int sg = seg_of(ei.wq, nz, fa.nseg);
+        for (int side = 0; side < 2; side++) {
+            if (!(side == 0 ? ei.lo : ei.hi)) continue;
+            const int lay = side == 0 ? nz + 2 * ((sg + fa.nseg - 1) % fa.nseg) + 1   // from the segment below
+                                      : nz + 2 * ((sg + 1) % fa.nseg);                // from the segment above
+            float ms, ts[3];
+            buf_ld(mcr(lay), cell * (unsigned)sizeof(float), (unsigned)m * ko, ms);
+            load_slots(inr(lay), sl, m, ts);
+            v += ms + gen(ts);
+        }
+        return v;
+    };
+    auto load_rho = [&](int wq, RhoIn &v) {
+        const Rsrc r = mcr(wq);
+#pragma unroll
+        for (int k = 0; k < KR; k++) buf_ld(r, roff[k] * (unsigned)sizeof(float), 0u, v.m[k]);
+        if (FOLD) {
+            const Rsrc ri = inr(wq);
+#pragma unroll
+            for (int k = 0; k < KR; k++) load_slots(ri, rsl[k], 0, v.s[k]);
+        }
+    };
+    // rho of ring slot q (plane counter wq) into LDS, completed (FOLD)
+    auto put_rho = [&](int q, int wq, const RhoIn &v) {
+        const EndInfo ei = end_info(q, wq);
 #pragma unroll
         for (int k = 0; k < KR; k++)
-            if (tid + 256 * k < RN) sRho[rs(q)][tid + 256 * k] = v[k];
+            if (tid + 256 * k < RN) {
+                float x = v.m[k];
+                if (FOLD) x = complete(v.m[k], v.s[k], rsl[k], roff[k], 0, ei);
+                sRho[rs(q)][tid + 256 * k] = x;
+            }
     };
-    auto load_jg = [&](int q, float *v) {
-        const Rsrc r = mcr(q);
+    auto load_jg = [&](int wq, JgIn &v) {
+        const Rsrc r = mcr(wq);
 #pragma unroll
-        for (int k = 0; k < 4; k++) buf_ld(r, oc * (unsigned)sizeof(float), (unsigned)(k + 1) * ko, v[k]);
+        for (int k = 0; k < 4; k++) buf_ld(r, oc * (unsigned)sizeof(float), (unsigned)(k + 1) * ko, v.m[k]);
+        if (FOLD) {
+            const Rsrc ri = inr(wq);
+            // a wavefront is one row of the tile: on an inner row only the two
+            // edge lanes have a (side) slot, so the row loads that one alone
+            if (row_perim) {
+#pragma unroll
+                for (int k = 0; k < 4; k++) load_slots(ri, osl, k + 1, v.s[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    buf_ld(ri, osl.sh, (unsigned)(k + 1) * TL::NR * (unsigned)sizeof(float), v.s[k][0]);
+                    v.s[k][1] = v.s[k][2] = 0.0f;
+                }
+            }
+        }
     };
     // Laplacian of plane q over the region (expression order as in the fused step)
     auto make_lap = [&](int q) {
@@ -467,8 +625,7 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
         }
     };
 
-    const int z0 = D == 3 ? blockIdx.z * zchunk : 0;
-    const int z1 = D == 3 ? min(nz, z0 + zchunk) : 1;
+    const int z0 = z0_blk, z1 = z1_blk;
     unsigned long long n_fb = 0, n_eval = 0;
     // per-block constants: the input map x = 2 (v - lo) / (hi - lo) - 1 as
     // (v - lo) s - 1, the residual bound tol c_v, and 1 / c_v for the Newton step
@@ -477,20 +634,25 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     const double inv_cv = 1.0 / (double)ph.cv;
     // prologue: rho of planes z0 - 2 .. z0 + 1 in LDS, the Laplacian of z0 - 1
     // and z0; rho of z0 + 2, z0 + 3 and j, G of z0, z0 + 1 in flight
-    float va[KR], vb[KR], ja[4], jb[4];
+    RhoIn va, vb;
+    JgIn ja, jb;
     {
-        float v[NRP][KR];
+        RhoIn v[NRP];
+        const int q0 = z0 - (D == 3 ? 2 : 0);
 #pragma unroll
-        for (int q = 0; q < NRP; q++) load_rho(z0 - (D == 3 ? 2 : 0) + q, v[q]);
+        for (int q = 0; q < NRP; q++) load_rho(zw(q0 + q), v[q]);
 #pragma unroll
-        for (int q = 0; q < NRP; q++) put_rho(z0 - (D == 3 ? 2 : 0) + q, v[q]);
+        for (int q = 0; q < NRP; q++) put_rho(q0 + q, zw(q0 + q), v[q]);
     }
     if (D == 3) {
-        load_rho(z0 + 2, va);
-        load_rho(z0 + 3, vb);
+        load_rho(zw(z0 + 2), va);
+        load_rho(zw(z0 + 3), vb);
     }
-    load_jg(z0, ja);
-    if (D == 3) load_jg(z0 + 1, jb);
+    load_jg(zw(z0), ja);
+    if (D == 3) load_jg(zw(z0 + 1), jb);
+    // plane counters of the march: rho to put (z + 2) and to load (z + 4), j, G
+    // to load (z + 2), and the plane itself
+    int w_put = zw(z0 + 2), w_rho = zw(z0 + 4), w_jg = zw(z0 + 2), w_cur = zw(z0);
     __syncthreads();
     if (D == 3) make_lap(z0 - 1);
     make_lap(z0);
@@ -499,17 +661,41 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     // plane z; vr: rho of plane z + 2 (then loaded with z + 4), jg: j, G of
     // plane z (then loaded with z + 2).  Two register sets take turns, so no
     // register with a load in flight is ever copied.
-    auto plane_step = [&](int z, float (&vr)[KR], float (&jg)[4]) {
+    auto plane_step = [&](int z, RhoIn &vr, JgIn &jg) {
         if (D == 3) {
             // rho of plane z + 2 into the slot of plane z - 2 (last read before
             // the previous plane's first barrier), the Laplacian of z + 1
-            put_rho(z + 2, vr);
-            load_rho(z + 4, vr);  // also past the chunk (unused there): the loads' wait counts stay exact
+            put_rho(z + 2, w_put, vr);
+            w_put = inc(w_put);
+            load_rho(w_rho, vr);  // also past the chunk (unused there): the loads' wait counts stay exact
+            w_rho = inc(w_rho);
             __syncthreads();
             make_lap(z + 1);
             __syncthreads();
         }
         const float r = sRho[rs(z)][orr];
+        // j, G of the cell (completed: FOLD)
+        float j[4];
+        if (FOLD) {
+            const EndInfo ei = end_info(z, w_cur);
+#pragma unroll
+            for (int k = 0; k < 4; k++) j[k] = complete(jg.m[k], jg.s[k], osl, oc, k + 1, ei);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; k++) j[k] = jg.m[k];
+        }
+        if (D == 3) {
+            load_jg(w_jg, jg);
+            w_jg = inc(w_jg);
+        }
+        if (FOLD) {
+            // the complete moments of the cell for the fused step (a lane
+            // beyond the lattice writes its clamped cell's, the same values)
+            const Rsrc ro = make_rsrc(fa.Mco + (size_t)w_cur * 5 * plane, mc_bytes);
+            buf_st(ro, oc * (unsigned)sizeof(float), 0u, r);
+#pragma unroll
+            for (int k = 0; k < 4; k++) buf_st(ro, oc * (unsigned)sizeof(float), (unsigned)(k + 1) * ko, j[k]);
+        }
         const float inv_rho = __builtin_amdgcn_rcpf(r);  // 1 ulp; feeds the network input and the residual
         const float *lc = sLap[ls(z)];
         float F[3];
@@ -518,13 +704,12 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
         F[2] = D == 3 ? ph.kappa * r * 0.5f * (sLap[ls(z + 1)][ol] - sLap[ls(z - 1)][ol]) : 0.0f;
         float uF = 0.0f, u2 = 0.0f;
         for (int d = 0; d < 3; d++) {
-            const float u = d < D ? (jg[d] + 0.5f * F[d]) * inv_rho : 0.0f;
+            const float u = d < D ? (j[d] + 0.5f * F[d]) * inv_rho : 0.0f;
             uF += u * F[d];
             u2 += u * u;
         }
-        const float E = (jg[3] + 0.5f * uF) * inv_rho;
+        const float E = (j[3] + 0.5f * uF) * inv_rho;
         const float e = E - 0.5f * u2;
-        if (D == 3) load_jg(z + 2, jg);
         float yh[1];
         const float x0n = (r - norm[0]) * s0 - 1.0f, x1n = (e - norm[2]) * s1 - 1.0f;
         mlp::forward_wave_l1mfma<1>(x0n, x1n, net, l1, yh);
@@ -540,7 +725,8 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
         // every lane stores: a lane beyond the lattice evaluated the clamped
         // cell from the same inputs, so it writes the same value to it (no
         // branch around the store, which keeps the loads' wait counts exact)
-        buf_st(make_rsrc(Tout + (size_t)zw(z) * plane, ko), oc * (unsigned)sizeof(float), 0u, Th);
+        buf_st(make_rsrc(Tout + (size_t)w_cur * plane, ko), oc * (unsigned)sizeof(float), 0u, Th);
+        w_cur = inc(w_cur);
         n_fb += __popcll(__ballot(fb && act));
         n_eval += __popcll(__ballot(act));
     };

@@ -36,6 +36,12 @@ struct lbm_ctx {
     void *Mc[2] = {nullptr, nullptr};  // [nlay][5][ny][nx]
     void *Tsur = nullptr;              // surrogate form: T of every cell for the fused step
     void *IN[2] = {nullptr, nullptr};  // [nlay][tiles][5][slots]
+    // side channel state: Mc[mcc] holds the complete moments the next fused
+    // step reads; mc_pending: the last fused step's partial sums in
+    // Mc[1 - mcc] / IN[1 - mcc] still await completion (by the surrogate pass
+    // when it does the fix-up's work)
+    int mcc = 0;
+    bool mc_pending = false;
     size_t mc_bytes = 0, in_bytes = 0;
     int ntx = 0, nty = 0, nseg = 1, nlay = 0, chunk = 0;
 };
