@@ -389,8 +389,10 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     constexpr int NLP = D == 3 ? 3 : 1;
     __shared__ float sNet[mlp::OFF_W2 + 2 * mlp::H + 2];
     __shared__ __attribute__((aligned(16))) uint16_t sW2[mlp::H * W2LD];
-    __shared__ float sRho[NRP][RN];
-    __shared__ float sLap[NLP][LN];
+    // rows padded to whole multiples of the block, so that every thread
+    // stores its entries without a branch (the padding is never read)
+    __shared__ float sRho[NRP][KR * 256];
+    __shared__ float sLap[NLP][KL * 256];
     const int tid = threadIdx.x, lane = tid & 63;
     for (int r = tid; r < mlp::OFF_W2; r += 256) sNet[r] = P[r];
     for (int r = tid; r < 2 * mlp::H; r += 256) sNet[mlp::OFF_W2 + r] = P[mlp::OFF_B2 + r];  // b2, w3 row of T
@@ -545,11 +547,14 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     // cell adds its slots (inbound_sum_2x2), on an end plane every cell adds
     // them (inbound_sum) and then the spill layers with their slots -- the
     // terms, order and rounding of k_fused_fixup's two modes
-    auto complete = [&](float mc, const float (&sv)[3], const Slots &sl, unsigned cell, int m, const EndInfo &ei) {
-        if (!(ei.lo || ei.hi)) {
-            const float sum = ((sl.hs ? sv[0] : 0.0f) + (sl.vs ? sv[1] : 0.0f)) + ((sl.hs && sl.vs) ? sv[2] : 0.0f);
-            return (sl.hs || sl.vs) ? mc + sum : mc;
-        }
+    // (two functions: the ordinary planes' form has no branch and no load; the
+    // caller picks one per plane)
+    auto complete = [&](float mc, const float (&sv)[3], const Slots &sl) {
+        const float sum = ((sl.hs ? sv[0] : 0.0f) + (sl.vs ? sv[1] : 0.0f)) + ((sl.hs && sl.vs) ? sv[2] : 0.0f);
+        return (sl.hs || sl.vs) ? mc + sum : mc;
+    };
+    auto complete_end = [&](float mc, const float (&sv)[3], const Slots &sl, unsigned cell, int m,
+                            const EndInfo &ei) {
         auto gen = [&](const float (&t)[3]) {
             float v = 0.0f;
             if (sl.hs) v += t[0];
@@ -582,14 +587,21 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     };
     // rho of ring slot q (plane counter wq) into LDS, completed (FOLD)
     auto put_rho = [&](int q, int wq, const RhoIn &v) {
-        const EndInfo ei = end_info(q, wq);
+        float x[KR];
 #pragma unroll
-        for (int k = 0; k < KR; k++)
-            if (tid + 256 * k < RN) {
-                float x = v.m[k];
-                if (FOLD) x = complete(v.m[k], v.s[k], rsl[k], roff[k], 0, ei);
-                sRho[rs(q)][tid + 256 * k] = x;
+        for (int k = 0; k < KR; k++) x[k] = v.m[k];
+        if (FOLD) {
+            const EndInfo ei = end_info(q, wq);
+            if (ei.lo || ei.hi) {
+#pragma unroll
+                for (int k = 0; k < KR; k++) x[k] = complete_end(v.m[k], v.s[k], rsl[k], roff[k], 0, ei);
+            } else {
+#pragma unroll
+                for (int k = 0; k < KR; k++) x[k] = complete(v.m[k], v.s[k], rsl[k]);
             }
+        }
+#pragma unroll
+        for (int k = 0; k < KR; k++) sRho[rs(q)][tid + 256 * k] = x[k];
     };
     auto load_jg = [&](int wq, JgIn &v) {
         const Rsrc r = mcr(wq);
@@ -616,7 +628,6 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
         const float *rc = sRho[rs(q)], *rm = sRho[rs(q - 1)], *rp = sRho[rs(q + 1)];
 #pragma unroll
         for (int k = 0; k < KL; k++) {
-            if (tid + 256 * k >= LN) continue;
             const int c = lsrc[k];
             const float r0 = rc[c];
             float s = rc[c + 1] + rc[c - 1] - 2.0f * r0 + rc[c + RW] + rc[c - RW] - 2.0f * r0;
@@ -678,8 +689,13 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
         float j[4];
         if (FOLD) {
             const EndInfo ei = end_info(z, w_cur);
+            if (ei.lo || ei.hi) {
 #pragma unroll
-            for (int k = 0; k < 4; k++) j[k] = complete(jg.m[k], jg.s[k], osl, oc, k + 1, ei);
+                for (int k = 0; k < 4; k++) j[k] = complete_end(jg.m[k], jg.s[k], osl, oc, k + 1, ei);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; k++) j[k] = complete(jg.m[k], jg.s[k], osl);
+            }
         } else {
 #pragma unroll
             for (int k = 0; k < 4; k++) j[k] = jg.m[k];
