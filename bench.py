@@ -34,12 +34,34 @@ KERNEL_SOURCES = ("lbm_fused.hpp", "lbm_kernels.hpp", "lbm_device.hpp", "lbm_mlp
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_tgv512_hbm_traffic.md")
 
 
-def kernel_source_hash():
+def strip_comments(text):
+    """C++ source without its comments and blank lines (an edit of a comment
+    leaves the kernels, and so the measured traffic, as they were)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = []
+    for line in text.split("\n"):
+        i = line.find("//")
+        if i >= 0:
+            line = line[:i]
+        line = line.rstrip()
+        if line:
+            out.append(line)
+    return "\n".join(out)
+
+
+def kernel_source_hash(read=None):
+    """Hash of the fused step's sources, comments stripped; `read(name)` gives
+    a file's text (default: the working tree)."""
     import hashlib
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2510_14712_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        if read is None:
+            with open(os.path.join(ROOT, "paper_2510_14712_amd", "csrc", name)) as fh:
+                text = fh.read()
+        else:
+            text = read(name)
+        h.update(strip_comments(text).encode())
     return h.hexdigest()[:16]
 
 

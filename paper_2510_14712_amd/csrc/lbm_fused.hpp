@@ -478,7 +478,6 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     const bool row_perim = FOLD && __builtin_amdgcn_readfirstlane(osl.vs ? 1 : 0) != 0;
     const unsigned in_layer = (unsigned)(fa.ntx * fa.nty) * 5u * TL::NR;  // floats per IN layer
 
-    // periodic plane index of q in [z0 - 2, z1 + 4) (conditional adds, no division)
     // periodic plane index of q in [z0 - 2, z1 + 4) (conditional adds, no
     // division; set-up only: the march keeps wrapped plane counters, advanced
     // by inc, a compare and select)
