@@ -615,7 +615,10 @@ template <int D, class S> struct Impl {
         int rc = last_launch();
         return rc ? rc : fused_prepare(c);
     }
-    static void tiles(lbm_ctx *c) { mlp(c) ? tiles_t<true>(c) : tiles_t<false>(c); }
+    static void tiles(lbm_ctx *c) {
+        mlp(c) ? tiles_t<true>(c) : tiles_t<false>(c);
+        c->folded = fold(c);
+    }
     template <bool M> static void tiles_t(lbm_ctx *c) {
         using TL = TileOf<S, M>;
         c->ntx = (c->p.nx + TL::TX - 1) / TL::TX;
@@ -798,35 +801,10 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
     c->sc = params->sc_cmu > 0 || params->sc_ceta > 0 || params->sc_ck > 0;
     size_t nfield = (size_t)(8 + 4 * c->D + (c->sc ? 4 : 0));
     size_t field_bytes = nfield * N * cb;
-    c->red_blocks = 1024;
-    // one buffer per ping-pong slot holds both sets, f_i and g_i side by side
-    // (the g pointer is the f buffer offset by one element)
-    bool ok = hipMalloc(&c->f[0], 2 * pop_bytes) == hipSuccess && hipMalloc(&c->f[1], 2 * pop_bytes) == hipSuccess &&
-              hipMalloc(&c->work, field_bytes) == hipSuccess &&
-              hipMalloc((void **)&c->red_partials, sizeof(double) * RED_VALS * c->red_blocks) == hipSuccess &&
-              hipMalloc((void **)&c->red_out, sizeof(double) * RED_VALS) == hipSuccess &&
-              hipMalloc((void **)&c->mlp_counters, sizeof(unsigned long long) * 4) == hipSuccess &&
-              hipMalloc((void **)&c->mlp_params, sizeof(float) * (LBM_MLP_NPARAMS + 64)) == hipSuccess &&
-              hipMalloc((void **)&c->mlp_norm, sizeof(float) * 16) == hipSuccess &&
-              hipMalloc((void **)&c->mlp_w2b, sizeof(uint16_t) * 64 * 64) == hipSuccess;
-    if (ok)
-        for (int k = 0; k < 2; k++) c->g[k] = (char *)c->f[k] + sb;
-    if (!ok) {
-        lbm_note(hipGetLastError());
-        lbm_destroy(c);
-        return LBM_ENOMEM;
-    }
     // the single-pass step covers periodic z (and every D = 2 lattice)
     // with the van der Waals equation of state, without shock capturing
     c->fused = (c->D == 2 || params->bc[2] == LBM_BC_PERIODIC) && !c->sc && !lbm_eos_is_pr(params->eos) &&
                params->bc[0] != LBM_BC_WALL;
-    if (ok && c->grid.wallx)
-        ok = hipMalloc(&c->ghost, (size_t)2 * params->ny * params->nz * c->Q * cb) == hipSuccess;
-    if (!ok) {
-        lbm_note(hipGetLastError());
-        lbm_destroy(c);
-        return LBM_ENOMEM;
-    }
     if (c->fused) {
         auto tiles = [&]() { DISPATCH_VOID(c, tiles(c)); };
         tiles();
@@ -837,15 +815,49 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
         if (2LL * c->Q * plane * sb >= lim || 5 * plane * cb >= lim || (long long)(c->in_bytes / c->nlay) >= lim)
             c->fused = false;
     }
-    if (c->fused) {
-        ok = hipMalloc(&c->Mc[0], c->mc_bytes) == hipSuccess && hipMalloc(&c->Mc[1], c->mc_bytes) == hipSuccess &&
-             hipMalloc(&c->IN[0], c->in_bytes) == hipSuccess && hipMalloc(&c->IN[1], c->in_bytes) == hipSuccess &&
-             (params->eos != LBM_EOS_MLP || hipMalloc(&c->Tsur, sizeof(float) * (size_t)N) == hipSuccess);
-        if (!ok) {
-            lbm_note(hipGetLastError());
-            lbm_destroy(c);
-            return LBM_ENOMEM;
+    if (!c->fused) c->folded = false;
+    // The large buffers come from one allocation, carved at 2 MiB boundaries:
+    // the population sets (one buffer per ping-pong slot holds both sets, f_i
+    // and g_i side by side; the g pointer is the f buffer offset by one
+    // element), the field arrays, the wall ghosts, and the fused step's side
+    // channel, inbound slots and surrogate temperatures.
+    struct Part {
+        void **dst;
+        size_t bytes;
+    };
+    const bool mlpT = c->fused && params->eos == LBM_EOS_MLP;
+    const Part parts[] = {{&c->f[0], 2 * pop_bytes},
+                          {&c->f[1], 2 * pop_bytes},
+                          {&c->work, field_bytes},
+                          {&c->ghost, c->grid.wallx ? (size_t)2 * params->ny * params->nz * c->Q * cb : 0},
+                          {&c->Mc[0], c->fused ? c->mc_bytes : 0},
+                          {&c->Mc[1], c->fused ? c->mc_bytes : 0},
+                          {&c->IN[0], c->fused ? c->in_bytes : 0},
+                          {&c->IN[1], c->fused ? c->in_bytes : 0},
+                          {&c->Tsur, mlpT ? sizeof(float) * (size_t)N : 0}};
+    constexpr size_t ALIGN = (size_t)1 << 21;
+    size_t total = 0;
+    for (const Part &pt : parts) total += (pt.bytes + ALIGN - 1) / ALIGN * ALIGN;
+    c->red_blocks = 1024;
+    bool ok = hipMalloc(&c->block, total) == hipSuccess &&
+              hipMalloc((void **)&c->red_partials, sizeof(double) * RED_VALS * c->red_blocks) == hipSuccess &&
+              hipMalloc((void **)&c->red_out, sizeof(double) * RED_VALS) == hipSuccess &&
+              hipMalloc((void **)&c->mlp_counters, sizeof(unsigned long long) * 4) == hipSuccess &&
+              hipMalloc((void **)&c->mlp_params, sizeof(float) * (LBM_MLP_NPARAMS + 64)) == hipSuccess &&
+              hipMalloc((void **)&c->mlp_norm, sizeof(float) * 16) == hipSuccess &&
+              hipMalloc((void **)&c->mlp_w2b, sizeof(uint16_t) * 64 * 64) == hipSuccess;
+    if (!ok) {
+        lbm_note(hipGetLastError());
+        lbm_destroy(c);
+        return LBM_ENOMEM;
+    }
+    {
+        char *q = (char *)c->block;
+        for (const Part &pt : parts) {
+            *pt.dst = pt.bytes ? q : nullptr;
+            q += (pt.bytes + ALIGN - 1) / ALIGN * ALIGN;
         }
+        for (int k = 0; k < 2; k++) c->g[k] = (char *)c->f[k] + sb;
     }
     (void)hipMemsetAsync(c->mlp_counters, 0, sizeof(unsigned long long) * 4, c->stream);
     c->cur = 0;
@@ -863,9 +875,8 @@ void lbm_destroy(lbm_ctx *c) {
     // is released regardless
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
-    void *ptrs[] = {c->f[0], c->f[1], c->work, c->red_partials, c->red_out,
-                    c->mlp_counters, c->mlp_params, c->mlp_norm, c->mlp_w2b, c->Mc[0], c->Mc[1], c->IN[0], c->IN[1],
-                    c->Tsur, c->ghost};
+    // the large buffers are carved from c->block
+    void *ptrs[] = {c->block, c->red_partials, c->red_out, c->mlp_counters, c->mlp_params, c->mlp_norm, c->mlp_w2b};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;
@@ -941,9 +952,10 @@ const char *lbm_last_error(void) { return g_last_error; }
 
 const char *lbm_kernel_name(const lbm_ctx *c, int k) {
     static const char *names[LBM_NUM_KERNELS] = {"k_moments", "k_lap", "k_fields", "k_collide"};
-    if (c && c->fused)
+    if (c && c->fused)  // the surrogate pass does the fix-up's work when folded
         return k == 0 ? "k_fused"
-                      : (k == 1 ? "k_fused_fixup" : (k == 2 && c->p.eos == LBM_EOS_MLP ? "k_eos_surrogate" : ""));
+                      : (k == 1 ? (c->folded ? "" : "k_fused_fixup")
+                                : (k == 2 && c->p.eos == LBM_EOS_MLP ? "k_eos_surrogate" : ""));
     return k >= 0 && k < LBM_NUM_KERNELS ? names[k] : "";
 }
 

@@ -10,6 +10,7 @@ struct lbm_ctx {
     lbm_params p;
     lbm::Grid grid;
     int D, Q, store_bytes;
+    void *block = nullptr;             // one allocation holding the large buffers below
     void *f[2] = {nullptr, nullptr};  // population state buffers (ping-pong), f_i and g_i side by side
     void *g[2] = {nullptr, nullptr};  // f[k] + one element (not separately allocated)
     int cur = 0;                      // index of the buffer holding the state
@@ -42,6 +43,7 @@ struct lbm_ctx {
     // when it does the fix-up's work)
     int mcc = 0;
     bool mc_pending = false;
+    bool folded = false;  // the surrogate pass completes the side channel (no separate fix-up)
     size_t mc_bytes = 0, in_bytes = 0;
     int ntx = 0, nty = 0, nseg = 1, nlay = 0, chunk = 0;
 };
