@@ -221,7 +221,8 @@ const char *lbm_kernel_name(const lbm_ctx *ctx, int kernel);
  * populations, one moment layer and the inbound slots each below 2^31 bytes)
  * followed by the small pass completing its moment side channel (kernel kinds
  * "k_fused", "k_fused_fixup"; with the surrogate EOS the network runs in a
- * pass ahead of them, kind "k_eos_surrogate", writing T of every cell), 0 when
+ * pass ahead of them, kind "k_eos_surrogate", writing the network's T of
+ * every cell and whether it passed the residual check), 0 when
  * it runs the four-kernel path (moments, Laplacian, fields, collide). */
 int lbm_is_fused(const lbm_ctx *ctx);
 

@@ -343,6 +343,9 @@ template <int D, class S> struct Impl {
         a.Mco = (C *)c->Mc[1 - c->mcc];
         a.INo = (C *)c->IN[1 - c->mcc];
         a.Tin = (const C *)c->Tsur;
+        a.Acc = (const unsigned *)c->Acc;
+        a.accw = 2 * ((c->p.nx + 63) / 64);
+        a.inv_cv_d = 1.0 / (double)(float)c->p.cv;
         const dim3 grid((unsigned)(c->ntx * c->nty * c->nseg));
         // full tiles and periodic x, y: the specialisation without wall and
         // partial-tile handling
@@ -401,13 +404,13 @@ template <int D, class S> struct Impl {
                 hipLaunchKernelGGL((k_eos_surrogate<D, true>), grid, dim3(256), 0, c->stream, c->grid,
                                    make_phys<float>(c->p), (const float *)c->Mc[1 - c->mcc], (float *)c->Tsur,
                                    c->mlp_params, c->mlp_w2b, c->mlp_norm, (float)c->p.mlp_tol, c->mlp_counters,
-                                   zchunk, fa);
+                                   zchunk, fa, (unsigned long long *)c->Acc);
                 c->mc_pending = false;
             } else {
                 hipLaunchKernelGGL((k_eos_surrogate<D, false>), grid, dim3(256), 0, c->stream, c->grid,
                                    make_phys<float>(c->p), (const float *)c->Mc[c->mcc], (float *)c->Tsur,
                                    c->mlp_params, c->mlp_w2b, c->mlp_norm, (float)c->p.mlp_tol, c->mlp_counters,
-                                   zchunk, fa);
+                                   zchunk, fa, (unsigned long long *)c->Acc);
             }
         }
     }
@@ -820,7 +823,7 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
     // the population sets (one buffer per ping-pong slot holds both sets, f_i
     // and g_i side by side; the g pointer is the f buffer offset by one
     // element), the field arrays, the wall ghosts, and the fused step's side
-    // channel, inbound slots and surrogate temperatures.
+    // channel, inbound slots, surrogate temperatures and their acceptance bits.
     struct Part {
         void **dst;
         size_t bytes;
@@ -834,7 +837,8 @@ int lbm_create(const lbm_params *params, lbm_ctx **out) {
                           {&c->Mc[1], c->fused ? c->mc_bytes : 0},
                           {&c->IN[0], c->fused ? c->in_bytes : 0},
                           {&c->IN[1], c->fused ? c->in_bytes : 0},
-                          {&c->Tsur, mlpT ? sizeof(float) * (size_t)N : 0}};
+                          {&c->Tsur, mlpT ? sizeof(float) * (size_t)N : 0},
+                          {&c->Acc, mlpT ? 8 * (size_t)((params->nx + 63) / 64) * params->ny * params->nz : 0}};
     constexpr size_t ALIGN = (size_t)1 << 21;
     size_t total = 0;
     for (const Part &pt : parts) total += (pt.bytes + ALIGN - 1) / ALIGN * ALIGN;

@@ -88,7 +88,12 @@ template <class C, class T> struct FusedArgs {
     const C *Mci;  // complete moments of the input state, [nlay][5][ny][nx]
     C *Mco, *INo;  // output: tile-own partial sums, inbound slots [nlay][tiles][5][NR]
     // surrogate equation of state (kernels built with MLP)
-    const C *Tin;  // surrogate form: T of every cell from k_eos_surrogate (layout of one z plane after another)
+    const C *Tin;  // surrogate form: the network's T of every cell from k_eos_surrogate ([z][y][x])
+    // which cells' network T passed the residual check: bit x % 32 of word
+    // [z][y][x / 32] (accw words per row); the others take the exact inversion
+    const unsigned *Acc;
+    int accw;
+    double inv_cv_d;  // 1 / c_v of the FP32 constant, for that inversion in FP64
 };
 
 // ring cell r of a w x h tile: bottom row, top row, left column, right column
@@ -349,11 +354,13 @@ template <class C> struct CenterF {
 // stencil (central differences, ghosts of zero-gradient axes take the
 // clamped cell's values, as in the fused step); u, E and e (eqs. def_u,
 // def_E); the network's T_hat (both hidden layers on MFMA); the caloric residual
-// |e(rho, T_hat) - e| / (c_v T_hat) against the threshold, and one FP64
-// Newton step on e(rho, T) = e where it fails (exact for van der Waals).
-// Writes T of every cell; the fused step reads it in place of the explicit
-// inversion.  A workgroup takes a 64 x 4 block of (x, y) columns (one row per
-// wavefront) and marches through `zchunk` planes.  The rho of a 68 x 8 region
+// |e(rho, T_hat) - e| / (c_v T_hat) against the threshold.  Writes T_hat of
+// every cell and one bit per cell, set where T_hat passed; the fused step
+// takes T_hat where the bit is set and the exact inversion of eq. lbm_temp,
+// in FP64, where it is not (the fallback: one Newton step on e(rho, T) = e
+// lands on it exactly for van der Waals).  A workgroup takes a 64 x 4 block
+// of (x, y) columns (one row per wavefront) and marches through `zchunk`
+// planes.  The rho of a 68 x 8 region
 // (the block and two cells around it) is staged in LDS for four planes, the
 // Laplacian of the 66 x 6 region in LDS for three, so that a plane costs one
 // coalesced load of the region per thread-share instead of a load per stencil
@@ -378,7 +385,8 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
                                                        float *__restrict__ Tout, const float *__restrict__ P,
                                                        const uint16_t *__restrict__ W2b,
                                                        const float *__restrict__ norm, float tol,
-                                                       unsigned long long *count, int zchunk, FoldArgs fa) {
+                                                       unsigned long long *count, int zchunk, FoldArgs fa,
+                                                       unsigned long long *__restrict__ Acc) {
     using TL = Tile<64, 4>;
     constexpr int W2LD = 72;  // padded BF16 rows: conflict-free 16-byte A-operand reads
     constexpr int RW = 68, RN = RW * 8;   // rho region: x0 - 2 .. x0 + 65, y0 - 2 .. y0 + 5
@@ -641,7 +649,9 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     // (v - lo) s - 1, the residual bound tol c_v, and 1 / c_v for the Newton step
     const float s0 = 2.0f / (norm[1] - norm[0]), s1 = 2.0f / (norm[3] - norm[2]);
     const float tol_cv = tol * ph.cv;
-    const double inv_cv = 1.0 / (double)ph.cv;
+    // acceptance words [z][y][x / 64], one per wavefront (a row of the block)
+    const unsigned nxb = (unsigned)(nx + 63) / 64u, acc_bytes = (unsigned)ny * nxb * 8u;
+    const unsigned acc_off = ((unsigned)yc * nxb + blockIdx.x) * 8u;
     // prologue: rho of planes z0 - 2 .. z0 + 1 in LDS, the Laplacian of z0 - 1
     // and z0; rho of z0 + 2, z0 + 3 and j, G of z0, z0 + 1 in flight
     RhoIn va, vb;
@@ -732,15 +742,15 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
         // relative residual |c_v T - a rho - e| / (c_v |T|) <= tol, without the
         // division; a NaN fails the test and takes the fallback
         const bool fb = !(fabsf(ph.cv * Th - ph.a * r - e) <= tol_cv * fabsf(Th));
-        if (fb) {
-            double Td = (double)Th;
-            Td = Td - ((double)ph.cv * Td - (double)ph.a * (double)r - (double)e) * inv_cv;
-            Th = (float)Td;
-        }
+        const unsigned long long accepted = __ballot(!fb);
         // every lane stores: a lane beyond the lattice evaluated the clamped
-        // cell from the same inputs, so it writes the same value to it (no
-        // branch around the store, which keeps the loads' wait counts exact)
+        // cell from the same inputs, so it writes the same values to it, and
+        // a wavefront beyond the lattice's last row the same word as that
+        // row's (no branch around the stores, which keeps the loads' wait
+        // counts exact)
         buf_st(make_rsrc(Tout + (size_t)w_cur * plane, ko), oc * (unsigned)sizeof(float), 0u, Th);
+        __builtin_amdgcn_raw_buffer_store_b64((u32x2){(unsigned)accepted, (unsigned)(accepted >> 32)},
+                                              make_rsrc(Acc + (size_t)w_cur * ny * nxb, acc_bytes), acc_off, 0u, 0);
         w_cur = inc(w_cur);
         n_fb += __popcll(__ballot(fb && act));
         n_eval += __popcll(__ballot(act));
@@ -921,7 +931,30 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         for (int k = 0; k < NR3; k++)
             if (tid + k * NT < TL::R3) dst[tid + k * NT] = v[k];
     };
-    auto load_jg = [&](int p, C *jo, C *jr) {
+    // surrogate form: acceptance words of the own and the ring cell of plane
+    // p (loaded one plane ahead of the temperatures they select)
+    const unsigned acc_row_bytes = (unsigned)a.accw * 4u;
+    const unsigned acc_own = (unsigned)gy * acc_row_bytes + (unsigned)(gx >> 5) * 4u;
+    unsigned acc_ring = acc_own;
+    int bit_own = gx & 31, bit_ring = bit_own;
+    if (MLP && ring) {
+        const int rgx = axis_global(x0, rx, g.nx, g.clampx), rgy = axis_global(y0, ry, g.ny, g.clampy);
+        acc_ring = (unsigned)rgy * acc_row_bytes + (unsigned)(rgx >> 5) * 4u;
+        bit_ring = rgx & 31;
+    }
+    auto load_acc = [&](int p, unsigned &wo, unsigned &wr) {
+        if constexpr (MLP) {
+            const Rsrc rm = make_rsrc(a.Acc + (long long)zwrap(p) * g.ny * a.accw, (unsigned)g.ny * acc_row_bytes);
+            wo = __builtin_amdgcn_raw_buffer_load_b32(rm, acc_own, 0u, 0);
+            wr = __builtin_amdgcn_raw_buffer_load_b32(rm, acc_ring, 0u, 0);
+        }
+    };
+    // j, G of plane p for the own and the ring cell; the surrogate form also
+    // loads the network's T where the cell's acceptance bit (in wo / wr) is
+    // set, and marks the cell accepted in jo[5] / jr[5] (1 or 0); a rejected
+    // cell reads the plane's first entry instead, a line every cell of the
+    // plane shares, so that no lane branches around its load
+    auto load_jg = [&](int p, C *jo, C *jr, unsigned wo, unsigned wr) {
         const Rsrc r = mc_layer(a.Mci, zwrap(p));
 #pragma unroll
         for (int k = 0; k < 4; k++) {
@@ -929,10 +962,12 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
             jr[k] = mom(r, 1 + k, ring_off);
         }
         if constexpr (MLP) {
-            // the surrogate form's temperatures of the own and the ring cell
+            const bool ao = (wo >> bit_own) & 1u, ar = (wr >> bit_ring) & 1u;
             const Rsrc rt = make_rsrc(a.Tin + (long long)zwrap(p) * plane, (unsigned)(plane * (long long)sizeof(C)));
-            buf_ld(rt, own_off * (unsigned)sizeof(C), 0u, jo[4]);
-            buf_ld(rt, ring_off * (unsigned)sizeof(C), 0u, jr[4]);
+            buf_ld(rt, ao ? own_off * (unsigned)sizeof(C) : 0u, 0u, jo[4]);
+            buf_ld(rt, ar ? ring_off * (unsigned)sizeof(C) : 0u, 0u, jr[4]);
+            jo[5] = ao ? C(1) : C(0);
+            jr[5] = ar ? C(1) : C(0);
         }
     };
     auto make_lap = [&](int p) {
@@ -972,7 +1007,10 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         const C E = (jg[3] + C(0.5) * uF) * inv_rho;
         const C e = E - C(0.5) * u2;
         if constexpr (MLP) {
-            Tt = jg[4];  // the surrogate's accepted (or fallback) temperature
+            // the network's T where the residual check accepted it; elsewhere
+            // the exact inversion of eq. lbm_temp, in FP64 (the fallback)
+            Tt = jg[5] != C(0) ? jg[4]
+                               : (C)(((double)e + (double)a.ph.a * (double)rho) * a.inv_cv_d);
         } else {
             Tt = (e + a.ph.a * rho) * a.ph.inv_cv;  // eq. lbm_temp
         }
@@ -1133,8 +1171,9 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
 
     // -- prologue: rho(z0-3 .. z0+4), L(z0-2 .. z0+2), fields of z0-1, z0 -----
     CenterF<C> Zc, Zm4;  // centre fields of plane z; plane z-1 (u_z, T, h, Lambda_z used)
-    constexpr int NJ = MLP ? 5 : 4;  // j, G (and T of the surrogate form) per cell
+    constexpr int NJ = MLP ? 6 : 4;  // j, G (and T, accepted flag of the surrogate form) per cell
     C jo[NJ], jr[NJ];
+    unsigned wo = 0, wr = 0;  // acceptance words of the next plane whose j, G are loaded
     {
         C rv[NR3];
         if (D == 3) {
@@ -1150,7 +1189,9 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
             __syncthreads();
             load_rho_regs(z0 + 1, rv);
             store_rho(z0 + 1, rv);
-            load_jg(z0 - 1, jo, jr);
+            load_acc(z0 - 1, wo, wr);
+            load_jg(z0 - 1, jo, jr, wo, wr);
+            load_acc(z0, wo, wr);
             __syncthreads();
             make_lap(z0);
             __syncthreads();
@@ -1160,20 +1201,23 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
                 load_rho_regs(p, rv);
                 store_rho(p, rv);
             }
-            load_jg(z0, jo, jr);
+            load_jg(z0, jo, jr, wo, wr);
+            load_acc(z0 + 1, wo, wr);
             __syncthreads();
             make_lap(z0 + 1);
             make_lap(z0 + 2);
             __syncthreads();
             make_fields(z0, jo, jr, Zc);
-            load_jg(z0 + 1, jo, jr);
+            load_jg(z0 + 1, jo, jr, wo, wr);
+            load_acc(z0 + 2, wo, wr);
             load_rho_regs(z0 + 4, rv);
             __syncthreads();
             store_rho(z0 + 4, rv);
         } else {
             load_rho_regs(0, rv);
             store_rho(0, rv);
-            load_jg(0, jo, jr);
+            load_acc(0, wo, wr);
+            load_jg(0, jo, jr, wo, wr);
             __syncthreads();
             make_lap(0);
             __syncthreads();
@@ -1218,7 +1262,8 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         CenterF<C> Zp;
         if (D == 3) {
             load_rho_regs(z + 5, rv);
-            load_jg(z + 2, jon, jrn);
+            load_jg(z + 2, jon, jrn, wo, wr);
+            load_acc(z + 3, wo, wr);
             make_lap(z + 3);
             make_fields(z + 1, jo, jr, Zp);
             __syncthreads();

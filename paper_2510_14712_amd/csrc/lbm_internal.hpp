@@ -35,7 +35,8 @@ struct lbm_ctx {
     // single-pass fused step: moment side channel of the current state
     bool fused = false;
     void *Mc[2] = {nullptr, nullptr};  // [nlay][5][ny][nx]
-    void *Tsur = nullptr;              // surrogate form: T of every cell for the fused step
+    void *Tsur = nullptr;              // surrogate form: the network's T of every cell for the fused step
+    void *Acc = nullptr;               // and whether it passed the residual check: bits [z][y][x / 64]
     void *IN[2] = {nullptr, nullptr};  // [nlay][tiles][5][slots]
     // side channel state: Mc[mcc] holds the complete moments the next fused
     // step reads; mc_pending: the last fused step's partial sums in
