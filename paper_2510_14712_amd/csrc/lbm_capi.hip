@@ -314,6 +314,19 @@ template <int D, class S> struct Impl {
         rs[2] = (C)sg;
         rs[3] = (C)(sg - (double)rs[2]);
     }
+    // full tiles and periodic x, y: the instance without wall and
+    // partial-tile handling.  With 16-bit storage and the explicit EOS that
+    // instance also completes its input moments itself (kfold) and needs z
+    // segments of at least 6 planes; shorter ones take the general instance.
+    static constexpr bool fold_storage = sizeof(T) == 2;
+    template <bool M> static bool fast_instance(const lbm_ctx *c) {
+        using TL = TileOf<S, M>;
+        const bool fast = c->p.nx % TL::TX == 0 && c->p.ny % TL::TY == 0 && c->p.bc[0] == LBM_BC_PERIODIC &&
+                          c->p.bc[1] == LBM_BC_PERIODIC;
+        if (!fast || M || !fold_storage || D == 2) return fast;
+        return c->p.nz / c->nseg >= 6;
+    }
+    static bool kfold(const lbm_ctx *c) { return fold_storage && !mlp(c) && c->fused && fast_instance<false>(c); }
     // the fused step proper (kind 0 of step_timed)
     static void fused_main(lbm_ctx *c) { mlp(c) ? fused_main_t<true>(c) : fused_main_t<false>(c); }
     template <bool M> static void fused_main_t(lbm_ctx *c) {
@@ -342,15 +355,13 @@ template <int D, class S> struct Impl {
         a.Mci = (const C *)c->Mc[c->mcc];
         a.Mco = (C *)c->Mc[1 - c->mcc];
         a.INo = (C *)c->IN[1 - c->mcc];
+        a.INi = (const C *)c->IN[c->mcc];
         a.Tin = (const C *)c->Tsur;
         a.Acc = (const unsigned *)c->Acc;
         a.accw = 2 * ((c->p.nx + 63) / 64);
         a.inv_cv_d = 1.0 / (double)(float)c->p.cv;
         const dim3 grid((unsigned)(c->ntx * c->nty * c->nseg));
-        // full tiles and periodic x, y: the specialisation without wall and
-        // partial-tile handling
-        const bool fast = c->p.nx % TL::TX == 0 && c->p.ny % TL::TY == 0 && c->p.bc[0] == LBM_BC_PERIODIC &&
-                          c->p.bc[1] == LBM_BC_PERIODIC;
+        const bool fast = fast_instance<M>(c);
         if constexpr (M && std::is_same<C, float>::value) {
             if (fast) hipLaunchKernelGGL((k_fused<D, S, TL, true, true>), grid, dim3(TL::NT), 0, c->stream, a);
             else hipLaunchKernelGGL((k_fused<D, S, TL, true, false>), grid, dim3(TL::NT), 0, c->stream, a);
@@ -367,16 +378,19 @@ template <int D, class S> struct Impl {
     static bool fold(const lbm_ctx *c) {
         return mlp(c) && c->p.nx >= 2 && c->p.ny >= 2 && c->p.nx % 64 != 1 && c->p.ny % 4 != 1;
     }
-    // completes the output moments (kind 1 of step_timed) and flips the state
+    // completes the output moments (kind 1 of step_timed) and flips the state;
+    // after a folding step only the segment-end planes (the next step adds
+    // the perimeter cells' slots on load)
     static void fused_fixup(lbm_ctx *c) { mlp(c) ? fused_fixup_t<true>(c) : fused_fixup_t<false>(c); }
     template <bool M> static void fused_fixup_t(lbm_ctx *c) {
         using TL = TileOf<S, M>;
         if (!c->mc_pending || fold(c)) return;
         const int nxt = 1 - c->mcc;
         const long long per = (long long)c->ntx * c->nty * TL::PMAX;
-        hipLaunchKernelGGL((k_fused_fixup<D, TL, C>), dim3((unsigned)((per + BX - 1) / BX), c->p.nz), dim3(BX), 0,
-                           c->stream, c->grid, c->ntx, c->nty, c->nseg, 0, (C *)c->Mc[nxt],
-                           (const C *)c->IN[nxt]);
+        if (!kfold(c))
+            hipLaunchKernelGGL((k_fused_fixup<D, TL, C>), dim3((unsigned)((per + BX - 1) / BX), c->p.nz), dim3(BX),
+                               0, c->stream, c->grid, c->ntx, c->nty, c->nseg, 0, (C *)c->Mc[nxt],
+                               (const C *)c->IN[nxt]);
         if (D == 3) {
             const long long plane = (long long)c->p.nx * c->p.ny;
             hipLaunchKernelGGL((k_fused_fixup<D, TL, C>), dim3((unsigned)((plane + BX - 1) / BX), 2 * c->nseg),

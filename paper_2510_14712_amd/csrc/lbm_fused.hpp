@@ -87,6 +87,7 @@ template <class C, class T> struct FusedArgs {
     T *fo;        // output pair buffer
     const C *Mci;  // complete moments of the input state, [nlay][5][ny][nx]
     C *Mco, *INo;  // output: tile-own partial sums, inbound slots [nlay][tiles][5][NR]
+    const C *INi;  // folding instances: the input state's inbound slots (Mci then holds partial sums)
     // surrogate equation of state (kernels built with MLP)
     const C *Tin;  // surrogate form: the network's T of every cell from k_eos_surrogate ([z][y][x])
     // which cells' network T passed the residual check: bit x % 32 of word
@@ -802,6 +803,17 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         g.clampx = 0;
         g.clampy = 0;
     }
+    // FOLD (the full-tile periodic instances with 16-bit storage and the
+    // explicit EOS): the input side channel holds the previous step's
+    // tile-own partial sums -- complete only on the segment-end planes, which
+    // the fix-up's end-plane launch completes -- and INi its inbound slots.
+    // Every moment read is completed on load with the fix-up's terms, order
+    // and rounding (a perimeter cell adds its side, bottom/top and corner
+    // slot), so the step needs no pass over the tiles' perimeter cells.  The
+    // extra loads cost these instances less than the pass they replace; the
+    // FP32 instance, already at the register limit, ran 30 % slower with them
+    // and keeps the separate fix-up.
+    constexpr bool FOLD = FAST && !MLP && sizeof(T) == 2;
     const long long N = g.N;
     const long long plane = (long long)g.nx * g.ny;
     const int tid = threadIdx.x;
@@ -852,6 +864,36 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         const int r = min(tid + k * NT, TL::R3 - 1);
         rho_off[k] = (unsigned)(axis_global(x0, r % TL::W3 - 3, g.nx, g.clampx) +
                                 g.nx * axis_global(y0, r / TL::W3 - 3, g.ny, g.clampy));
+    }
+    // FOLD: byte offsets (moment 0, within a layer) of the side, bottom/top
+    // and corner slot of a lattice cell in its tile's slot array, and whether
+    // it lies on the tile's left/right and bottom/top edge (full tiles)
+    struct SlotRef {
+        unsigned sh, sv, sc;
+        bool hs, vs;
+    };
+    auto slot_ref = [&](int xe, int ye) {
+        const int ttx = xe / TX, tty = ye / TY;
+        const int ex = xe - ttx * TX, ey = ye - tty * TY;
+        const bool l = ex == 0, r = ex == TX - 1, b = ey == 0, t = ey == TY - 1;
+        const unsigned base = (unsigned)(tty * a.ntx + ttx) * 5u * TL::NR;
+        SlotRef o;
+        o.sh = (base + (unsigned)((l ? TL::FROM_L : TL::FROM_R) + ey)) * (unsigned)sizeof(C);
+        o.sv = (base + (unsigned)((b ? TL::FROM_B : TL::FROM_T) + ex)) * (unsigned)sizeof(C);
+        o.sc = (base + (unsigned)(TL::FROM_BL + (r ? 1 : 0) + (t ? 2 : 0))) * (unsigned)sizeof(C);
+        o.hs = l || r;
+        o.vs = b || t;
+        return o;
+    };
+    SlotRef rho_ref[FOLD ? NR3 : 1], own_ref{}, ring_ref{};
+    if constexpr (FOLD) {
+#pragma unroll
+        for (int k = 0; k < NR3; k++) {
+            const int r = min(tid + k * NT, TL::R3 - 1);
+            rho_ref[k] = slot_ref(axis_global(x0, r % TL::W3 - 3, g.nx, 0), axis_global(y0, r / TL::W3 - 3, g.ny, 0));
+        }
+        own_ref = slot_ref(gx, gy);
+        ring_ref = ring ? slot_ref(axis_global(x0, rx, g.nx, 0), axis_global(y0, ry, g.ny, 0)) : own_ref;
     }
     // Laplacian on R2: R3 index of the evaluation point
     int lap_c[NR2];
@@ -920,16 +962,49 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
     for (int r = tid; r < (D == 3 ? 3 : 1) * 5 * TL::NR; r += NT) (&sRacc[0][0][0])[r] = C(0);
 
     // -- pipeline stages -----------------------------------------------------
-    auto load_rho_regs = [&](int p, C *v) {
+    // FOLD: inbound slots of the input state, one resource per layer
+    const unsigned in_layer = (unsigned)(a.ntx * a.nty) * 5u * TL::NR;
+    auto in_in = [&](int layer) { return make_rsrc(a.INi + (size_t)layer * in_layer, in_layer * (unsigned)sizeof(C)); };
+    auto ld_slots = [&](Rsrc ri, const SlotRef &sl, int m, C(&v)[3]) {
+        const unsigned mo = (unsigned)m * TL::NR * (unsigned)sizeof(C);
+        buf_ld(ri, sl.sh, mo, v[0]);
+        buf_ld(ri, sl.sv, mo, v[1]);
+        buf_ld(ri, sl.sc, mo, v[2]);
+    };
+    // the complete moment: inbound_sum_2x2's terms and order added to the
+    // partial sum of a perimeter cell
+    auto complete = [&](C mc, const C(&v)[3], const SlotRef &sl) {
+        const C sum = ((sl.hs ? v[0] : C(0)) + (sl.vs ? v[1] : C(0))) + ((sl.hs && sl.vs) ? v[2] : C(0));
+        return (sl.hs || sl.vs) ? mc + sum : mc;
+    };
+    // segment-end planes hold complete moments already (the end-plane
+    // fix-up); with segments of at least 6 planes the march's window
+    // [z0 - 3, z1 + 5) meets no other segment's end plane
+    const int zend_below = D == 3 ? zwrap(z0 - 1) : -1, zend_above = D == 3 ? zwrap(z1) : -1;
+    auto is_end = [&](int p) {
+        if (D != 3) return false;
+        const int wp = zwrap(p);
+        return wp == z0 || wp == z1 - 1 || wp == zend_below || wp == zend_above;
+    };
+    auto load_rho_regs = [&](int p, C *v, C(*vs)[3]) {
         const Rsrc r = mc_layer(a.Mci, zwrap(p));
 #pragma unroll
         for (int k = 0; k < NR3; k++) v[k] = mom(r, 0, rho_off[k]);
-    };
-    auto store_rho = [&](int p, const C *v) {
-        C *dst = sRho[s4(p)];
+        if constexpr (FOLD) {
+            const Rsrc ri = in_in(zwrap(p));
 #pragma unroll
-        for (int k = 0; k < NR3; k++)
-            if (tid + k * NT < TL::R3) dst[tid + k * NT] = v[k];
+            for (int k = 0; k < NR3; k++) ld_slots(ri, rho_ref[k], 0, vs[k]);
+        }
+    };
+    auto store_rho = [&](int p, const C *v, const C(*vs)[3]) {
+        C *dst = sRho[s4(p)];
+        const bool add = FOLD && !is_end(p);
+#pragma unroll
+        for (int k = 0; k < NR3; k++) {
+            C x = v[k];
+            if constexpr (FOLD) x = add ? complete(x, vs[k], rho_ref[k]) : x;
+            if (tid + k * NT < TL::R3) dst[tid + k * NT] = x;
+        }
     };
     // surrogate form: acceptance words of the own and the ring cell of plane
     // p (loaded one plane ahead of the temperatures they select)
@@ -968,6 +1043,28 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
             buf_ld(rt, ar ? ring_off * (unsigned)sizeof(C) : 0u, 0u, jr[4]);
             jo[5] = ao ? C(1) : C(0);
             jr[5] = ar ? C(1) : C(0);
+        }
+    };
+    // FOLD: the slots of j, G of plane p for the own and the ring cell, and the
+    // completion of a raw load_jg with them
+    auto load_jg_slots = [&](int p, C(*os)[3], C(*rs)[3]) {
+        if constexpr (FOLD) {
+            const Rsrc ri = in_in(zwrap(p));
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                ld_slots(ri, own_ref, 1 + k, os[k]);
+                ld_slots(ri, ring_ref, 1 + k, rs[k]);
+            }
+        }
+    };
+    auto complete_jg = [&](int p, C *jo, C *jr, const C(*os)[3], const C(*rs)[3]) {
+        if constexpr (FOLD) {
+            const bool add = !is_end(p);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                jo[k] = add ? complete(jo[k], os[k], own_ref) : jo[k];
+                jr[k] = add ? complete(jr[k], rs[k], ring_ref) : jr[k];
+            }
         }
     };
     auto make_lap = [&](int p) {
@@ -1070,7 +1167,6 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         for (int k = 0; k < 5; k++) acc[q][k] = C(0);
     // inbound slots, layer-major: one resource per layer over every tile's
     // slots (the whole array may exceed what one resource addresses)
-    const unsigned in_layer = (unsigned)(a.ntx * a.nty) * 5u * TL::NR;
     auto in_rsrc = [&](int layer) { return make_rsrc(a.INo + (size_t)layer * in_layer, in_layer * (unsigned)sizeof(C)); };
     // write plane p (own: acc[0]) to `layer`, then clear its ring slot; the
     // reference sums enter once per cell, with the tile-own part of its plane
@@ -1174,23 +1270,31 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
     constexpr int NJ = MLP ? 6 : 4;  // j, G (and T, accepted flag of the surrogate form) per cell
     C jo[NJ], jr[NJ];
     unsigned wo = 0, wr = 0;  // acceptance words of the next plane whose j, G are loaded
+    C jos[FOLD ? 4 : 1][3], jrs[FOLD ? 4 : 1][3];  // FOLD: slots of the j, G in flight
+    C rvs[FOLD ? NR3 : 1][3];                       // FOLD: slots of the rho entries in flight
+    // j, G of plane p complete on return (the prologue's loads)
+    auto load_jg_now = [&](int p) {
+        load_jg(p, jo, jr, wo, wr);
+        load_jg_slots(p, jos, jrs);
+        complete_jg(p, jo, jr, jos, jrs);
+    };
     {
         C rv[NR3];
         if (D == 3) {
             // four rho slots: each plane is overwritten once its last reader
             // has passed a barrier
             for (int p = z0 - 3; p <= z0; p++) {
-                load_rho_regs(p, rv);
-                store_rho(p, rv);
+                load_rho_regs(p, rv, rvs);
+                store_rho(p, rv, rvs);
             }
             __syncthreads();
             make_lap(z0 - 2);
             make_lap(z0 - 1);
             __syncthreads();
-            load_rho_regs(z0 + 1, rv);
-            store_rho(z0 + 1, rv);
+            load_rho_regs(z0 + 1, rv, rvs);
+            store_rho(z0 + 1, rv, rvs);
             load_acc(z0 - 1, wo, wr);
-            load_jg(z0 - 1, jo, jr, wo, wr);
+            load_jg_now(z0 - 1);
             load_acc(z0, wo, wr);
             __syncthreads();
             make_lap(z0);
@@ -1198,26 +1302,26 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
             make_fields(z0 - 1, jo, jr, Zm4);
             __syncthreads();
             for (int p = z0 + 2; p <= z0 + 3; p++) {
-                load_rho_regs(p, rv);
-                store_rho(p, rv);
+                load_rho_regs(p, rv, rvs);
+                store_rho(p, rv, rvs);
             }
-            load_jg(z0, jo, jr, wo, wr);
+            load_jg_now(z0);
             load_acc(z0 + 1, wo, wr);
             __syncthreads();
             make_lap(z0 + 1);
             make_lap(z0 + 2);
             __syncthreads();
             make_fields(z0, jo, jr, Zc);
-            load_jg(z0 + 1, jo, jr, wo, wr);
+            load_jg_now(z0 + 1);
             load_acc(z0 + 2, wo, wr);
-            load_rho_regs(z0 + 4, rv);
+            load_rho_regs(z0 + 4, rv, rvs);
             __syncthreads();
-            store_rho(z0 + 4, rv);
+            store_rho(z0 + 4, rv, rvs);
         } else {
-            load_rho_regs(0, rv);
-            store_rho(0, rv);
+            load_rho_regs(0, rv, rvs);
+            store_rho(0, rv, rvs);
             load_acc(0, wo, wr);
-            load_jg(0, jo, jr, wo, wr);
+            load_jg_now(0);
             __syncthreads();
             make_lap(0);
             __syncthreads();
@@ -1261,7 +1365,7 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         C rv[NR3], jon[NJ], jrn[NJ];
         CenterF<C> Zp;
         if (D == 3) {
-            load_rho_regs(z + 5, rv);
+            load_rho_regs(z + 5, rv, rvs);
             load_jg(z + 2, jon, jrn, wo, wr);
             load_acc(z + 3, wo, wr);
             make_lap(z + 3);
@@ -1308,7 +1412,7 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
             collide_cell<D>(a.ph, in, f, gq);
         }
         if (D == 3) {
-            store_rho(z + 5, rv);
+            store_rho(z + 5, rv, rvs);
 #pragma unroll
             for (int k = 0; k < NJ; k++) {
                 jo[k] = jon[k];
@@ -1347,11 +1451,13 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         xwrite(f, 0);
         xwrite(gq, GROW);
         if (D == 3 && z + 1 < z1) load_pops(z + 1);
+        if (D == 3) load_jg_slots(z + 2, jos, jrs);  // FOLD (live across the gather, not the collision)
         __syncthreads();
         rounds(WFG{});
         if (D == 3) {
             flush(z - 1, z == z0 ? nz + 2 * seg : z - 1);  // plane z-1 is complete
             shift_acc();
+            complete_jg(z + 2, jo, jr, jos, jrs);  // FOLD: j, G of plane z+2 (moved into jo, jr above)
             Zm4 = Zc;
             Zc = Zp;
         } else {

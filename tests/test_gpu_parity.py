@@ -532,6 +532,52 @@ def test_checkpoint_resume_bitwise(storage):
         assert bool((fa == fb).all()) and bool((ga == gb).all())
 
 
+@pytest.mark.parametrize("storage,nseg", [("bf16", 1), ("bf16", 3), ("f16", 2), ("f16", 4), ("f32", 2)])
+def test_checkpoint_resume_bitwise_folding_instance(storage, nseg):
+    """The full-tile periodic instance with 16-bit storage and the explicit
+    EOS completes its input moments on load (the previous step's tile-own
+    partial sums plus inbound slots; segment-end planes completed by the
+    end-plane fix-up).  A run restarted from its populations, whose moments
+    the library recomputes complete, continues bit for bit like the
+    uninterrupted one: 128 x 8 x 24 periodic, 1 to 4 z segments (FP32: the
+    same instance with the separate fix-up)."""
+    lbm = _lbm()
+    shape = (128, 8, 24)
+    _assert_fast_instance(shape, (0, 0, 0), storage)
+    rho, u, T = inputs.random_state(3, shape, 21, RHOC, 1.1 * TC)
+    kw = dict(KW, zsegments=nseg)
+    if storage != "f32":
+        kw.update(ref_rho=RHOC, ref_T=1.1 * TC)
+    _say(f"case resume folding instance {storage} nseg {nseg}")
+    with lbm.Lattice(3, shape, storage=storage, **kw) as a, lbm.Lattice(3, shape, storage=storage, **kw) as b:
+        a.init(rho, u, T).step(5)
+        f, g = a.get_populations()
+        b.set_populations(f, g)
+        a.step(9)
+        b.step(9)
+        fa, ga = a.get_populations()
+        fb, gb = b.get_populations()
+        assert bool((fa == fb).all()) and bool((ga == gb).all())
+
+
+@pytest.mark.parametrize("storage,nseg", [("bf16", 1), ("bf16", 3), ("f16", 2), ("f16", 4), ("bf16", 5)])
+def test_folding_instance_z_segments_step_by_step(storage, nseg):
+    """The folding instance (16-bit storage, explicit EOS, full tiles,
+    periodic) on identical inputs (see _step_by_step_16bit), upwind switch
+    active: 128 x 8 x 24 with 1 to 5 z segments, three steps after two of
+    warm-up, so that its input moments are the previous step's partial sums
+    and inbound slots completed on load; 5 segments (4-5 planes) run the
+    general instance with the separate fix-up."""
+    lbm = _lbm()
+    shape = (128, 8, 24)
+    _assert_fast_instance(shape, (0, 0, 0), storage)
+    rho, u, T = inputs.random_state(3, shape, 22, RHOC, 1.1 * TC, drho=0.04, du=0.08, dT=0.03, white=0.002)
+    _say(f"case folding instance step by step {storage} nseg {nseg}")
+    with lbm.Lattice(3, shape, storage=storage, ref_rho=RHOC, ref_T=1.1 * TC, zsegments=nseg, **KW) as lat:
+        lat.init(rho, u, T).step(2)
+        _step_by_step_16bit(lat, 3, shape, (0, 0, 0), storage, 3)
+
+
 def test_conservation_sums():
     lbm = _lbm()
     D, shape = 3, (24, 10, 8)
