@@ -305,6 +305,11 @@ __device__ __forceinline__ void buf_st(Rsrc r, unsigned vo, unsigned so, double 
 __device__ __forceinline__ void buf_st(Rsrc r, unsigned vo, unsigned so, uint16_t v) {
     __builtin_amdgcn_raw_buffer_store_b16(v, r, vo, so, 0);
 }
+// byte offset of an absent inbound slot: beyond every slot resource (each
+// below 2^31 bytes), so the buffer load's range check returns zero without a
+// memory access.  A cell's slot sum then needs no per-slot select and equals
+// inbound_sum_2x2's, whose absent terms are zeros too.
+constexpr unsigned SLOT_NONE = 0x80000000u;
 // the (f_i, g_i) pair of one cell in one access
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // (vector elements are copied to scalars before __builtin_bit_cast: this
@@ -453,9 +458,10 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     const int ol = (yc - y0 + 1) * LW + (xc - x0 + 1);  // the cell in the Laplacian region
     const int orr = (yc - y0 + 2) * RW + (xc - x0 + 2);  // and in the rho region
 
-    // FOLD: inbound-slot byte offsets (moment 0, within a layer) of a lattice cell:
-    // its side, bottom/top and corner slot in its tile's array, and whether it
-    // lies on the tile's left/right and bottom/top edge (as in inbound_sum)
+    // FOLD: inbound-slot byte offsets (moment 0, within a layer) of a lattice
+    // cell: its side, bottom/top and corner slot in its tile's array
+    // (SLOT_NONE where the cell has none), and whether it lies on the tile's
+    // left/right and bottom/top edge (as in inbound_sum)
     struct Slots {
         unsigned sh, sv, sc;
         bool hs, vs;
@@ -466,11 +472,12 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
         const bool l = lx == 0, r = lx == w - 1, b = ly == 0, t = ly == h - 1;
         const unsigned base = (unsigned)(ty * fa.ntx + tx) * 5u * TL::NR;
         Slots o;  // byte offsets
-        o.sh = (base + (unsigned)((l ? TL::FROM_L : TL::FROM_R) + ly)) * (unsigned)sizeof(float);
-        o.sv = (base + (unsigned)((b ? TL::FROM_B : TL::FROM_T) + lx)) * (unsigned)sizeof(float);
-        o.sc = (base + (unsigned)(TL::FROM_BL + (r ? 1 : 0) + (t ? 2 : 0))) * (unsigned)sizeof(float);
         o.hs = l || r;
         o.vs = b || t;
+        o.sh = o.hs ? (base + (unsigned)((l ? TL::FROM_L : TL::FROM_R) + ly)) * (unsigned)sizeof(float) : SLOT_NONE;
+        o.sv = o.vs ? (base + (unsigned)((b ? TL::FROM_B : TL::FROM_T) + lx)) * (unsigned)sizeof(float) : SLOT_NONE;
+        o.sc = o.hs && o.vs ? (base + (unsigned)(TL::FROM_BL + (r ? 1 : 0) + (t ? 2 : 0))) * (unsigned)sizeof(float)
+                            : SLOT_NONE;
         return o;
     };
     Slots rsl[KR], osl;
@@ -558,8 +565,7 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     // (two functions: the ordinary planes' form has no branch and no load; the
     // caller picks one per plane)
     auto complete = [&](float mc, const float (&sv)[3], const Slots &sl) {
-        const float sum = ((sl.hs ? sv[0] : 0.0f) + (sl.vs ? sv[1] : 0.0f)) + ((sl.hs && sl.vs) ? sv[2] : 0.0f);
-        return (sl.hs || sl.vs) ? mc + sum : mc;
+        return (sl.hs || sl.vs) ? mc + ((sv[0] + sv[1]) + sv[2]) : mc;  // absent slots read as zero
     };
     auto complete_end = [&](float mc, const float (&sv)[3], const Slots &sl, unsigned cell, int m,
                             const EndInfo &ei) {
@@ -866,8 +872,9 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
                                 g.nx * axis_global(y0, r / TL::W3 - 3, g.ny, g.clampy));
     }
     // FOLD: byte offsets (moment 0, within a layer) of the side, bottom/top
-    // and corner slot of a lattice cell in its tile's slot array, and whether
-    // it lies on the tile's left/right and bottom/top edge (full tiles)
+    // and corner slot of a lattice cell in its tile's slot array (SLOT_NONE
+    // where it has none), and whether it lies on the tile's left/right and
+    // bottom/top edge (full tiles)
     struct SlotRef {
         unsigned sh, sv, sc;
         bool hs, vs;
@@ -878,11 +885,12 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         const bool l = ex == 0, r = ex == TX - 1, b = ey == 0, t = ey == TY - 1;
         const unsigned base = (unsigned)(tty * a.ntx + ttx) * 5u * TL::NR;
         SlotRef o;
-        o.sh = (base + (unsigned)((l ? TL::FROM_L : TL::FROM_R) + ey)) * (unsigned)sizeof(C);
-        o.sv = (base + (unsigned)((b ? TL::FROM_B : TL::FROM_T) + ex)) * (unsigned)sizeof(C);
-        o.sc = (base + (unsigned)(TL::FROM_BL + (r ? 1 : 0) + (t ? 2 : 0))) * (unsigned)sizeof(C);
         o.hs = l || r;
         o.vs = b || t;
+        o.sh = o.hs ? (base + (unsigned)((l ? TL::FROM_L : TL::FROM_R) + ey)) * (unsigned)sizeof(C) : SLOT_NONE;
+        o.sv = o.vs ? (base + (unsigned)((b ? TL::FROM_B : TL::FROM_T) + ex)) * (unsigned)sizeof(C) : SLOT_NONE;
+        o.sc = o.hs && o.vs ? (base + (unsigned)(TL::FROM_BL + (r ? 1 : 0) + (t ? 2 : 0))) * (unsigned)sizeof(C)
+                            : SLOT_NONE;
         return o;
     };
     SlotRef rho_ref[FOLD ? NR3 : 1], own_ref{}, ring_ref{};
@@ -974,8 +982,7 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
     // the complete moment: inbound_sum_2x2's terms and order added to the
     // partial sum of a perimeter cell
     auto complete = [&](C mc, const C(&v)[3], const SlotRef &sl) {
-        const C sum = ((sl.hs ? v[0] : C(0)) + (sl.vs ? v[1] : C(0))) + ((sl.hs && sl.vs) ? v[2] : C(0));
-        return (sl.hs || sl.vs) ? mc + sum : mc;
+        return (sl.hs || sl.vs) ? mc + ((v[0] + v[1]) + v[2]) : mc;  // absent slots read as zero
     };
     // segment-end planes hold complete moments already (the end-plane
     // fix-up); with segments of at least 6 planes the march's window
