@@ -578,6 +578,22 @@ def test_folding_instance_z_segments_step_by_step(storage, nseg):
         _step_by_step_16bit(lat, 3, shape, (0, 0, 0), storage, 3)
 
 
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_folding_instance_d2q9_step_by_step(storage):
+    """The folding instance on D2Q9 (one plane, no segment-end planes):
+    128 x 8 periodic, 16-bit storage, explicit EOS, three steps on identical
+    inputs after two of warm-up (see _step_by_step_16bit), upwind switch
+    active."""
+    lbm = _lbm()
+    shape = (128, 8)
+    _assert_fast_instance(shape, (0, 0, 0), storage)
+    rho, u, T = inputs.random_state(2, shape, 23, RHOC, 1.1 * TC, drho=0.04, du=0.08, dT=0.03, white=0.002)
+    _say(f"case folding instance D2Q9 step by step {storage}")
+    with lbm.Lattice(2, shape, storage=storage, ref_rho=RHOC, ref_T=1.1 * TC, **KW) as lat:
+        lat.init(rho, u, T).step(2)
+        _step_by_step_16bit(lat, 2, shape, (0, 0, 0), storage, 3)
+
+
 def test_conservation_sums():
     lbm = _lbm()
     D, shape = 3, (24, 10, 8)
