@@ -251,11 +251,13 @@ struct StoreBF16 {
     __device__ static __forceinline__ C load(const T *p, long long j, C ref) { return ref + bf16_to_f32(p[j]); }
     __device__ static __forceinline__ T enc(C v, C ref) { return bf16_hw(v - ref); }
     __device__ static __forceinline__ C dev(const T *p, long long j, C) { return bf16_to_f32(p[j]); }
-    // two populations in one convert
+    // one convert per population: the same bits as converting the pair in one
+    // v_cvt_pk_bf16_f32, which held more registers through the fused step's
+    // store loop (253 against 244 VGPRs, and a spill in the 16-bit instance
+    // that completes its input moments)
     __device__ static __forceinline__ void enc2(C a, C ra, C b, C rb, T &ea, T &eb) {
-        const uint32_t h = bf16x2_hw(a - ra, b - rb);
-        ea = (T)h;
-        eb = (T)(h >> 16);
+        ea = enc(a, ra);
+        eb = enc(b, rb);
     }
 };
 struct StoreF16 {
