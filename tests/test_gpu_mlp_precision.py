@@ -210,6 +210,47 @@ def test_step_surrogate_accepted_where_residual_allows():
     assert errs["trained", 1e-3]["rho"] <= 1e-3
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_full_tile_instance_uses_accepted_surrogate_temperature(storage):
+    """The full-tile periodic instance of the surrogate form (64 x 8 x 8, the
+    benchmark's kernel) takes the network's T where the residual check passed
+    (the pass's acceptance bits) and the exact FP64 inversion elsewhere: at
+    threshold 1e-2 the network is accepted almost everywhere, at 1e-6 almost
+    nowhere, and the two runs differ (were either bit ignored, both would take
+    the same temperatures everywhere and agree bit for bit).  Density against
+    the FP64 oracle after 20 steps: at 1e-2 the accepted temperatures may be
+    1 % off (the residual bounds |T_hat - T| by the threshold times T for van
+    der Waals), rho within 1e-2 (measured 2.2e-3 in FP32); at 1e-6 the storage
+    form's bar (FP32 1e-5, measured 4.5e-7; BF16 1e-3)."""
+    lbm = _lbm()
+    params, norm, _ = _train()
+    c = ST["tgv_3d_512"]
+    shape = (64, 8, 8)
+    assert shape[0] % 64 == 0 and shape[1] % 4 == 0
+    rho, u, T = inputs.taylor_green(shape, c["seed"], c["rho0"], c["T0"], c["U0"], c["noise"])
+    p = oracle.Params(3, shape, **KW)
+    ref = oracle.fields(p, *oracle.run(p, *oracle.init(p, rho, u, T), 20))
+    out = {}
+    for tol in (1e-2, 1e-6):
+        kw = dict(KW)
+        if storage != "f32":
+            kw.update(ref_rho=c["rho0"], ref_T=c["T0"])
+        with lbm.Lattice(3, shape, storage=storage, eos="mlp", mlp_tol=tol, **kw) as lat:
+            assert lat.fused
+            lat.mlp_set(params, norm)
+            lat.init(rho, u, T).step(20)
+            f, g = (t.cpu().numpy() for t in lat.get_populations())
+            mom = {k: v.cpu().numpy() for k, v in lat.moments().items()}
+            out[tol] = (lat.mlp_stats(), f, g, rel_l2(mom["rho"], ref["rho"]))
+        _say(f"  {storage} tol {tol}: fallback fraction {out[tol][0]:.4f}, rho rel-L2 {out[tol][3]:.2e}")
+    d = rel_l2(out[1e-2][1], out[1e-6][1].astype(np.float64))
+    _say(f"  populations f differ by rel-L2 {d:.2e} between the thresholds")
+    assert out[1e-2][0] < 0.1 and out[1e-6][0] > 0.9
+    assert d > 0.0
+    assert out[1e-2][3] <= 1e-2
+    assert out[1e-6][3] <= (1e-5 if storage == "f32" else 1e-3)
+
+
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
 def test_deviation_storage_error_per_field(storage):
     """BF16 / FP16 deviation storage with the explicit EOS, Taylor-Green
