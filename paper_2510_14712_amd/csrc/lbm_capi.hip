@@ -405,8 +405,13 @@ template <int D, class S> struct Impl {
     static void fused_eos(lbm_ctx *c) {
         if constexpr (std::is_same<C, float>::value) {
             if (!mlp(c)) return;
-            // 64 x 4 columns per workgroup, marching through chunks of 32 planes
-            const int zchunk = D == 3 ? 32 : 1;
+            // 64 x 4 columns per workgroup, marching through chunks of 56 planes
+            // (longer chunks spread the prologue -- rho region of four planes,
+            // two Laplacians, the permuted weights -- over more planes: 32 ->
+            // 56 took the pass 2.98 -> 2.88 ms at 512^3; the end-plane bitmask of
+            // the completing pass spans a chunk plus 6 planes, at most 64)
+            const int zchunk = D == 3 ? 56 : 1;
+            static_assert(56 + 6 <= 64, "end-plane bitmask of the surrogate pass");
             const dim3 grid((unsigned)((c->p.nx + 63) / 64), (unsigned)((c->p.ny + 3) / 4),
                             (unsigned)((c->p.nz + zchunk - 1) / zchunk));
             FoldArgs fa{nullptr, nullptr, c->ntx, c->nty, c->nseg};

@@ -537,7 +537,8 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
         bool lo, hi;
         int wq;
     };
-    // bit i: plane z0 - 2 + i (i < 64; a chunk spans at most zchunk + 6 planes)
+    // bit i: plane z0 - 2 + i (i < 64; a chunk spans zchunk + 6 planes, the
+    // host keeps zchunk <= 58)
     // is a segment's first (lo_m) / last (hi_m) plane, set up once per block
     unsigned long long lo_m = 0, hi_m = 0;
     if (D == 3 && FOLD) {
