@@ -380,12 +380,24 @@ template <int D, class S> struct Impl {
     }
     // completes the output moments (kind 1 of step_timed) and flips the state;
     // after a folding step only the segment-end planes (the next step adds
-    // the perimeter cells' slots on load)
+    // the perimeter cells' slots on load).  In the surrogate form with the
+    // completion in its pass, only the segment-end planes too, and the state
+    // stays pending: the pass adds the perimeter cells' slots and writes the
+    // complete moments to the other buffer.
     static void fused_fixup(lbm_ctx *c) { mlp(c) ? fused_fixup_t<true>(c) : fused_fixup_t<false>(c); }
     template <bool M> static void fused_fixup_t(lbm_ctx *c) {
         using TL = TileOf<S, M>;
-        if (!c->mc_pending || fold(c)) return;
+        if (!c->mc_pending) return;
         const int nxt = 1 - c->mcc;
+        if (fold(c)) {
+            if (D == 3) {
+                const long long plane = (long long)c->p.nx * c->p.ny;
+                hipLaunchKernelGGL((k_fused_fixup<D, TL, C>), dim3((unsigned)((plane + BX - 1) / BX), 2 * c->nseg),
+                                   dim3(BX), 0, c->stream, c->grid, c->ntx, c->nty, c->nseg, 1,
+                                   (C *)c->Mc[nxt], (const C *)c->IN[nxt]);
+            }
+            return;
+        }
         const long long per = (long long)c->ntx * c->nty * TL::PMAX;
         if (!kfold(c))
             hipLaunchKernelGGL((k_fused_fixup<D, TL, C>), dim3((unsigned)((per + BX - 1) / BX), c->p.nz), dim3(BX),
@@ -416,7 +428,8 @@ template <int D, class S> struct Impl {
                             (unsigned)((c->p.nz + zchunk - 1) / zchunk));
             FoldArgs fa{nullptr, nullptr, c->ntx, c->nty, c->nseg};
             if (fold(c) && c->mc_pending) {
-                // partial sums and slots of the last fused step in, complete
+                // partial sums and slots of the last fused step in (its
+                // segment-end planes completed by the fix-up), complete
                 // moments out to the buffer that step read
                 fa.IN = (const float *)c->IN[1 - c->mcc];
                 fa.Mco = (float *)c->Mc[c->mcc];
@@ -975,9 +988,9 @@ const char *lbm_last_error(void) { return g_last_error; }
 
 const char *lbm_kernel_name(const lbm_ctx *c, int k) {
     static const char *names[LBM_NUM_KERNELS] = {"k_moments", "k_lap", "k_fields", "k_collide"};
-    if (c && c->fused)  // the surrogate pass does the fix-up's work when folded
+    if (c && c->fused)  // folded: the surrogate pass does the fix-up's work but on the segment-end planes
         return k == 0 ? "k_fused"
-                      : (k == 1 ? (c->folded ? "" : "k_fused_fixup")
+                      : (k == 1 ? (c->folded && c->p.lattice == 2 ? "" : "k_fused_fixup")
                                 : (k == 2 && c->p.eos == LBM_EOS_MLP ? "k_eos_surrogate" : ""));
     return k >= 0 && k < LBM_NUM_KERNELS ? names[k] : "";
 }

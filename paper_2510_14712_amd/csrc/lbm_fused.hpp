@@ -373,11 +373,12 @@ template <class C> struct CenterF {
 // point; the region loads and the cell's j, G run two planes ahead of their use,
 // so that their latency overlaps the network of the planes between.
 //
-// FOLD: the pass also completes the side channel, doing k_fused_fixup's work.
-// Mc then holds the previous fused step's partial sums, IN its inbound slots
-// and spill layers; every value the pass uses is completed on load with the
-// fix-up's terms, order and rounding (a perimeter cell adds its slots, every
-// cell of a segment's end plane its slots and the spill layers), and the five
+// FOLD: the pass also completes the side channel, doing the perimeter part of
+// k_fused_fixup's work.  Mc then holds the previous fused step's partial sums,
+// complete already on the segment-end planes (the fix-up's end-plane launch
+// runs between the fused step and the pass), and IN its inbound slots; every
+// value the pass uses on another plane is completed on load with the fix-up's
+// terms, order and rounding (a perimeter cell adds its slots), and the five
 // complete moments of every cell go to Mco, which the next fused step reads.
 // The fused step's tiles are the pass's 64 x 4 blocks; tiles of at least 2 x 2
 // cells (the host falls back to the separate fix-up otherwise).
@@ -530,65 +531,23 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
         buf_ld(ri, sl.sv, mo, v[1]);
         buf_ld(ri, sl.sc, mo, v[2]);
     };
-    // the segment structure of plane wq (D = 3, FOLD): an end plane of its z
-    // segment also takes the spill layers (lay_hi on its first plane, from the
-    // segment below; lay_lo on its last, from the segment above)
-    struct EndInfo {
-        bool lo, hi;
-        int wq;
-    };
     // bit i: plane z0 - 2 + i (i < 64; a chunk spans zchunk + 6 planes, the
-    // host keeps zchunk <= 58)
-    // is a segment's first (lo_m) / last (hi_m) plane, set up once per block
-    unsigned long long lo_m = 0, hi_m = 0;
+    // host keeps zchunk <= 58) is a segment's first or last plane, whose
+    // moments the end-plane fix-up has completed; set up once per block
+    unsigned long long end_m = 0;
     if (D == 3 && FOLD) {
         for (int i = 0; i < 64 && z0_blk - 2 + i < z1_blk + 4; i++) {
             const int wq = zw(z0_blk - 2 + i), sg = seg_of(wq, nz, fa.nseg);
-            if (wq == seg_lo(sg, nz, fa.nseg)) lo_m |= 1ull << i;
-            if (wq == seg_lo(sg + 1, nz, fa.nseg) - 1) hi_m |= 1ull << i;
+            if (wq == seg_lo(sg, nz, fa.nseg) || wq == seg_lo(sg + 1, nz, fa.nseg) - 1) end_m |= 1ull << i;
         }
     }
-    // q: the plane (unwrapped), wq: its layer
-    auto end_info = [&](int q, int wq) {
-        EndInfo ei{false, false, wq};
-        if (D == 3 && FOLD) {
-            const int i = q - (z0_blk - 2);
-            ei.lo = (lo_m >> i) & 1ull;
-            ei.hi = (hi_m >> i) & 1ull;
-        }
-        return ei;
-    };
-    // complete moment m of a cell (lane offset `cell` in a plane) of layer wq
-    // from its partial sum mc and slots sv: on an ordinary plane a perimeter
-    // cell adds its slots (inbound_sum_2x2), on an end plane every cell adds
-    // them (inbound_sum) and then the spill layers with their slots -- the
-    // terms, order and rounding of k_fused_fixup's two modes
-    // (two functions: the ordinary planes' form has no branch and no load; the
-    // caller picks one per plane)
+    // plane q (unwrapped) is a segment-end plane
+    auto is_end = [&](int q) { return D == 3 && FOLD && ((end_m >> (q - (z0_blk - 2))) & 1ull) != 0; };
+    // complete moment of a cell from its partial sum mc and slots sv: a
+    // perimeter cell adds its slots (inbound_sum_2x2's terms, order and
+    // rounding); the slots of an interior cell are absent and read as zero
     auto complete = [&](float mc, const float (&sv)[3], const Slots &sl) {
-        return (sl.hs || sl.vs) ? mc + ((sv[0] + sv[1]) + sv[2]) : mc;  // absent slots read as zero
-    };
-    auto complete_end = [&](float mc, const float (&sv)[3], const Slots &sl, unsigned cell, int m,
-                            const EndInfo &ei) {
-        auto gen = [&](const float (&t)[3]) {
-            float v = 0.0f;
-            if (sl.hs) v += t[0];
-            if (sl.vs) v += t[1];
-            if (sl.hs && sl.vs) v += t[2];
-            return v;
-        };
-        float v = mc + gen(sv);
-        const int sg = seg_of(ei.wq, nz, fa.nseg);
-        for (int side = 0; side < 2; side++) {
-            if (!(side == 0 ? ei.lo : ei.hi)) continue;
-            const int lay = side == 0 ? nz + 2 * ((sg + fa.nseg - 1) % fa.nseg) + 1   // from the segment below
-                                      : nz + 2 * ((sg + 1) % fa.nseg);                // from the segment above
-            float ms, ts[3];
-            buf_ld(mcr(lay), cell * (unsigned)sizeof(float), (unsigned)m * ko, ms);
-            load_slots(inr(lay), sl, m, ts);
-            v += ms + gen(ts);
-        }
-        return v;
+        return (sl.hs || sl.vs) ? mc + ((sv[0] + sv[1]) + sv[2]) : mc;
     };
     auto load_rho = [&](int wq, RhoIn &v) {
         const Rsrc r = mcr(wq);
@@ -600,23 +559,16 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
             for (int k = 0; k < KR; k++) load_slots(ri, rsl[k], 0, v.s[k]);
         }
     };
-    // rho of ring slot q (plane counter wq) into LDS, completed (FOLD)
-    auto put_rho = [&](int q, int wq, const RhoIn &v) {
-        float x[KR];
+    // rho of plane q into its LDS ring slot, completed (FOLD) unless q is a
+    // segment-end plane
+    auto put_rho = [&](int q, const RhoIn &v) {
+        const bool add = FOLD && !is_end(q);
 #pragma unroll
-        for (int k = 0; k < KR; k++) x[k] = v.m[k];
-        if (FOLD) {
-            const EndInfo ei = end_info(q, wq);
-            if (ei.lo || ei.hi) {
-#pragma unroll
-                for (int k = 0; k < KR; k++) x[k] = complete_end(v.m[k], v.s[k], rsl[k], roff[k], 0, ei);
-            } else {
-#pragma unroll
-                for (int k = 0; k < KR; k++) x[k] = complete(v.m[k], v.s[k], rsl[k]);
-            }
+        for (int k = 0; k < KR; k++) {
+            float x = v.m[k];
+            if (FOLD) x = add ? complete(x, v.s[k], rsl[k]) : x;
+            sRho[rs(q)][tid + 256 * k] = x;
         }
-#pragma unroll
-        for (int k = 0; k < KR; k++) sRho[rs(q)][tid + 256 * k] = x[k];
     };
     auto load_jg = [&](int wq, JgIn &v) {
         const Rsrc r = mcr(wq);
@@ -655,7 +607,10 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     unsigned long long n_fb = 0, n_eval = 0;
     // per-block constants: the input map x = 2 (v - lo) / (hi - lo) - 1 as
     // (v - lo) s - 1, the residual bound tol c_v, and 1 / c_v for the Newton step
-    const float s0 = 2.0f / (norm[1] - norm[0]), s1 = 2.0f / (norm[3] - norm[2]);
+    // (read once: the buffer stores of the march could alias them as far as
+    // the compiler knows, which would reload them every plane)
+    const float n0 = norm[0], n2 = norm[2], n4 = norm[4], n5 = norm[5];
+    const float s0 = 2.0f / (norm[1] - n0), s1 = 2.0f / (norm[3] - n2);
     const float tol_cv = tol * ph.cv;
     // acceptance words [z][y][x / 64], one per wavefront (a row of the block)
     const unsigned nxb = (unsigned)(nx + 63) / 64u, acc_bytes = (unsigned)ny * nxb * 8u;
@@ -670,7 +625,7 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
 #pragma unroll
         for (int q = 0; q < NRP; q++) load_rho(zw(q0 + q), v[q]);
 #pragma unroll
-        for (int q = 0; q < NRP; q++) put_rho(q0 + q, zw(q0 + q), v[q]);
+        for (int q = 0; q < NRP; q++) put_rho(q0 + q, v[q]);
     }
     if (D == 3) {
         load_rho(zw(z0 + 2), va);
@@ -678,9 +633,9 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     }
     load_jg(zw(z0), ja);
     if (D == 3) load_jg(zw(z0 + 1), jb);
-    // plane counters of the march: rho to put (z + 2) and to load (z + 4), j, G
-    // to load (z + 2), and the plane itself
-    int w_put = zw(z0 + 2), w_rho = zw(z0 + 4), w_jg = zw(z0 + 2), w_cur = zw(z0);
+    // plane counters of the march: rho to load (z + 4), j, G to load (z + 2),
+    // and the plane itself
+    int w_rho = zw(z0 + 4), w_jg = zw(z0 + 2), w_cur = zw(z0);
     __syncthreads();
     if (D == 3) make_lap(z0 - 1);
     make_lap(z0);
@@ -693,8 +648,7 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
         if (D == 3) {
             // rho of plane z + 2 into the slot of plane z - 2 (last read before
             // the previous plane's first barrier), the Laplacian of z + 1
-            put_rho(z + 2, w_put, vr);
-            w_put = inc(w_put);
+            put_rho(z + 2, vr);
             load_rho(w_rho, vr);  // also past the chunk (unused there): the loads' wait counts stay exact
             w_rho = inc(w_rho);
             __syncthreads();
@@ -705,14 +659,9 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
         // j, G of the cell (completed: FOLD)
         float j[4];
         if (FOLD) {
-            const EndInfo ei = end_info(z, w_cur);
-            if (ei.lo || ei.hi) {
+            const bool add = !is_end(z);
 #pragma unroll
-                for (int k = 0; k < 4; k++) j[k] = complete_end(jg.m[k], jg.s[k], osl, oc, k + 1, ei);
-            } else {
-#pragma unroll
-                for (int k = 0; k < 4; k++) j[k] = complete(jg.m[k], jg.s[k], osl);
-            }
+            for (int k = 0; k < 4; k++) j[k] = add ? complete(jg.m[k], jg.s[k], osl) : jg.m[k];
         } else {
 #pragma unroll
             for (int k = 0; k < 4; k++) j[k] = jg.m[k];
@@ -744,9 +693,9 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
         const float E = (j[3] + 0.5f * uF) * inv_rho;
         const float e = E - 0.5f * u2;
         float yh[1];
-        const float x0n = (r - norm[0]) * s0 - 1.0f, x1n = (e - norm[2]) * s1 - 1.0f;
+        const float x0n = (r - n0) * s0 - 1.0f, x1n = (e - n2) * s1 - 1.0f;
         mlp::forward_wave_l1mfma<1>(x0n, x1n, net, l1, yh);
-        float Th = yh[0] * norm[5] + norm[4];
+        float Th = yh[0] * n5 + n4;
         // relative residual |c_v T - a rho - e| / (c_v |T|) <= tol, without the
         // division; a NaN fails the test and takes the fallback
         const bool fb = !(fabsf(ph.cv * Th - ph.a * r - e) <= tol_cv * fabsf(Th));

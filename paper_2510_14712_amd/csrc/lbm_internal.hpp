@@ -44,7 +44,7 @@ struct lbm_ctx {
     // when it does the fix-up's work)
     int mcc = 0;
     bool mc_pending = false;
-    bool folded = false;  // the surrogate pass completes the side channel (no separate fix-up)
+    bool folded = false;  // the surrogate pass completes the side channel (the fix-up only its segment-end planes)
     size_t mc_bytes = 0, in_bytes = 0;
     int ntx = 0, nty = 0, nseg = 1, nlay = 0, chunk = 0;
 };
