@@ -334,22 +334,25 @@ def test_surrogate_pass_2d_walls_partial_tiles():
     assert errs["mlp"]["u"] <= 1.5 * errs["vdw"]["u"]
 
 
-@pytest.mark.parametrize("shape", [(65, 9, 10), (66, 10, 9)])
-def test_surrogate_form_with_and_without_the_folded_completion(shape):
+@pytest.mark.parametrize("shape,nseg", [((65, 9, 10), 0), ((66, 10, 9), 0), ((66, 10, 18), 3)])
+def test_surrogate_form_with_and_without_the_folded_completion(shape, nseg):
     """The surrogate pass completes the fused step's side channel itself
     (partial sums and inbound slots in, complete moments out) on tiles of at
     least 2 x 2 cells; a lattice with a one-cell-wide last tile column or row
     (65 x 9: 65 = 64 + 1, 9 = 2 * 4 + 1) takes the separate fix-up instead.
-    Both, with a zero-gradient x axis and z segments, against the FP64
-    oracle for 20 steps (FP32 storage, threshold 1e-6, so the exact fallback):
-    rho and T within 1e-5; u within 1e-4 (a lattice this size always has
+    Both, with a zero-gradient x axis, and the folded completion with three
+    z segments (whose end planes the end-plane fix-up completes before the
+    pass), against the FP64 oracle for 20 steps (FP32 storage, threshold
+    1e-6, so the exact fallback): rho and T within 1e-5; u within 1e-4 (a
+    lattice this size always has
     cells within FP32 rounding of the upwind switch's threshold, where the
     FP32 step may take the other branch)."""
     lbm = _lbm()
     params, norm, _ = _train(epochs=10)
     rho, u, T = inputs.random_state(3, shape, 36, ST["critical"]["rho"], 1.1 * ST["critical"]["T"])
-    _say(f"case surrogate D3Q27 {shape} bc x zero-gradient")
-    with lbm.Lattice(3, shape, bc=(1, 0, 0), storage="f32", eos="mlp", mlp_tol=1e-6, **KW) as lat:
+    _say(f"case surrogate D3Q27 {shape} bc x zero-gradient, z segments {nseg or 'default'}")
+    kw = dict(KW, zsegments=nseg) if nseg else KW
+    with lbm.Lattice(3, shape, bc=(1, 0, 0), storage="f32", eos="mlp", mlp_tol=1e-6, **kw) as lat:
         assert lat.fused
         lat.mlp_set(params, norm)
         lat.init(rho, u, T).step(20)
