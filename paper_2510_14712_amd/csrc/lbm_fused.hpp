@@ -533,12 +533,23 @@ __global__ void __launch_bounds__(256, 2) k_eos_surrogate(Grid g, Phys<float> ph
     };
     // bit i: plane z0 - 2 + i (i < 64; a chunk spans zchunk + 6 planes, the
     // host keeps zchunk <= 58) is a segment's first or last plane, whose
-    // moments the end-plane fix-up has completed; set up once per block
+    // moments the end-plane fix-up has completed; set up once per block from
+    // the segment boundaries (one division each; a window longer than nz
+    // holds a plane more than once)
     unsigned long long end_m = 0;
     if (D == 3 && FOLD) {
-        for (int i = 0; i < 64 && z0_blk - 2 + i < z1_blk + 4; i++) {
-            const int wq = zw(z0_blk - 2 + i), sg = seg_of(wq, nz, fa.nseg);
-            if (wq == seg_lo(sg, nz, fa.nseg) || wq == seg_lo(sg + 1, nz, fa.nseg) - 1) end_m |= 1ull << i;
+        const int q0 = z0_blk - 2, len = min(64, z1_blk + 4 - q0);
+        auto mark = [&](int e) {
+            int i = (e - q0) % nz;
+            if (i < 0) i += nz;
+            for (; i < len; i += nz) end_m |= 1ull << i;
+        };
+        int lo = 0;  // seg_lo(0)
+        for (int sg = 0; sg < fa.nseg; sg++) {
+            const int next = seg_lo(sg + 1, nz, fa.nseg);
+            mark(lo);
+            mark(next - 1);
+            lo = next;
         }
     }
     // plane q (unwrapped) is a segment-end plane
