@@ -560,25 +560,28 @@ def test_checkpoint_resume_bitwise_folding_instance(storage, nseg):
         assert bool((fa == fb).all()) and bool((ga == gb).all())
 
 
-@pytest.mark.parametrize("storage,nseg", [("bf16", 1), ("bf16", 3), ("f16", 2), ("f32", 4)])
-def test_checkpoint_resume_bitwise_surrogate_form(storage, nseg):
+@pytest.mark.parametrize("storage,nseg,nz", [("bf16", 1, 24), ("bf16", 3, 24), ("f16", 2, 24), ("f32", 4, 24),
+                                             ("bf16", 4, 120), ("f32", 3, 130)])
+def test_checkpoint_resume_bitwise_surrogate_form(storage, nseg, nz):
     """The surrogate form completes the side channel in its network pass: the
     previous fused step's partial sums plus inbound slots on ordinary planes,
     the segment-end planes completed before it by the end-plane fix-up.  A
     run restarted from its populations, whose moments the library recomputes
     complete (and whose first pass therefore completes nothing), continues
-    bit for bit like the uninterrupted one: 128 x 8 x 24 periodic, 1 to 4 z
-    segments, residual threshold 1e-2 so that the network's temperature is
-    taken (the exact inversion is taken where it fails)."""
+    bit for bit like the uninterrupted one: 128 x 8 x nz periodic, 1 to 4 z
+    segments; with nz = 120 and 130 the pass's chunks of 56 planes hold
+    segment ends inside them and at their edges.  Residual threshold 1e-2, so
+    that the network's temperature is taken (the exact inversion is taken
+    where it fails)."""
     lbm = _lbm()
-    shape = (128, 8, 24)
+    shape = (128, 8, nz)
     _assert_fast_instance(shape, (0, 0, 0), storage)
     rho, u, T = inputs.random_state(3, shape, 24, RHOC, 1.1 * TC)
     kw = dict(KW, zsegments=nseg, eos="mlp", mlp_tol=1e-2)
     if storage != "f32":
         kw.update(ref_rho=RHOC, ref_T=1.1 * TC)
     net = _surrogate(lbm)
-    _say(f"case resume surrogate form {storage} nseg {nseg}")
+    _say(f"case resume surrogate form {storage} nseg {nseg} nz {nz}")
     with lbm.Lattice(3, shape, storage=storage, **kw) as a, lbm.Lattice(3, shape, storage=storage, **kw) as b:
         assert a.fused
         a.mlp_set(*net)
