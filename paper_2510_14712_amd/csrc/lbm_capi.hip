@@ -666,11 +666,16 @@ template <int D, class S> struct Impl {
         } else {
             // segments of at least 16 planes; the count minimises the
             // workgroup rounds times the planes per segment (no half-empty
-            // last round), and among equal costs reaches 1024 workgroups for
-            // load balance.  Resident workgroups: compute units x the fused
-            // kernel's occupancy (the instance the step launches); if the
-            // device cannot be queried, the first count giving 1024
-            // workgroups.
+            // last round).  Among equal costs: segments of at least 64
+            // planes where there are such (the prologue, about 8 planes of
+            // loads, stays small), the first count giving 8 workgroups per
+            // resident slot, else the longest of them -- a march of one or
+            // two rounds ends on its slowest workgroups (512^3, 16-bit: one
+            // segment, two rounds, 9.6 ms; four segments 9.0 ms); without
+            // such segments the first count reaching 1024 workgroups.
+            // Resident workgroups: compute units x the fused kernel's
+            // occupancy (the instance the step launches); if the device
+            // cannot be queried, the first count giving 1024 workgroups.
             const int smax = std::max(1, c->p.nz / 16);
             int dev = 0, ncu = 0, nb = 0;
             const bool known =
@@ -685,13 +690,21 @@ template <int D, class S> struct Impl {
                 c->nseg = std::max(1, std::min((int)((1024 + ntiles - 1) / ntiles), smax));
             } else {
                 const long long res = (long long)ncu * nb;
+                const int nz = c->p.nz;
+                auto cost = [&](int s) { return ((ntiles * s + res - 1) / res) * ((nz + s - 1) / s); };
                 long long best_cost = -1;
-                int best = 1;
-                for (int s = 1; s <= smax; s++) {
-                    const long long cost = ((ntiles * s + res - 1) / res) * ((c->p.nz + s - 1) / s);
-                    if (best_cost < 0 || cost < best_cost || (cost == best_cost && ntiles * best < 1024)) {
-                        best_cost = cost;
+                for (int s = 1; s <= smax; s++) best_cost = best_cost < 0 ? cost(s) : std::min(best_cost, cost(s));
+                int best = -1;
+                for (int s = 1; s <= smax && nz / s >= 64; s++) {
+                    if (cost(s) != best_cost) continue;
+                    best = s;
+                    if (ntiles * s >= 8 * res) break;
+                }
+                if (best < 0) {
+                    for (int s = 1; s <= smax; s++) {
+                        if (cost(s) != best_cost) continue;
                         best = s;
+                        if (ntiles * s >= 1024) break;
                     }
                 }
                 c->nseg = best;
