@@ -417,13 +417,17 @@ template <int D, class S> struct Impl {
     static void fused_eos(lbm_ctx *c) {
         if constexpr (std::is_same<C, float>::value) {
             if (!mlp(c)) return;
-            // 64 x 4 columns per workgroup, marching through chunks of 56 planes
-            // (longer chunks spread the prologue -- rho region of four planes,
-            // two Laplacians, the permuted weights -- over more planes: 32 ->
-            // 56 took the pass 2.98 -> 2.88 ms at 512^3; the end-plane bitmask of
-            // the completing pass spans a chunk plus 6 planes, at most 64)
-            const int zchunk = D == 3 ? 56 : 1;
-            static_assert(56 + 6 <= 64, "end-plane bitmask of the surrogate pass");
+            // 64 x 4 columns per workgroup, marching through the fewest chunks
+            // of at most 58 planes, as even as nz allows (longer chunks spread
+            // the prologue -- rho region of four planes, two Laplacians, the
+            // permuted weights -- over more planes: at 512^3, 32 -> 56 took the
+            // pass 2.98 -> 2.88 ms, nine chunks of 57 and 56 instead of nine of
+            // 56 and one of 8 2.39 -> 2.36 ms; the end-plane bitmask of the
+            // completing pass spans a chunk plus 6 planes, at most 64)
+            constexpr int ZCHUNK_MAX = 58;
+            static_assert(ZCHUNK_MAX + 6 <= 64, "end-plane bitmask of the surrogate pass");
+            const int nchunk = D == 3 ? (c->p.nz + ZCHUNK_MAX - 1) / ZCHUNK_MAX : 1;
+            const int zchunk = D == 3 ? (c->p.nz + nchunk - 1) / nchunk : 1;
             const dim3 grid((unsigned)((c->p.nx + 63) / 64), (unsigned)((c->p.ny + 3) / 4),
                             (unsigned)((c->p.nz + zchunk - 1) / zchunk));
             FoldArgs fa{nullptr, nullptr, c->ntx, c->nty, c->nseg};
