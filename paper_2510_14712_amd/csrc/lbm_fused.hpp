@@ -1332,22 +1332,26 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         //    plane z+1 ------------------------------------------------------------
         C rv[NR3], jon[NJ], jrn[NJ];
         CenterF<C> Zp;
+        __builtin_amdgcn_s_setprio(2);  // raised outside the collision (see phase B)
         if (D == 3) {
-            // a wavefront issuing its loads takes precedence over the other
-            // wavefront of its SIMD (two per SIMD in the 16-bit forms), so
-            // that they are in flight before its next stretch of arithmetic
-            // (BF16 + surrogate at 512^3: 9.24-9.33 -> 9.09-9.12 ms)
-            __builtin_amdgcn_s_setprio(2);
             load_rho_regs(z + 5, rv, rvs);
             load_jg(z + 2, jon, jrn, wo, wr);
             load_acc(z + 3, wo, wr);
-            __builtin_amdgcn_s_setprio(0);
             make_lap(z + 3);
             make_fields(z + 1, jo, jr, Zp);
             __syncthreads();
         }
 
         // -- phase B: collide the own cell of plane z ---------------------------
+        // Wavefront priority: the collision, a long stretch of arithmetic
+        // with no memory access or barrier, runs at the base priority; the
+        // rest of the iteration (loads, LDS stencils and exchange, the two
+        // barriers) at a raised one.  Two workgroups share a compute unit in
+        // the 16-bit forms, so a wavefront in its load and barrier phases
+        // takes precedence over the other workgroup's collision, which fills
+        // the gaps (BF16 + surrogate at 512^3: k_fused 9.16 -> 8.64 ms; loads
+        // alone raised 9.10, phase A 8.91)
+        __builtin_amdgcn_s_setprio(0);
         {
             const C *rf = &sRing[s2(z)][0][0];
             CollideIn<C> in;
@@ -1393,6 +1397,7 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
                 jr[k] = jrn[k];
             }
         }
+        __builtin_amdgcn_s_setprio(2);
         // -- store the post-collision set at the cell itself (the next step
         //    streams it on the way in); the moment sums of the next step use
         //    the stored values (as deviations) --------------------------------
@@ -1424,10 +1429,8 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
         };
         xwrite(f, 0);
         xwrite(gq, GROW);
-        __builtin_amdgcn_s_setprio(2);  // as for the loads above
         if (D == 3 && z + 1 < z1) load_pops(z + 1);
         if (D == 3) load_jg_slots(z + 2, jos, jrs);  // FOLD (live across the gather, not the collision)
-        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         rounds(WFG{});
         if (D == 3) {
