@@ -1338,19 +1338,22 @@ __global__ void __launch_bounds__(TL::NT, (fused_occupancy<S, MLP>())) k_fused(F
             load_jg(z + 2, jon, jrn, wo, wr);
             load_acc(z + 3, wo, wr);
             make_lap(z + 3);
+            __builtin_amdgcn_s_setprio(0);  // arithmetic, as the collision (see phase B)
             make_fields(z + 1, jo, jr, Zp);
+            __builtin_amdgcn_s_setprio(2);
             __syncthreads();
         }
 
         // -- phase B: collide the own cell of plane z ---------------------------
-        // Wavefront priority: the collision, a long stretch of arithmetic
-        // with no memory access or barrier, runs at the base priority; the
-        // rest of the iteration (loads, LDS stencils and exchange, the two
-        // barriers) at a raised one.  Two workgroups share a compute unit in
-        // the 16-bit forms, so a wavefront in its load and barrier phases
-        // takes precedence over the other workgroup's collision, which fills
-        // the gaps (BF16 + surrogate at 512^3: k_fused 9.16 -> 8.64 ms; loads
-        // alone raised 9.10, phase A 8.91)
+        // Wavefront priority: the collision and the fields of the next plane,
+        // long stretches of arithmetic with no memory access or barrier, run
+        // at the base priority; the rest of the iteration (loads, LDS
+        // stencils and exchange, the two barriers) at a raised one.  Two
+        // workgroups share a compute unit in the 16-bit forms, so a wavefront
+        // in its load and barrier phases takes precedence over the other
+        // workgroup's arithmetic, which fills the gaps (BF16 + surrogate at
+        // 512^3: k_fused 9.16 -> 8.55 ms; loads alone raised 9.10, phase A
+        // 8.91, all but the collision 8.60)
         __builtin_amdgcn_s_setprio(0);
         {
             const C *rf = &sRing[s2(z)][0][0];
